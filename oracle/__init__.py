@@ -1,0 +1,25 @@
+"""Plain, slow CPU FP64 oracle for the PDEP chi0 path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or runs this
+package; only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
+It shares no code with the HIP library.
+
+What it computes follows the paper's own definitions (Hartree units, e^2 = 1, Gamma
+point, doubly occupied bands):
+
+* plane-wave basis: all G with 1/2 |G|^2 <= E_cut (Sec. 2.1, plane-wave expansion);
+* Kohn-Sham model Hamiltonian H = T + V_loc (Sec. 2, KS equation; local potential only);
+* Sternheimer equation (H - e_v) P_c dpsi = -P_c dV psi_v (Sec. 2.3, Eq. stern);
+* density response dn = sum over spin and bands of [dpsi* psi + c.c.] (Eq. deltani);
+* chi0bar_ij = 4 pi <phi~_i | dn_j> with phi~ = phi/|G| (Eq. chiisamatrixinpdep,
+  symmetrised form of Eq. symmoperator);
+* sum-over-states (Adler-Wiser at omega = 0, q = 0 body, Eq. AdlerWiser) as a second,
+  independent route to the same response;
+* PDEP eigenpairs = lowest eigenpairs of chi0bar (Eq. eigendecompzerofreq).
+
+Modules:
+  planewave  -- sphere, grid, naive DFT, dense H
+  response   -- ground state, direct and sum-over-states Sternheimer, dn, chi0bar, PDEP
+  matfree    -- matrix-free FFT + CG version of the same chain (used for CPU timing and
+                sampled checks at sizes where dense matrices do not fit)
+"""

@@ -1,0 +1,334 @@
+"""Pins of the CPU FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what it pins.  Together they are chosen so that a plausible mistake in
+the oracle (a dropped factor, a wrong sign, a conjugate on the wrong side, a transposed
+transform, a wrong Coulomb scaling, a wrong projector) fails at least one of them; the
+mutation tests at the end plant such mistakes and check that they are caught.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import matfree as MF
+from oracle import planewave as pw
+from oracle import response as R
+from paper_1501_03141_amd import inputs
+
+TINY = inputs.WORKLOADS["tiny"]
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    V = inputs.vloc(TINY)
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, V)
+    gs = R.ground_state(m, TINY.n_v, full=True)
+    return m, gs
+
+
+@pytest.fixture(scope="module")
+def tiny_pdep(tiny):
+    m, gs = tiny
+    lam, Phi, M = R.pdep_exact(m, gs, TINY.n_pdep)
+    return lam, Phi, M
+
+
+# --- basis ------------------------------------------------------------------------------
+
+def test_sphere_brute_force_membership_and_order():
+    """S is exactly the set of integer triples with 1/2|2 pi m/L|^2 <= ecut, in
+    lexicographic order, closed under G -> -G (cutoff of Sec. 2.1)."""
+    for w in inputs.WORKLOADS.values():
+        m = pw.sphere(w.L, w.ecut)
+        # brute force over a generous box
+        box = [int(math.sqrt(2 * w.ecut) * w.L[d] / (2 * math.pi)) + 3 for d in range(3)]
+        ref = []
+        for a in range(-box[0], box[0] + 1):
+            for b in range(-box[1], box[1] + 1):
+                for c in range(-box[2], box[2] + 1):
+                    g2 = (2 * math.pi) ** 2 * ((a / w.L[0]) ** 2 + (b / w.L[1]) ** 2 + (c / w.L[2]) ** 2)
+                    if 0.5 * g2 <= w.ecut:
+                        ref.append((a, b, c))
+        assert [tuple(r) for r in m.tolist()] == ref
+        s = {tuple(r) for r in m.tolist()}
+        assert all((-a, -b, -c) in s for (a, b, c) in s)
+        # the sphere fits the grid without wrap-around collisions
+        assert len(set(pw.grid_index(w.n, m).tolist())) == m.shape[0]
+
+
+def test_sphere_sizes():
+    """Full complex sphere sizes of the four workloads (enumerated by hand above)."""
+    sizes = [pw.sphere(w.L, w.ecut).shape[0] for w in inputs.WORKLOADS.values()]
+    assert sizes == [515, 5041, 15895, 31791]
+
+
+def test_fft_route_equals_naive_dft(tiny):
+    m, gs = tiny
+    rng = np.random.default_rng(0)
+    c = rng.standard_normal((3, m.n_pw)) + 1j * rng.standard_normal((3, m.n_pw))
+    a = pw.inv_naive(m.E, c.T).T
+    b = pw.inv_fft(m.n, m.idx, c).reshape(3, -1)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+    f = rng.standard_normal((3, m.n_grid)) + 1j * rng.standard_normal((3, m.n_grid))
+    a = pw.fwd_naive(m.E, f.T).T
+    b = pw.fwd_fft(m.n, m.idx, f.reshape((3,) + m.n))
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+    H1 = pw.hamiltonian_naive(m.E, m.kin, m.vloc.ravel())
+    H2 = pw.hamiltonian_fft(m.n, m.miller, m.kin, m.vloc)
+    assert np.max(np.abs(H1 - H2)) <= 1e-13
+
+
+def test_single_plane_wave_transform():
+    """Inv of a unit coefficient at G is exp(i G.r) sampled on the grid (closed form)."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    k = 37
+    c = np.zeros(m.n_pw, complex)
+    c[k] = 1.0
+    f = m.inv(c).reshape(TINY.n)
+    G = pw.gvectors(TINY.L, m.miller[k:k + 1])[0]
+    x = [np.arange(TINY.n[d]) * TINY.L[d] / TINY.n[d] for d in range(3)]
+    X, Y, Z = np.meshgrid(*x, indexing="ij")
+    ref = np.exp(1j * (G[0] * X + G[1] * Y + G[2] * Z))
+    assert np.max(np.abs(f - ref)) < 1e-12
+    back = m.fwd(f.ravel())
+    e = np.zeros(m.n_pw)
+    e[k] = 1
+    assert np.max(np.abs(back - e)) < 1e-14
+
+
+# --- Hamiltonian and ground state --------------------------------------------------------
+
+def test_free_hamiltonian_spectrum():
+    """V = 0: the eigenvalues are exactly 1/2|G|^2."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    H = R.hamiltonian(m)
+    w = np.linalg.eigvalsh(H)
+    assert np.max(np.abs(w - np.sort(m.kin))) < 1e-13
+
+
+def test_constant_shift(tiny):
+    """V -> V + c shifts every eigenvalue by c and leaves chi0bar unchanged."""
+    m, gs = tiny
+    c = 0.37
+    m2 = R.make_model(TINY.L, TINY.n, TINY.ecut, m.vloc + c)
+    gs2 = R.ground_state(m2, TINY.n_v, full=True)
+    assert np.max(np.abs(gs2.eps - gs.eps - c)) < 1e-12
+    phi = inputs.trial_block(m.miller[m.nz], 2, 11)
+    a = R.chi0bar_apply(m, gs, phi)
+    b = R.chi0bar_apply(m2, gs2, phi)
+    assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
+
+
+def test_hamiltonian_hermitian(tiny):
+    m, gs = tiny
+    assert np.max(np.abs(gs.H - gs.H.conj().T)) < 1e-15
+
+
+def test_gap_positive(tiny):
+    m, gs = tiny
+    assert gs.gap > 1e-3
+
+
+# --- Sternheimer and density response ----------------------------------------------------
+
+def test_sum_over_states_equals_direct_solve(tiny):
+    """Adler-Wiser at omega = 0 (sum over empty states) equals the Sternheimer solve."""
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 3, 5)
+    a = R.chi0bar_apply(m, gs, phi, method="direct")
+    b = R.chi0bar_apply(m, gs, phi, method="sos")
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def _density(model, n_v):
+    gs = R.ground_state(model, n_v, full=False)
+    return (2.0 / model.volume) * np.sum(np.abs(gs.U) ** 2, axis=0)
+
+
+def test_finite_difference_density_response(tiny):
+    """dn from Sternheimer equals the central difference of the ground-state density
+    n = (2/Omega) sum_v |u_v|^2 under V -> V +- h dV (pins the factor 4, the sign, the
+    conjugation and the projector without using any response formula)."""
+    m, gs = tiny
+    rng = np.random.default_rng(3)
+    phi = inputs.trial_block(m.miller[m.nz], 1, 9)
+    dV = R.perturbation_grid(m, phi)[0]
+    dV = dV / np.max(np.abs(dV))
+    h = 1e-5
+    mp = R.make_model(TINY.L, TINY.n, TINY.ecut, m.vloc + h * dV.reshape(TINY.n))
+    mm = R.make_model(TINY.L, TINY.n, TINY.ecut, m.vloc - h * dV.reshape(TINY.n))
+    fd = (_density(mp, TINY.n_v) - _density(mm, TINY.n_v)) / (2 * h)
+    dn = R.chi0_real(m, gs, dV)
+    assert np.max(np.abs(fd - dn)) <= 1e-6 * np.max(np.abs(dn))
+    assert np.max(np.abs(dn)) > 1e-3
+
+
+def test_zero_response_to_uniform_potential(tiny):
+    """A constant dV gives b = -P_c (c u_v) = 0, hence dn = 0."""
+    m, gs = tiny
+    dn = R.chi0_real(m, gs, np.full(m.n_grid, 0.8))
+    assert np.max(np.abs(dn)) < 1e-13
+
+
+def test_particle_conservation(tiny):
+    """dn integrates to zero: the response keeps the electron count (dc_v is orthogonal
+    to every occupied band)."""
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 1, 4)
+    dn = R.chi0_real(m, gs, R.perturbation_grid(m, phi)[0])
+    assert abs(np.sum(dn)) <= 1e-13 * np.sum(np.abs(dn))
+
+
+def test_band_phase_invariance(tiny):
+    """chi0bar does not depend on the phase of each occupied orbital."""
+    m, gs = tiny
+    ph = np.exp(1j * np.array([0.3, 1.9, -2.2, 0.7]))
+    gs2 = R.GroundState(gs.eps, gs.C * ph[:, None], gs.U * ph[:, None], gs.gap, gs.eps_all, None, gs.H)
+    phi = inputs.trial_block(m.miller[m.nz], 2, 6)
+    a = R.chi0bar_apply(m, gs, phi)
+    b = R.chi0bar_apply(m, gs2, phi)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_linearity(tiny):
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 2, 8)
+    a = R.chi0bar_apply(m, gs, phi)
+    s = R.chi0bar_apply(m, gs, 2.0 * phi[0:1] - 3.0 * phi[1:2])
+    assert np.max(np.abs(s[0] - (2 * a[0] - 3 * a[1]))) <= 1e-12 * np.max(np.abs(a))
+
+
+# --- chi0bar and PDEP ---------------------------------------------------------------------
+
+def test_free_electron_closed_form():
+    """V = 0, one occupied state (G = 0): chi0bar is diagonal with
+    lambda_G = -32 pi / (Omega |G|^4) (Hartree units, two spins)."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    gs = R.ground_state(m, 1, full=True)
+    M, Bm = R.chi0bar_matrix(m, gs)
+    G2 = 2 * m.kin[m.nz]
+    # every real basis vector is built from one +-G pair, so M must be diagonal
+    assert np.max(np.abs(M - np.diag(np.diag(M)))) < 1e-13
+    Omega = TINY.L[0] * TINY.L[1] * TINY.L[2]
+    closed = np.sort(-32 * math.pi / (Omega * G2 ** 2))
+    assert np.max(np.abs(np.sort(np.diag(M)) - closed)) < 1e-13
+    # most screened shell: 6-fold, -2L/pi^3 for a cube of edge L
+    assert abs(closed[0] - (-2 * TINY.L[0] / math.pi ** 3)) < 1e-13
+    assert abs(closed[5] - closed[0]) < 1e-15 and closed[6] > closed[5] + 0.1
+
+
+def test_chi0bar_hermitian_negative(tiny, tiny_pdep):
+    """chi0bar is Hermitian (real symmetric in the real basis) and negative
+    semidefinite, so every eps = 1 - lambda >= 1."""
+    m, gs = tiny
+    M, Bm = R.chi0bar_matrix(m, gs)
+    assert np.max(np.abs(M - M.T)) <= 1e-13 * np.max(np.abs(M))
+    w = np.linalg.eigvalsh(0.5 * (M + M.T))
+    assert w.max() <= 1e-12
+    lam = tiny_pdep[0]
+    assert np.all(1.0 - lam >= 1.0)
+
+
+def test_translation_invariance(tiny, tiny_pdep):
+    """Moving every well by a whole grid vector (a cyclic roll of V) leaves the
+    spectrum of chi0bar unchanged."""
+    m, gs = tiny
+    V2 = np.roll(m.vloc, shift=(3, -5, 7), axis=(0, 1, 2))
+    m2 = R.make_model(TINY.L, TINY.n, TINY.ecut, V2)
+    gs2 = R.ground_state(m2, TINY.n_v, full=True)
+    lam2, _, _ = R.pdep_exact(m2, gs2, TINY.n_pdep)
+    assert np.max(np.abs(lam2 - tiny_pdep[0])) < 1e-11
+
+
+def test_pdep_eigenpairs(tiny, tiny_pdep):
+    """The exact PDEP vectors are Hermitian-symmetric eigenvectors of chi0bar."""
+    m, gs = tiny
+    lam, Phi, _ = tiny_pdep
+    A = R.chi0bar_apply(m, gs, Phi)
+    res = np.linalg.norm(A - lam[:, None] * Phi, axis=1)
+    assert res.max() < 1e-11
+    assert np.allclose(Phi.conj() @ Phi.T, np.eye(len(lam)), atol=1e-12)
+
+
+def test_rayleigh_ritz_interlacing(tiny, tiny_pdep):
+    """Ritz values of any subspace are bounded below by the exact eigenvalues
+    (Courant-Fischer); a random block gives a strict bound."""
+    m, gs = tiny
+    X = inputs.trial_block(m.miller[m.nz], TINY.n_pdep, 1)
+    theta = R.rayleigh_ritz(m, gs, X)
+    assert np.all(theta >= tiny_pdep[0] - 1e-12)
+
+
+def test_subspace_iteration_reaches_exact(tiny, tiny_pdep):
+    """Independent route: power/subspace iteration from a random block converges to the
+    exact lowest eigenvalues (a block larger than N_pdep is carried)."""
+    m, gs = tiny
+    X = inputs.trial_block(m.miller[m.nz], 16, 2)
+    lam, it = R.subspace_iteration(m, gs, X, n_iter=200, tol=1e-13)
+    assert np.max(np.abs(lam[:4] - tiny_pdep[0][:4])) < 1e-8
+
+
+def test_matrix_free_equals_dense(tiny):
+    """FFT + preconditioned CG reaches the dense result."""
+    m, gs = tiny
+    mf = R.make_model(TINY.L, TINY.n, TINY.ecut, m.vloc, naive=False)
+    phi = inputs.trial_block(m.miller[m.nz], 2, 12)
+    a = R.chi0bar_apply(m, gs, phi)
+    for pre in (True, False):
+        b, it = MF.chi0bar_apply_cg(mf, gs, phi, 1e-13, precondition=pre)
+        assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
+
+
+# --- mutation tests: planted mistakes must be caught -------------------------------------
+
+def _free_electron_lambda(model, gs):
+    M, _ = R.chi0bar_matrix(model, gs)
+    return np.sort(np.diag(M))
+
+
+def test_mutation_density_factor_caught(monkeypatch):
+    """Dropping the spin factor (4 -> 2) breaks the free-electron closed form."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    gs = R.ground_state(m, 1, full=True)
+    good = _free_electron_lambda(m, gs)
+    real_apply = R.chi0bar_apply
+
+    def bad(model, gs_, phi, method="direct"):
+        return 0.5 * real_apply(model, gs_, phi, method)
+    monkeypatch.setattr(R, "chi0bar_apply", bad)
+    wrong = _free_electron_lambda(m, gs)
+    G2 = 2 * m.kin[m.nz]
+    closed = np.sort(-32 * math.pi / (m.volume * G2 ** 2))
+    assert np.max(np.abs(good - closed)) < 1e-13
+    assert np.max(np.abs(wrong - closed)) > 1e-3
+
+
+def test_mutation_conjugation_caught(tiny):
+    """Using u_v instead of conj(u_v) in the density breaks the finite-difference pin
+    (the orbitals here carry non-trivial phases)."""
+    m, gs = tiny
+    ph = np.exp(1j * np.array([0.3, 1.9, -2.2, 0.7]))
+    gsp = R.GroundState(gs.eps, gs.C * ph[:, None], gs.U * ph[:, None], gs.gap, gs.eps_all, None, gs.H)
+    phi = inputs.trial_block(m.miller[m.nz], 1, 9)
+    dV = R.perturbation_grid(m, phi)[0]
+    dC = R.solve_direct(m, gsp, R.rhs(m, gsp, dV))
+    good = R.density_response(m, gsp, dC)
+    bad = (4.0 / m.volume) * np.real(np.sum(gsp.U * m.inv(dC), axis=0))
+    assert np.max(np.abs(good - bad)) > 1e-2 * np.max(np.abs(good))
+    assert np.max(np.abs(good - R.chi0_real(m, gs, dV))) <= 1e-11 * np.max(np.abs(good))
+
+
+def test_mutation_missing_projector_caught(tiny):
+    """Solving without P_c (plain (H - e_v) x = -Fwd(dV u_v)) is singular or wrong; the
+    sum-over-states pin catches the difference."""
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 1, 13)
+    dV = R.perturbation_grid(m, phi)[0]
+    w = m.fwd(dV[None, :] * gs.U)
+    sigma_free = []
+    for v in range(TINY.n_v):
+        A = gs.H - (gs.eps[v] - 1e-3) * np.eye(m.n_pw)
+        sigma_free.append(np.linalg.solve(A, -w[v]))
+    bad = R.density_response(m, gs, np.array(sigma_free))
+    good = R.chi0_real(m, gs, dV, method="sos")
+    assert np.max(np.abs(bad - good)) > 1e-2 * np.max(np.abs(good))
