@@ -1,0 +1,207 @@
+/*
+ * pdep.h -- C ABI of the MI355X PDEP chi0 library (libpdep.so).
+ *
+ * The library applies the static independent-particle response chi0bar of a
+ * Kohn-Sham system to blocks of trial potentials through density-functional
+ * perturbation theory, and finds the PDEP eigenpairs of chi0bar by block Davidson
+ * (Govoni & Galli, "Large scale GW calculations", Sec. 2.3: the Sternheimer equation
+ * Eq. stern, the density response Eq. deltani and the projected polarizability
+ * Eq. chiisamatrixinpdep; the spectral form of Eq. eigendecompzerofreq).
+ *
+ * Model and conventions (all calls):
+ *  - Hartree atomic units, e^2 = 1.  The paper writes Rydberg units; dielectric
+ *    eigenvalues are dimensionless and do not depend on the choice.
+ *  - Orthorhombic cell with edges L[3] (bohr), FFT grid n[3], volume Omega.
+ *    Grid points r = (ix Lx/nx, iy Ly/ny, iz Lz/nz); real-space arrays are C order
+ *    (ix slowest, iz fastest), length N_g = nx*ny*nz.
+ *  - Wavefunction basis S: all G = 2 pi (mx/Lx, my/Ly, mz/Lz) with
+ *    1/2 |G|^2 <= ecut (the plane-wave expansion and cutoff of Sec. 2.1), listed
+ *    lexicographically in (mx, my, mz), mz fastest.  N_pw = |S|.
+ *    S' = S without G = 0 (N_pw' = N_pw - 1) is the space of the PDEP potentials.
+ *  - Transforms: Inv(c)(r) = sum_{G in S} c_G exp(iG.r);
+ *                Fwd(f)(G) = N_g^-1 sum_r f(r) exp(-iG.r).
+ *  - Hamiltonian: H = 1/2|G|^2 + Fwd(V_loc * Inv(.)) restricted to S (a local
+ *    potential only; products alias on the grid exactly as the transforms make them).
+ *  - Occupied orbitals: the N_v lowest eigenvectors c_v of H, normalised to
+ *    sum_G |c_vG|^2 = 1, doubly occupied (two spins, Gamma point only).
+ *  - chi0bar phi for phi on S' (Hermitian-symmetric: phi(-G) = conj phi(G), so the
+ *    potential is real in r):  phi~ = sqrt(4 pi)/|G| phi, dV = Re Inv(phi~),
+ *    solve P_c (H - e_v) P_c dc_v = -P_c Fwd(dV u_v) for every v (u_v = Inv(c_v)),
+ *    dn = (4/Omega) Re sum_v conj(u_v) Inv(dc_v), result sqrt(4 pi)/|G| Fwd(dn) on S'.
+ *  - Complex arrays are interleaved (re, im) doubles, row-major; "a x b complex"
+ *    means 2*a*b doubles.
+ *
+ * Memory and ownership: inputs are read during the call and stay owned by the
+ * caller; outputs are written into caller-allocated buffers.  By default every
+ * array argument is host memory; with PDEP_DEVICE_PTRS in pdep_opts.flags the
+ * array arguments of chi0_apply / chi0_apply_raw / pdep_eigs are device memory
+ * on the context's device instead.  The context owns all device-resident state
+ * (tables, potential, orbitals, u_v grids, solver work space), allocated through
+ * pdep_opts.alloc when given, else hipMalloc.  All device work is queued on
+ * pdep_opts.stream (NULL: the default stream); calls return after it finished.
+ *
+ * Errors: every call returns a pdep_status; on error pdep_last_error() gives a
+ * message for the calling thread.  PDEP_ENOTCONV still fills outputs and stats.
+ * A context must not be used by two threads at once.
+ */
+#ifndef PDEP_H
+#define PDEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PDEP_OK = 0,
+    PDEP_EINVAL = -1,     /* bad argument (sizes, NaN/Inf in inputs, bad options) */
+    PDEP_ENOMEM = -2,     /* device allocation failed or the HBM budget is exceeded */
+    PDEP_ENOTCONV = -3,   /* an iterative solver hit its iteration cap */
+    PDEP_EGAP = -4,       /* HOMO-LUMO gap below opts.gap_min: chi0 is undefined */
+    PDEP_EDEVICE = -5,    /* HIP runtime or device library error */
+    PDEP_EBUSY = -6,      /* server queue full */
+    PDEP_ENOTFOUND = -7   /* unknown ticket */
+} pdep_status;
+
+typedef enum {
+    PDEP_FP64 = 0,        /* every step in FP64 */
+    PDEP_MIXED_FP32 = 1   /* FP32 inner CG (transforms, H, P_c) with FP64 residual
+                             refinement; FP64 right-hand sides, density, projection */
+} pdep_precision;
+
+#define PDEP_DEVICE_PTRS 1u
+
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} pdep_allocator;
+
+typedef struct {
+    double L[3];          /* cell edges (bohr), each > 0 */
+    int n[3];             /* FFT grid, each a product of 2s and 3s, 4 <= n <= 128 */
+    double ecut;          /* wavefunction cutoff (Ha); the sphere must fit the grid */
+} pdep_cell;
+
+typedef struct {
+    int n_v;              /* number of doubly occupied bands, >= 1 */
+    int precision;        /* pdep_precision */
+    double cg_tol;        /* Sternheimer stop: ||P_c(b - A x)|| <= cg_tol ||b|| (FP64 residual) */
+    int cg_maxit;         /* iteration cap of each CG solve */
+    double inner_tol;     /* mixed: relative reduction asked of each FP32 inner solve */
+    int refine_maxit;     /* mixed: cap on FP64 refinement steps */
+    int precond;          /* 1: diagonal kinetic preconditioner 1/max(1, 1/2|G|^2 - e_v), 0: none */
+    double gap_min;       /* setup fails with PDEP_EGAP below this HOMO-LUMO gap (Ha) */
+    double gs_tol;        /* ground state: residual norm target ||H c - e c|| */
+    int gs_maxit;         /* ground state: Davidson iteration cap */
+    size_t hbm_budget;    /* bytes of solver work space per call; 0 = size to the problem */
+    int rhs_tile;         /* Sternheimer systems per batched CG tile; 0 = automatic */
+    void* stream;         /* hipStream_t; NULL = default stream */
+    pdep_allocator alloc; /* device allocator; alloc == NULL: hipMalloc / hipFree */
+    uint32_t flags;       /* PDEP_DEVICE_PTRS */
+} pdep_opts;
+
+/* Fill *o with defaults: FP64, cg_tol 1e-10, cg_maxit 2000, inner_tol 1e-5,
+ * refine_maxit 8, precond 1, gap_min 1e-3, gs_tol 1e-10, gs_maxit 400, no budget,
+ * automatic tiles, default stream, hipMalloc, host pointers. */
+void pdep_default_opts(pdep_opts* o);
+
+typedef struct {
+    int n_pw;             /* |S| */
+    int n_v;
+    int n_grid;
+    double gap;           /* e_{N_v+1} - e_{N_v} (Ha); 0 when orbitals were supplied */
+    double volume;
+    int gs_iterations;    /* ground-state Davidson iterations (0 if supplied) */
+    double gs_residual;   /* max_v ||H c_v - e_v c_v|| of the orbitals in use */
+} pdep_info;
+
+typedef struct {
+    int n_rhs;                    /* Sternheimer systems solved (n_pert * n_v) */
+    int cg_iter_max;              /* largest CG iteration count of any system (sum over refinement steps) */
+    long long cg_iter_total;      /* sum of CG iterations over systems */
+    long long op_applications;    /* batched operator applications (launch count of the CG operator) */
+    int refine_steps;             /* FP64 refinement steps taken (mixed) */
+    int n_notconv;                /* systems that missed cg_tol */
+    double max_rel_residual;      /* max over systems of the final FP64 relative residual */
+    double ms;                    /* wall time of the call on the device stream */
+} pdep_apply_stats;
+
+typedef struct {
+    double tol;           /* converged when every wanted residual ||chi0bar x - l x|| <= tol */
+    int maxit;            /* Davidson iteration cap */
+    int max_subspace;     /* restart size (columns); 0 = 4 * n_pdep */
+    int n_buffer;         /* extra unreported vectors carried for faster convergence */
+} pdep_eig_opts;
+
+typedef struct {
+    int iterations;
+    int chi0_columns;             /* chi0bar applications performed */
+    double max_residual;          /* of the reported pairs */
+    long long cg_iter_total;
+    double ms;
+} pdep_eig_stats;
+
+typedef struct pdep_ctx pdep_ctx;
+
+/* Build the basis tables, upload V_loc and obtain the occupied orbitals.
+ * vloc: N_g doubles (host), real potential in Ha.  psi_in: NULL, or N_v x N_pw
+ * complex (host) orthonormal occupied coefficients in S order with eps_in their
+ * N_v energies; when NULL the library finds the N_v lowest eigenpairs of H with an
+ * FP64 block Davidson to opts.gs_tol and checks the gap (PDEP_EGAP below
+ * opts.gap_min).  *out receives the new context (NULL on error). */
+int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
+               const double* psi_in, const double* eps_in, pdep_ctx** out);
+
+int pdep_get_info(pdep_ctx* ctx, pdep_info* info);
+
+/* Miller indices of S, 3 * N_pw int32 (host), lexicographic (mx, my, mz). */
+int pdep_get_gvectors(pdep_ctx* ctx, int32_t* miller);
+
+/* Occupied energies (N_v doubles) and coefficients (N_v x N_pw complex), host.
+ * Either pointer may be NULL. */
+int pdep_get_orbitals(pdep_ctx* ctx, double* eps, double* psi);
+
+/* chi0bar applied to n_pert potentials (Eq. chiisamatrixinpdep with V_pert = phi~):
+ * phi: n_pert x N_pw' complex on S' (Hermitian-symmetric rows); out: same shape.
+ * The n_pert * N_v Sternheimer systems are solved as one batched CG (tiled under
+ * opts.hbm_budget / opts.rhs_tile).  st may be NULL. */
+int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st);
+
+/* Test hook: density response dn (n_pert x N_g doubles) to real potentials
+ * dv_r (n_pert x N_g doubles) given directly on the grid, no Coulomb scaling. */
+int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, pdep_apply_stats* st);
+
+/* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
+ * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
+ * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own
+ * SplitMix64 + Box-Muller generator) or n_pdep x N_pw' complex Hermitian-symmetric
+ * start vectors.  eps_out: n_pdep dielectric eigenvalues 1 - lambda_i, descending.
+ * basis_out: NULL or n_pdep x N_pw' complex eigenvectors in the same order.
+ * eo may be NULL (tol 1e-9, maxit 60, restart 4 n_pdep, no buffer). */
+int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0,
+              const pdep_eig_opts* eo, double* eps_out, double* basis_out, pdep_eig_stats* st);
+
+int pdep_destroy(pdep_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* pdep_last_error(void);
+
+/* Kernel timing (instrumentation, process-wide).  While enabled, every kernel launch
+ * of the library is bracketed by two HIP events recorded on its launch stream.
+ * pdep_profile_read returns, per kernel class k < max_kernels, the summed device time
+ * (ms), launch count, algorithmic HBM bytes and algorithmic flops since the last reset
+ * (any output pointer may be NULL); classes are named by pdep_profile_kernel_name(k)
+ * ("" past the last class).  Call after the timed work finished. */
+int pdep_profile_enable(int on);
+int pdep_profile_read(int reset, double* total_ms, long long* launches, double* bytes, double* flops,
+                      int max_kernels);
+const char* pdep_profile_kernel_name(int k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDEP_H */

@@ -1,0 +1,369 @@
+// C ABI entry points (declared in include/pdep.h): argument checks, host/device
+// marshalling, S <-> S' conversion, timing and error reporting.  All numerical work is
+// in the kernels of fft.hip / linalg.hip driven by solver.hip and davidson.hip.
+#include <chrono>
+#include <cmath>
+#include <string>
+
+#include "pdep_internal.h"
+
+using pdep::Ctx;
+using pdep::Error;
+
+struct pdep_ctx {
+    Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+bool all_finite(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        PDEP_HIP(hipEventCreate(&a));
+        PDEP_HIP(hipEventCreate(&b));
+        PDEP_HIP(hipEventRecord(a, s));
+    }
+    double stop() {
+        float ms = 0.f;
+        PDEP_HIP(hipEventRecord(b, s));
+        PDEP_HIP(hipEventSynchronize(b));
+        PDEP_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+enum CapiSlot { C_IN = 17, C_OUT = 18, C_STAGE = 19 };
+
+void check_ctx(pdep_ctx* ctx) { PDEP_REQUIRE(ctx != nullptr, PDEP_EINVAL, "null context"); }
+
+// Build the resident u_v(r) = Inv(c_v) grids and the FP32 copies of Psi and V.
+void finish_setup(Ctx& c) {
+    const pdep::Basis& b = c.basis;
+    const int nv = c.nv, npw = b.npw;
+    hipStream_t s = c.stream;
+    c.u64.ensure(&c.al, (size_t)nv * b.ng * sizeof(double2));
+    double2* planes = static_cast<double2*>(c.ws(pdep::W_STAGE_PLANES, (size_t)nv * b.ax * b.dims.ny * b.dims.nz *
+                                                                           sizeof(double2)));
+    pdep::launch_sphere_to_planes<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nullptr, nv, nullptr, planes, s);
+    pdep::launch_pencil_inv_store<double>(b.dims, b.tables, planes, nv, c.u64.as<double2>(), nullptr, s);
+    c.psi32.ensure(&c.al, (size_t)nv * npw * sizeof(float2));
+    pdep::launch_convert_rows<double, float>(nv, npw, c.psi64.as<double2>(), npw, nullptr, nullptr,
+                                             c.psi32.as<float2>(), npw, s);
+    c.eps_dev.ensure(&c.al, (size_t)nv * sizeof(double));
+    PDEP_HIP(hipMemcpyAsync(c.eps_dev.get(), c.eps.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
+    // residual of the orbitals in use
+    const long ld = npw;
+    double2* hx = static_cast<double2*>(c.ws(C_OUT, (size_t)nv * ld * sizeof(double2)));
+    pdep::apply_h64(c, c.psi64.as<double2>(), ld, nv, c.eps_dev.as<double>(), nv, hx, ld, planes);
+    double* dots = static_cast<double*>(c.ws(C_STAGE, (size_t)nv * sizeof(double)));
+    pdep::launch_row_dots<double>(nv, npw, hx, ld, hx, ld, dots, nullptr, s);
+    std::vector<double> r2(nv);
+    PDEP_HIP(hipMemcpyAsync(r2.data(), dots, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    double mx = 0.0;
+    for (double x : r2) mx = std::max(mx, std::sqrt(std::max(x, 0.0)));
+    c.gs_residual = mx;
+}
+
+}  // namespace
+
+#define API_BEGIN try {
+#define API_END                                                                  \
+    }                                                                            \
+    catch (const Error& e) { return fail(e.code, e.what()); }                    \
+    catch (const std::bad_alloc&) { return fail(PDEP_ENOMEM, "host allocation failed"); } \
+    catch (const std::exception& e) { return fail(PDEP_EDEVICE, e.what()); }     \
+    g_err.clear();                                                               \
+    return PDEP_OK;
+
+extern "C" {
+
+void pdep_default_opts(pdep_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_v = 1;
+    o->precision = PDEP_FP64;
+    o->cg_tol = 1e-10;
+    o->cg_maxit = 2000;
+    o->inner_tol = 1e-5;
+    o->refine_maxit = 8;
+    o->precond = 1;
+    o->gap_min = 1e-3;
+    o->gs_tol = 1e-10;
+    o->gs_maxit = 400;
+}
+
+const char* pdep_last_error(void) { return g_err.c_str(); }
+
+int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts, const double* psi_in,
+               const double* eps_in, pdep_ctx** out) {
+    if (out) *out = nullptr;
+    pdep_ctx* ctx = nullptr;
+    API_BEGIN
+    PDEP_REQUIRE(cell && vloc && opts && out, PDEP_EINVAL, "null argument");
+    PDEP_REQUIRE(opts->n_v >= 1, PDEP_EINVAL, "n_v must be >= 1");
+    PDEP_REQUIRE(opts->precision == PDEP_FP64 || opts->precision == PDEP_MIXED_FP32, PDEP_EINVAL, "bad precision");
+    PDEP_REQUIRE(opts->cg_tol > 0 && opts->cg_tol < 1 && opts->cg_maxit >= 1, PDEP_EINVAL, "bad CG tolerance/cap");
+    PDEP_REQUIRE(opts->precision == PDEP_FP64 || (opts->inner_tol > 0 && opts->inner_tol < 1), PDEP_EINVAL,
+                 "bad inner tolerance");
+    PDEP_REQUIRE((psi_in == nullptr) == (eps_in == nullptr), PDEP_EINVAL, "psi_in and eps_in go together");
+    ctx = new pdep_ctx();
+    Ctx& c = ctx->c;
+    c.opts = *opts;
+    c.al.a = opts->alloc;
+    c.stream = static_cast<hipStream_t>(opts->stream);
+    pdep::build_basis(*cell, c.basis);
+    const pdep::Basis& b = c.basis;
+    PDEP_REQUIRE(all_finite(vloc, b.ng), PDEP_EINVAL, "V_loc contains NaN or Inf");
+    PDEP_REQUIRE(opts->n_v + 1 < b.npw, PDEP_EINVAL, "n_v too large for the basis");
+    PDEP_HIP(hipGetDevice(&c.device));
+    pdep::upload_basis(c.basis, &c.al, c.stream);
+    c.nv = opts->n_v;
+    c.vloc64.ensure(&c.al, (size_t)b.ng * sizeof(double));
+    PDEP_HIP(hipMemcpyAsync(c.vloc64.get(), vloc, (size_t)b.ng * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    std::vector<float> v32(vloc, vloc + b.ng);
+    c.vloc32.ensure(&c.al, (size_t)b.ng * sizeof(float));
+    PDEP_HIP(hipMemcpyAsync(c.vloc32.get(), v32.data(), (size_t)b.ng * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    PDEP_HIP(hipStreamSynchronize(c.stream));
+    if (psi_in) {
+        PDEP_REQUIRE(all_finite(psi_in, (size_t)2 * c.nv * b.npw) && all_finite(eps_in, c.nv), PDEP_EINVAL,
+                     "psi_in / eps_in contain NaN or Inf");
+        c.eps.assign(eps_in, eps_in + c.nv);
+        c.psi64.ensure(&c.al, (size_t)c.nv * b.npw * sizeof(double2));
+        PDEP_HIP(hipMemcpyAsync(c.psi64.get(), psi_in, (size_t)c.nv * b.npw * sizeof(double2), hipMemcpyHostToDevice,
+                                c.stream));
+        c.gap = 0.0;
+        c.gs_iterations = 0;
+    } else {
+        pdep::ground_state(c);
+        if (c.gap < opts->gap_min) {
+            const std::string m = "HOMO-LUMO gap " + std::to_string(c.gap) + " Ha below gap_min";
+            delete ctx;
+            ctx = nullptr;
+            return fail(PDEP_EGAP, m);
+        }
+    }
+    finish_setup(c);
+    *out = ctx;
+    ctx = nullptr;
+    }
+    catch (const Error& e) { delete ctx; return fail(e.code, e.what()); }
+    catch (const std::bad_alloc&) { delete ctx; return fail(PDEP_ENOMEM, "host allocation failed"); }
+    catch (const std::exception& e) { delete ctx; return fail(PDEP_EDEVICE, e.what()); }
+    g_err.clear();
+    return PDEP_OK;
+}
+
+int pdep_get_info(pdep_ctx* ctx, pdep_info* info) {
+    API_BEGIN
+    check_ctx(ctx);
+    PDEP_REQUIRE(info != nullptr, PDEP_EINVAL, "null info");
+    const Ctx& c = ctx->c;
+    info->n_pw = c.basis.npw;
+    info->n_v = c.nv;
+    info->n_grid = c.basis.ng;
+    info->gap = c.gap;
+    info->volume = c.basis.omega;
+    info->gs_iterations = c.gs_iterations;
+    info->gs_residual = c.gs_residual;
+    API_END
+}
+
+int pdep_get_gvectors(pdep_ctx* ctx, int32_t* miller) {
+    API_BEGIN
+    check_ctx(ctx);
+    PDEP_REQUIRE(miller != nullptr, PDEP_EINVAL, "null output");
+    std::memcpy(miller, ctx->c.basis.miller.data(), ctx->c.basis.miller.size() * sizeof(int32_t));
+    API_END
+}
+
+int pdep_get_orbitals(pdep_ctx* ctx, double* eps, double* psi) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    if (eps) std::memcpy(eps, c.eps.data(), c.nv * sizeof(double));
+    if (psi) {
+        PDEP_HIP(hipMemcpyAsync(psi, c.psi64.get(), (size_t)c.nv * c.basis.npw * sizeof(double2), hipMemcpyDeviceToHost,
+                                c.stream));
+        PDEP_HIP(hipStreamSynchronize(c.stream));
+    }
+    API_END
+}
+
+int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    PDEP_REQUIRE(n_pert >= 0, PDEP_EINVAL, "n_pert must be >= 0");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (n_pert == 0) { g_err.clear(); return PDEP_OK; }
+    PDEP_REQUIRE(phi && out, PDEP_EINVAL, "null phi/out");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)n_pert * ld * sizeof(double2)));
+    double2* out_s = static_cast<double2*>(c.ws(C_OUT, (size_t)n_pert * ld * sizeof(double2)));
+    if (dev) {
+        pdep::launch_expand_s1(n_pert, npw, g0, reinterpret_cast<const double2*>(phi), n1, in_s, ld, s);
+    } else {
+        PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pert * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+        pdep::launch_expand_s1(n_pert, npw, g0, stage, n1, in_s, ld, s);
+    }
+    pdep::ApplyStats as;
+    pdep::chi0bar_sphere(c, n_pert, in_s, out_s, as);
+    if (dev) {
+        pdep::launch_compact_s1(n_pert, npw, g0, out_s, ld, reinterpret_cast<double2*>(out), n1, s);
+    } else {
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        pdep::launch_compact_s1(n_pert, npw, g0, out_s, ld, stage, n1, s);
+        PDEP_HIP(hipMemcpyAsync(out, stage, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    const double ms = tm.stop();
+    if (st) {
+        st->n_rhs = as.n_rhs;
+        st->cg_iter_max = as.cg_iter_max;
+        st->cg_iter_total = as.cg_iter_total;
+        st->op_applications = as.op_applications;
+        st->refine_steps = as.refine_steps;
+        st->n_notconv = as.n_notconv;
+        st->max_rel_residual = as.max_rel_residual;
+        st->ms = ms;
+    }
+    if (as.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
+    API_END
+}
+
+int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, pdep_apply_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    PDEP_REQUIRE(n_pert >= 0, PDEP_EINVAL, "n_pert must be >= 0");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (n_pert == 0) { g_err.clear(); return PDEP_OK; }
+    PDEP_REQUIRE(dv_r && dn_r, PDEP_EINVAL, "null dv/dn");
+    const size_t ng = c.basis.ng;
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    const double* dv = dv_r;
+    double* dn = dn_r;
+    if (!dev) {
+        PDEP_REQUIRE(all_finite(dv_r, (size_t)n_pert * ng), PDEP_EINVAL, "dv contains NaN or Inf");
+        double* in_d = static_cast<double*>(c.ws(C_IN, (size_t)n_pert * ng * sizeof(double)));
+        PDEP_HIP(hipMemcpyAsync(in_d, dv_r, (size_t)n_pert * ng * sizeof(double), hipMemcpyHostToDevice, s));
+        dv = in_d;
+        dn = static_cast<double*>(c.ws(C_OUT, (size_t)n_pert * ng * sizeof(double)));
+    }
+    pdep::ApplyStats as;
+    pdep::chi0_grid(c, n_pert, dv, dn, as);
+    if (!dev) PDEP_HIP(hipMemcpyAsync(dn_r, dn, (size_t)n_pert * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+    const double ms = tm.stop();
+    if (st) {
+        st->n_rhs = as.n_rhs;
+        st->cg_iter_max = as.cg_iter_max;
+        st->cg_iter_total = as.cg_iter_total;
+        st->op_applications = as.op_applications;
+        st->refine_steps = as.refine_steps;
+        st->n_notconv = as.n_notconv;
+        st->max_rel_residual = as.max_rel_residual;
+        st->ms = ms;
+    }
+    if (as.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
+    API_END
+}
+
+int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, const pdep_eig_opts* eo_in,
+              double* eps_out, double* basis_out, pdep_eig_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    PDEP_REQUIRE(eps_out != nullptr, PDEP_EINVAL, "null eps_out");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    PDEP_REQUIRE(n_pdep >= 1 && n_pdep < n1, PDEP_EINVAL, "n_pdep out of range");
+    pdep_eig_opts eo;
+    eo.tol = 1e-9;
+    eo.maxit = 60;
+    eo.max_subspace = 0;
+    eo.n_buffer = 0;
+    if (eo_in) eo = *eo_in;
+    PDEP_REQUIRE(eo.tol > 0 && eo.maxit >= 1 && eo.n_buffer >= 0, PDEP_EINVAL, "bad eig options");
+    if (st) std::memset(st, 0, sizeof(*st));
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    // C_IN / C_OUT are used by chi0 inside the Davidson loop: keep own buffers here
+    pdep::Buf phi0_s, basis_s, stage;
+    if (phi0) {
+        phi0_s.ensure(&c.al, (size_t)n_pdep * ld * sizeof(double2));
+        if (dev) {
+            pdep::launch_expand_s1(n_pdep, npw, g0, reinterpret_cast<const double2*>(phi0), n1, phi0_s.as<double2>(),
+                                   ld, s);
+        } else {
+            PDEP_REQUIRE(all_finite(phi0, (size_t)2 * n_pdep * n1), PDEP_EINVAL, "phi0 contains NaN or Inf");
+            stage.ensure(&c.al, (size_t)n_pdep * n1 * sizeof(double2));
+            PDEP_HIP(hipMemcpyAsync(stage.get(), phi0, (size_t)n_pdep * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+            pdep::launch_expand_s1(n_pdep, npw, g0, stage.as<double2>(), n1, phi0_s.as<double2>(), ld, s);
+        }
+    }
+    if (basis_out) basis_s.ensure(&c.al, (size_t)n_pdep * ld * sizeof(double2));
+    std::vector<double> lam(n_pdep);
+    pdep::EigResult r = pdep::pdep_davidson(c, n_pdep, seed, phi0 ? phi0_s.as<double2>() : nullptr, eo, lam.data(),
+                                            basis_out ? basis_s.as<double2>() : nullptr);
+    for (int i = 0; i < n_pdep; ++i) eps_out[i] = 1.0 - lam[i];
+    if (basis_out) {
+        if (dev) {
+            pdep::launch_compact_s1(n_pdep, npw, g0, basis_s.as<double2>(), ld, reinterpret_cast<double2*>(basis_out),
+                                    n1, s);
+        } else {
+            stage.ensure(&c.al, (size_t)n_pdep * n1 * sizeof(double2));
+            pdep::launch_compact_s1(n_pdep, npw, g0, basis_s.as<double2>(), ld, stage.as<double2>(), n1, s);
+            PDEP_HIP(hipMemcpyAsync(basis_out, stage.get(), (size_t)n_pdep * n1 * sizeof(double2),
+                                    hipMemcpyDeviceToHost, s));
+        }
+    }
+    const double ms = tm.stop();
+    if (st) {
+        st->iterations = r.iterations;
+        st->chi0_columns = r.columns;
+        st->max_residual = r.max_residual;
+        st->cg_iter_total = r.cg_iter_total;
+        st->ms = ms;
+    }
+    if (!r.converged) return fail(PDEP_ENOTCONV, "PDEP Davidson did not reach tol");
+    API_END
+}
+
+int pdep_destroy(pdep_ctx* ctx) {
+    API_BEGIN
+    if (!ctx) { g_err.clear(); return PDEP_OK; }
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+    API_END
+}
+
+}  // extern "C"

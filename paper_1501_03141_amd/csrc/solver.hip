@@ -1,0 +1,360 @@
+// Batched Sternheimer solves and the chi0 chain on the device.
+//
+// For a block of real potentials dV_i(r) and every occupied band v (one "row" per
+// pair (i, v), row = i * N_v + v):
+//   b_iv  = -P_c Fwd(dV_i u_v)                               (right-hand side, FP64)
+//   solve   P_c (H - e_v) P_c dc_iv = b_iv  on range(P_c)    (Sec. 2.3, Eq. stern)
+//   dn_i  = (4/Omega) Re sum_v conj(u_v) Inv(dc_iv)           (Eq. deltani, Gamma, 2 spins)
+//   out_i = sqrt(4 pi)/|G| Fwd(dn_i) on S'                    (Eq. chiisamatrixinpdep)
+//
+// The solve is a preconditioned conjugate gradient (the paper's suggestion after
+// Eq. stern) batched over all rows of a tile, wrapped in an FP64 iterative refinement:
+//   x = 0, r = b;  repeat:  d ~ A^-1 r by CG in precision T (FP64 or FP32),
+//                           x += d,  r = b - A x in FP64,
+// until ||r|| <= cg_tol ||b|| per row.  In FP64 mode the inner CG already aims at the
+// final tolerance, so one step normally suffices and the second FP64 residual only
+// confirms it.  In mixed mode the inner FP32 CG reduces the residual by inner_tol per
+// step.  Converged rows drop out of later steps (the row list is compacted on the host).
+//
+// Inner CG (rows independent, per-row scalars in FP64):
+//   r = b, z = P_c K r, p = z
+//   q = A p;  alpha = <r,z>/<p,q>;  x += alpha p;  r -= alpha q;  z = P_c K r;
+//   beta = <r,z>_new/<r,z>;  p = z + beta p;  stop when ||r||^2 <= thr2
+// with A = P_c (H - e_v) applied as plane pass -> pencil pass (V_loc) -> plane pass with
+// the kinetic/shift epilogue -> P_c GEMM pair, and K the diagonal kinetic preconditioner
+// 1/max(1, 1/2|G|^2 - e_v) (the paper does not fix K; it only changes iteration counts).
+#include <algorithm>
+#include <cmath>
+
+#include "pdep_internal.h"
+
+namespace pdep {
+
+namespace {
+
+enum Slot {
+    W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_PLANES, W_S, W_SCAL,
+    W_ROWS, W_VR, W_DN
+};
+
+template <typename T> const cplx<T>* psi_of(Ctx& c);
+template <> const double2* psi_of<double>(Ctx& c) { return c.psi64.as<double2>(); }
+template <> const float2* psi_of<float>(Ctx& c) { return c.psi32.as<float2>(); }
+template <typename T> const T* vloc_of(Ctx& c);
+template <> const double* vloc_of<double>(Ctx& c) { return c.vloc64.as<double>(); }
+template <> const float* vloc_of<float>(Ctx& c) { return c.vloc32.as<float>(); }
+template <typename T> const T* kin_of(Ctx& c);
+template <> const double* kin_of<double>(Ctx& c) { return c.basis.d_kin64.as<double>(); }
+template <> const float* kin_of<float>(Ctx& c) { return c.basis.d_kin32.as<float>(); }
+
+size_t planes_row_bytes(const Ctx& c) {
+    const FftDims& d = c.basis.dims;
+    return (size_t)d.ax * d.ny * d.nz * sizeof(double2);
+}
+
+}  // namespace
+
+long sphere_ld(int npw) { return ((long)npw + 63) / 64 * 64; }
+
+// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.
+template <typename T>
+void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
+    const int npw = c.basis.npw, nv = c.nv;
+    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), npw, Y, ld, nullptr, S, nv, c.stream);
+    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), npw, S, nv, -1.0, 1.0, Y, ld, nullptr, c.stream);
+}
+
+// q = [P_c] (H - shift) p
+template <typename T>
+void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const double* shift, int nshift,
+              bool project, void* planes, double2* S) {
+    const Basis& b = c.basis;
+    cplx<T>* pl = static_cast<cplx<T>*>(planes);
+    launch_sphere_to_planes<T>(b.dims, b.tables, p, ld, nullptr, nrows, nullptr, pl, c.stream);
+    launch_pencil_hv<T>(b.dims, b.tables, pl, nrows, vloc_of<T>(c), 0, nullptr, c.stream);
+    launch_planes_to_sphere<T>(b.dims, b.tables, pl, nrows, nullptr, q, ld, EPI_SHIFTED_H, 0.0, p, ld, kin_of<T>(c),
+                               shift, nshift, nullptr, c.stream);
+    if (project) project_c<T>(c, q, ld, nrows, S);
+}
+
+void apply_h64(Ctx& c, const double2* x, long ldx, int nrows, const double* shift, int nshift, double2* out,
+               long ldo, double2* planes) {
+    PDEP_REQUIRE(ldx == ldo, PDEP_EINVAL, "apply_h64: ld mismatch");
+    apply_op<double>(c, x, out, ldx, nrows, shift, nshift, false, planes, nullptr);
+}
+
+namespace {
+
+struct CgScalars {
+    double *rz, *rz_new, *pq, *rr, *thr2, *shift;
+    int *active, *iters, *n_active;
+};
+
+CgScalars cg_scalars(Ctx& c, int n) {
+    const size_t nd = 6 * (size_t)n, ni = 2 * (size_t)n + 64;
+    char* base = static_cast<char*>(c.ws(W_SCAL, nd * sizeof(double) + ni * sizeof(int)));
+    CgScalars s;
+    double* d = reinterpret_cast<double*>(base);
+    s.rz = d; s.rz_new = d + n; s.pq = d + 2 * n; s.rr = d + 3 * n; s.thr2 = d + 4 * n; s.shift = d + 5 * n;
+    int* i = reinterpret_cast<int*>(base + nd * sizeof(double));
+    s.active = i; s.iters = i + n; s.n_active = i + 2 * n;
+    return s;
+}
+
+// Inner batched PCG in precision T on n rows: solves P_c (H - shift) x = b with x0 = 0.
+// sc.shift / sc.thr2 must be filled by the caller.  Returns the number of iterations
+// run; per-row counts are left in sc.iters.
+template <typename T>
+int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit, ApplyStats& st) {
+    const int npw = c.basis.npw, nv = c.nv;
+    hipStream_t s = c.stream;
+    const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
+    cplx<T>* x = static_cast<cplx<T>*>(c.ws(W_CX, vbytes));
+    cplx<T>* r = static_cast<cplx<T>*>(c.ws(W_CR, vbytes));
+    cplx<T>* z = static_cast<cplx<T>*>(c.ws(W_CZ, vbytes));
+    cplx<T>* p = static_cast<cplx<T>*>(c.ws(W_CP, vbytes));
+    cplx<T>* q = static_cast<cplx<T>*>(c.ws(W_CQ, vbytes));
+    void* planes = c.ws(W_PLANES, (size_t)n * planes_row_bytes(c));
+    double2* S = static_cast<double2*>(c.ws(W_S, (size_t)n * nv * sizeof(double2)));
+    const int pre = c.opts.precond;
+    const T* kin = kin_of<T>(c);
+
+    launch_cg_init<T>(n, npw, b, ld, x, r, z, kin, sc.shift, n, pre, s);
+    if (pre) project_c<T>(c, z, ld, n, S);
+    PDEP_HIP(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, s));
+    launch_row_dots<T>(n, npw, r, ld, z, ld, sc.rz, sc.rr, s);
+    launch_fill_i32(sc.active, n, 1, s);
+    launch_fill_i32(sc.iters, n, 0, s);
+    launch_fill_zero(sc.n_active, sizeof(int), s);
+    launch_cg_check(n, sc.rr, sc.thr2, sc.active, sc.iters, sc.rz, nullptr, sc.n_active, 0, s);
+    int h_active = 0;
+    PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    int it = 0;
+    const int poll = 4;
+    while (h_active > 0 && it < maxit) {
+        const int nstep = std::min(poll, maxit - it);
+        for (int k = 0; k < nstep; ++k) {
+            apply_op<T>(c, p, q, ld, n, sc.shift, n, true, planes, S);
+            st.op_applications++;
+            launch_row_dots<T>(n, npw, p, ld, q, ld, sc.pq, nullptr, s);
+            launch_cg_step1<T>(n, npw, x, r, z, p, q, ld, sc.rz, sc.pq, sc.active, kin, sc.shift, n, pre, s);
+            if (pre) project_c<T>(c, z, ld, n, S);
+            launch_row_dots<T>(n, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
+            launch_cg_step2<T>(n, npw, p, z, ld, sc.rz_new, sc.rz, sc.active, s);
+            launch_fill_zero(sc.n_active, sizeof(int), s);
+            launch_cg_check(n, sc.rr, sc.thr2, sc.active, sc.iters, sc.rz, sc.rz_new, sc.n_active, 1, s);
+        }
+        it += nstep;
+        PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        PDEP_HIP(hipStreamSynchronize(s));
+    }
+    return it;
+}
+
+template <typename T> cplx<T>* cg_solution(Ctx& c) { return c.w[W_CX].as<cplx<T>>(); }
+
+}  // namespace
+
+// Solve all n rows of b64 to opts.cg_tol; x64 receives dc (not yet re-projected).
+// ref2 (may be null): per-row squared norm of the right-hand side before P_c.  A row
+// whose projected norm is below 1e-13 of it carries only rounding noise (the
+// perturbation acts inside the occupied space, e.g. a constant dV) and is solved as
+// b = 0, x = 0.
+void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyStats& st,
+                const double* ref2) {
+    const int npw = c.basis.npw, nv = c.nv;
+    hipStream_t s = c.stream;
+    const double tol = c.opts.cg_tol;
+    const bool mixed = c.opts.precision == PDEP_MIXED_FP32;
+    const size_t vb64 = (size_t)n * ld * sizeof(double2);
+    double2* r64 = static_cast<double2*>(c.ws(W_R64, vb64));
+    double2* xa = static_cast<double2*>(c.ws(W_XA, vb64));
+    double2* qa = static_cast<double2*>(c.ws(W_QA, vb64));
+    // packed host->device row data: rows (int), scale, invscale (double)
+    char* rowbuf = static_cast<char*>(c.ws(W_ROWS, (size_t)n * (sizeof(int) + 2 * sizeof(double)) + 64));
+    double* d_scale = reinterpret_cast<double*>(rowbuf);
+    double* d_invscale = d_scale + n;
+    int* d_rows = reinterpret_cast<int*>(d_invscale + n);
+    CgScalars sc = cg_scalars(c, n);
+
+    std::vector<double> bb(n), rr(n), dots(n);
+    launch_row_dots<double>(n, npw, b64, ld, b64, ld, sc.rr, nullptr, s);
+    PDEP_HIP(hipMemcpyAsync(bb.data(), sc.rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_fill_zero(x64, vb64, s);
+    PDEP_HIP(hipMemcpyAsync(r64, b64, vb64, hipMemcpyDeviceToDevice, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) PDEP_REQUIRE(std::isfinite(bb[i]), PDEP_EINVAL, "non-finite right-hand side");
+    if (ref2) {
+        std::vector<double> w2(n);
+        PDEP_HIP(hipMemcpy(w2.data(), ref2, n * sizeof(double), hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i)
+            if (bb[i] <= 1e-26 * w2[i]) bb[i] = 0.0;
+    }
+    rr = bb;
+    std::vector<int> it_row(n, 0);
+    std::vector<int> rows;
+    std::vector<double> hs(3 * (size_t)n);
+    for (int step = 0;; ++step) {
+        rows.clear();
+        for (int i = 0; i < n; ++i)
+            if (bb[i] > 0.0 && rr[i] > tol * tol * bb[i]) rows.push_back(i);
+        if (rows.empty()) break;
+        if (step >= std::max(1, c.opts.refine_maxit)) {
+            st.n_notconv += (int)rows.size();
+            break;
+        }
+        const int na = (int)rows.size();
+        std::vector<double> scale(na), invscale(na), shift(na), thr2(na);
+        for (int j = 0; j < na; ++j) {
+            const int i = rows[j];
+            const double rn = std::sqrt(rr[i]);
+            scale[j] = 1.0 / rn;
+            invscale[j] = rn;
+            shift[j] = c.eps[i % nv];
+            if (mixed) {
+                thr2[j] = c.opts.inner_tol * c.opts.inner_tol;
+            } else {
+                const double t = 0.5 * tol * std::sqrt(bb[i]) / rn;
+                thr2[j] = std::max(t * t, 1e-30);
+            }
+        }
+        PDEP_HIP(hipMemcpyAsync(d_scale, scale.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        PDEP_HIP(hipMemcpyAsync(d_invscale, invscale.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        PDEP_HIP(hipMemcpyAsync(d_rows, rows.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
+        PDEP_HIP(hipMemcpyAsync(sc.shift, shift.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        PDEP_HIP(hipMemcpyAsync(sc.thr2, thr2.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        if (mixed) {
+            float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ld * sizeof(float2)));
+            launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ld, s);
+            cg_inner<float>(c, na, rhs, ld, sc, c.opts.cg_maxit, st);
+            launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ld, d_rows, d_invscale, x64, ld, s);
+        } else {
+            double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ld * sizeof(double2)));
+            launch_convert_rows<double, double>(na, npw, r64, ld, d_rows, d_scale, rhs, ld, s);
+            cg_inner<double>(c, na, rhs, ld, sc, c.opts.cg_maxit, st);
+            launch_axpy_rows<double>(na, npw, cg_solution<double>(c), ld, d_rows, d_invscale, x64, ld, s);
+        }
+        std::vector<int> its(na);
+        PDEP_HIP(hipMemcpyAsync(its.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
+        // true FP64 residual of the rows just updated
+        launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
+        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, c.ws(W_PLANES, (size_t)na * planes_row_bytes(c)),
+                         static_cast<double2*>(c.ws(W_S, (size_t)na * nv * sizeof(double2))));
+        st.op_applications++;
+        launch_sub_rows(na, npw, b64, ld, d_rows, qa, ld, qa, ld, s);
+        launch_scatter_rows(na, npw, qa, ld, d_rows, r64, ld, s);
+        launch_row_dots<double>(na, npw, qa, ld, qa, ld, sc.rr, nullptr, s);
+        PDEP_HIP(hipMemcpyAsync(dots.data(), sc.rr, na * sizeof(double), hipMemcpyDeviceToHost, s));
+        PDEP_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < na; ++j) {
+            rr[rows[j]] = dots[j];
+            it_row[rows[j]] += its[j];
+        }
+        st.refine_steps = std::max(st.refine_steps, step + 1);
+    }
+    for (int i = 0; i < n; ++i) {
+        st.cg_iter_total += it_row[i];
+        st.cg_iter_max = std::max(st.cg_iter_max, it_row[i]);
+        if (bb[i] > 0.0) st.max_rel_residual = std::max(st.max_rel_residual, std::sqrt(rr[i] / bb[i]));
+    }
+    st.n_rhs += n;
+}
+
+namespace {
+
+size_t row_bytes(const Ctx& c, long ld) {
+    const size_t inner = c.opts.precision == PDEP_MIXED_FP32 ? sizeof(float2) : sizeof(double2);
+    return (size_t)ld * sizeof(double2) * 5 + (size_t)ld * inner * 6 + planes_row_bytes(c) +
+           (size_t)c.nv * sizeof(double2) + 128;
+}
+
+int perturbation_tile(Ctx& c, int npert, long ld) {
+    if (c.opts.rhs_tile > 0)
+        return std::max(1, std::min({npert, c.opts.rhs_tile / std::max(1, c.nv), 65535 / std::max(1, c.nv)}));
+    size_t budget = c.opts.hbm_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            fr = (size_t)32 << 30;
+        }
+        budget = std::min((size_t)(fr * 0.6), (size_t)96 << 30);
+    }
+    const size_t per_pert = (size_t)c.nv * row_bytes(c, ld) + 2 * (size_t)c.basis.ng * sizeof(double);
+    size_t tp = budget / std::max<size_t>(per_pert, 1);
+    PDEP_REQUIRE(tp >= 1, PDEP_ENOMEM, "HBM budget below the work space of one perturbation");
+    tp = std::min<size_t>(tp, (size_t)(65535 / std::max(1, c.nv)));   // launch grid limit on rows
+    return (int)std::min<size_t>((size_t)npert, std::max<size_t>(tp, 1));
+}
+
+// Core chain for real grid potentials Vr [npert][ng] (device).  Writes dn [npert][ng]
+// (if non-null) and/or the projected result out [npert][ld_out] in S order (if non-null).
+void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out, long ld_out, ApplyStats& st) {
+    const Basis& b = c.basis;
+    const int nv = c.nv, npw = b.npw;
+    const long ld = sphere_ld(npw);
+    const long ng = b.ng;
+    hipStream_t s = c.stream;
+    const int tile = perturbation_tile(c, npert, ld);
+    for (int p0 = 0; p0 < npert; p0 += tile) {
+        const int tp = std::min(tile, npert - p0);
+        const int nrow = tp * nv;
+        double2* planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)nrow * planes_row_bytes(c)));
+        double2* b64 = static_cast<double2*>(c.ws(W_B64, (size_t)nrow * ld * sizeof(double2)));
+        double2* x64 = static_cast<double2*>(c.ws(W_X64, (size_t)nrow * ld * sizeof(double2)));
+        double2* S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
+        // right-hand sides b = -P_c Fwd(dV_i u_v)
+        launch_pencil_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.u64.as<double2>(), nv, nrow,
+                                          planes, s);
+        launch_planes_to_sphere<double>(b.dims, b.tables, planes, nrow, nullptr, b64, ld, EPI_SCALE, -1.0, nullptr,
+                                        0, nullptr, nullptr, 0, nullptr, s);
+        double* ref2 = static_cast<double*>(c.ws(W_DN + 1, (size_t)nrow * sizeof(double)));
+        launch_row_dots<double>(nrow, npw, b64, ld, b64, ld, ref2, nullptr, s);
+        project_c<double>(c, b64, ld, nrow, S);
+        PDEP_HIP(hipStreamSynchronize(s));
+        solve_rows(c, nrow, b64, x64, ld, st, ref2);
+        S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
+        project_c<double>(c, x64, ld, nrow, S);
+        // density response
+        planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)nrow * planes_row_bytes(c)));
+        launch_sphere_to_planes<double>(b.dims, b.tables, x64, ld, nullptr, nrow, nullptr, planes, s);
+        double* dn = dn_out ? dn_out + (long)p0 * ng
+                            : static_cast<double*>(c.ws(W_DN, (size_t)tp * ng * sizeof(double)));
+        launch_pencil_density(b.dims, b.tables, planes, tp, nv, c.u64.as<double2>(), 4.0 / b.omega, dn, s);
+        if (out) {
+            launch_pencil_fwd_product<double>(b.dims, b.tables, dn, nullptr, 1, tp, planes, s);
+            launch_planes_to_sphere<double>(b.dims, b.tables, planes, tp, nullptr, out + (long)p0 * ld_out, ld_out,
+                                            EPI_GSCALE, 0.0, nullptr, 0, nullptr, nullptr, 0,
+                                            b.d_coul.as<double>(), s);
+        }
+        PDEP_HIP(hipStreamSynchronize(s));
+    }
+}
+
+}  // namespace
+
+void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st) {
+    chi0_core(c, npert, dv, dn, nullptr, 0, st);
+}
+
+void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st) {
+    const Basis& b = c.basis;
+    const long ld = sphere_ld(b.npw);
+    double* Vr = static_cast<double*>(c.ws(W_VR, (size_t)npert * b.ng * sizeof(double)));
+    // dV_i = Re Inv(sqrt(4 pi)/|G| phi_i), processed in chunks to bound the plane buffer
+    const int chunk = 256;
+    for (int p0 = 0; p0 < npert; p0 += chunk) {
+        const int np = std::min(chunk, npert - p0);
+        double2* planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)np * planes_row_bytes(c)));
+        launch_sphere_to_planes<double>(b.dims, b.tables, phi + (long)p0 * ld, ld, nullptr, np,
+                                        b.d_coul.as<double>(), planes, c.stream);
+        launch_pencil_inv_store<double>(b.dims, b.tables, planes, np, nullptr, Vr + (long)p0 * b.ng, c.stream);
+    }
+    chi0_core(c, npert, Vr, nullptr, out, ld, st);
+}
+
+template void project_c<double>(Ctx&, double2*, long, int, double2*);
+template void project_c<float>(Ctx&, float2*, long, int, double2*);
+
+}  // namespace pdep

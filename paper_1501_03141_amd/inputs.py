@@ -168,3 +168,10 @@ def serving_stream(n_jobs: int = 300, rate_hz: float = 1.0, base_seed: int = 150
         wl = Workload(f"job{k}", (Ledge,) * 3, (g,) * 3, 12.0, nw, nv, npd, 1e-8, base_seed + 1 + k)
         jobs.append(ServingJob(k, wl, t))
     return jobs
+
+
+def random_grid_potentials(n: Sequence[int], n_pert: int, seed: int) -> np.ndarray:
+    """Real random-normal potentials on the grid, [n_pert, N_g] (test input for the
+    grid-level density-response hook)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((n_pert, int(np.prod(n))))

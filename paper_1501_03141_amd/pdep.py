@@ -1,0 +1,337 @@
+"""ctypes binding of libpdep.so (include/pdep.h): argument marshalling only.
+
+Every step of the chi0/PDEP path runs in the HIP library.  PyTorch is used only as
+plumbing: its caching allocator backs the library's device memory, its current HIP
+stream is the stream the library queues on, and torch tensors can be passed as
+device-resident inputs and outputs.  Loading fails loudly if the library is missing;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdep.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "pdep.h")
+
+PDEP_OK = 0
+PDEP_EINVAL = -1
+PDEP_ENOMEM = -2
+PDEP_ENOTCONV = -3
+PDEP_EGAP = -4
+PDEP_EDEVICE = -5
+PDEP_EBUSY = -6
+PDEP_ENOTFOUND = -7
+PDEP_FP64 = 0
+PDEP_MIXED_FP32 = 1
+PDEP_DEVICE_PTRS = 1
+
+_NAMES = {0: "PDEP_OK", -1: "PDEP_EINVAL", -2: "PDEP_ENOMEM", -3: "PDEP_ENOTCONV", -4: "PDEP_EGAP",
+          -5: "PDEP_EDEVICE", -6: "PDEP_EBUSY", -7: "PDEP_ENOTFOUND"}
+
+
+class PdepError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class Cell(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("n", C.c_int * 3), ("ecut", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("n_v", C.c_int), ("precision", C.c_int), ("cg_tol", C.c_double), ("cg_maxit", C.c_int),
+                ("inner_tol", C.c_double), ("refine_maxit", C.c_int), ("precond", C.c_int),
+                ("gap_min", C.c_double), ("gs_tol", C.c_double), ("gs_maxit", C.c_int),
+                ("hbm_budget", C.c_size_t), ("rhs_tile", C.c_int), ("stream", C.c_void_p),
+                ("alloc", Allocator), ("flags", C.c_uint32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_pw", C.c_int), ("n_v", C.c_int), ("n_grid", C.c_int), ("gap", C.c_double),
+                ("volume", C.c_double), ("gs_iterations", C.c_int), ("gs_residual", C.c_double)]
+
+
+class ApplyStats(C.Structure):
+    _fields_ = [("n_rhs", C.c_int), ("cg_iter_max", C.c_int), ("cg_iter_total", C.c_longlong),
+                ("op_applications", C.c_longlong), ("refine_steps", C.c_int), ("n_notconv", C.c_int),
+                ("max_rel_residual", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class EigOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("max_subspace", C.c_int), ("n_buffer", C.c_int)]
+
+
+class EigStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("chi0_columns", C.c_int), ("max_residual", C.c_double),
+                ("cg_iter_total", C.c_longlong), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpdep.so and declare the signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    # One HIP runtime per process: torch ships its own libamdhip64 / rocBLAS / rocSOLVER
+    # with the same sonames as /opt/rocm.  Loading torch first makes the library bind to
+    # those already-loaded copies instead of starting a second runtime next to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    D = C.POINTER(C.c_double)
+    lib.pdep_default_opts.argtypes = [C.POINTER(Opts)]
+    lib.pdep_default_opts.restype = None
+    lib.pdep_last_error.argtypes = []
+    lib.pdep_last_error.restype = C.c_char_p
+    lib.pdep_setup.argtypes = [C.POINTER(Cell), P, C.POINTER(Opts), P, P, C.POINTER(C.c_void_p)]
+    lib.pdep_get_info.argtypes = [P, C.POINTER(Info)]
+    lib.pdep_get_gvectors.argtypes = [P, P]
+    lib.pdep_get_orbitals.argtypes = [P, P, P]
+    lib.chi0_apply.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
+    lib.chi0_apply_raw.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
+    lib.pdep_eigs.argtypes = [P, C.c_int, C.c_uint64, P, C.POINTER(EigOpts), D, P, C.POINTER(EigStats)]
+    lib.pdep_destroy.argtypes = [P]
+    lib.pdep_profile_enable.argtypes = [C.c_int]
+    lib.pdep_profile_enable.restype = C.c_int
+    lib.pdep_profile_read.argtypes = [C.c_int, D, C.POINTER(C.c_longlong), D, D, C.c_int]
+    lib.pdep_profile_read.restype = C.c_int
+    lib.pdep_profile_kernel_name.argtypes = [C.c_int]
+    lib.pdep_profile_kernel_name.restype = C.c_char_p
+    for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
+                 "chi0_apply_raw", "pdep_eigs", "pdep_destroy"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions declared in include/pdep.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+def _check(code: int, allow=()):
+    if code != PDEP_OK and code not in allow:
+        msg = _lib.pdep_last_error().decode() if _lib is not None else ""
+        raise PdepError(code, msg)
+    return code
+
+
+def profile_enable(on: bool = True):
+    _check(load().pdep_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True):
+    """{kernel class: dict(ms, launches, bytes, flops)} since the last reset."""
+    lib = load()
+    n = 64
+    tot = (C.c_double * n)()
+    cnt = (C.c_longlong * n)()
+    byt = (C.c_double * n)()
+    flo = (C.c_double * n)()
+    _check(lib.pdep_profile_read(1 if reset else 0, tot, cnt, byt, flo, n))
+    out = {}
+    for k in range(n):
+        name = lib.pdep_profile_kernel_name(k).decode()
+        if not name:
+            break
+        out[name] = dict(ms=tot[k], launches=cnt[k], bytes=byt[k], flops=flo[k])
+    return out
+
+
+def _torch_allocator():
+    import torch
+
+    def alloc(nbytes, _ctx):
+        dev = torch.cuda.current_device()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, torch.cuda.current_stream(dev))
+
+    def free(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+    a = Allocator(ALLOC_FN(alloc), FREE_FN(free), None)
+    return a
+
+
+class Context:
+    """One Kohn-Sham system resident on the GPU (pdep_setup ... pdep_destroy).
+
+    Complex arrays are numpy complex128 (host mode) or torch complex128 CUDA tensors
+    (device mode, ``device_ptrs=True``).  PDEP vectors live on S' (G = 0 removed), in
+    the library's Miller order (see :meth:`miller`).
+    """
+
+    def __init__(self, L, n, ecut, vloc, n_v, precision=PDEP_FP64, cg_tol=1e-10, cg_maxit=2000,
+                 inner_tol=1e-5, refine_maxit=8, precond=1, gap_min=1e-3, gs_tol=1e-10, gs_maxit=400,
+                 hbm_budget=0, rhs_tile=0, psi=None, eps=None, device_ptrs=False, use_torch=True):
+        self._lib = load()
+        self._h = C.c_void_p()
+        cell = Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut))
+        o = Opts()
+        self._lib.pdep_default_opts(C.byref(o))
+        o.n_v = int(n_v)
+        o.precision = int(precision)
+        o.cg_tol = float(cg_tol)
+        o.cg_maxit = int(cg_maxit)
+        o.inner_tol = float(inner_tol)
+        o.refine_maxit = int(refine_maxit)
+        o.precond = int(precond)
+        o.gap_min = float(gap_min)
+        o.gs_tol = float(gs_tol)
+        o.gs_maxit = int(gs_maxit)
+        o.hbm_budget = int(hbm_budget)
+        o.rhs_tile = int(rhs_tile)
+        o.flags = PDEP_DEVICE_PTRS if device_ptrs else 0
+        self.device_ptrs = bool(device_ptrs)
+        self._alloc = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            self._alloc = _torch_allocator()
+            o.alloc = self._alloc
+            o.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
+        psi_p = eps_p = None
+        if psi is not None:
+            psi_a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+            eps_a = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+            psi_p, eps_p = psi_a.ctypes.data, eps_a.ctypes.data
+        self._opts = o
+        _check(self._lib.pdep_setup(C.byref(cell), v.ctypes.data, C.byref(o), psi_p, eps_p, C.byref(self._h)))
+        info = Info()
+        _check(self._lib.pdep_get_info(self._h, C.byref(info)))
+        self.n_pw = info.n_pw
+        self.n_v = info.n_v
+        self.n_grid = info.n_grid
+        self.gap = info.gap
+        self.volume = info.volume
+        self.gs_iterations = info.gs_iterations
+        self.gs_residual = info.gs_residual
+
+    # --------------------------------------------------------------------------------
+    def miller(self) -> np.ndarray:
+        m = np.empty((self.n_pw, 3), dtype=np.int32)
+        _check(self._lib.pdep_get_gvectors(self._h, m.ctypes.data))
+        return m
+
+    def orbitals(self):
+        eps = np.empty(self.n_v, dtype=np.float64)
+        psi = np.empty((self.n_v, self.n_pw), dtype=np.complex128)
+        _check(self._lib.pdep_get_orbitals(self._h, eps.ctypes.data, psi.ctypes.data))
+        return eps, psi
+
+    def _ptr(self, a, dtype, shape, out=False):
+        if self.device_ptrs:
+            import torch
+            if not (isinstance(a, torch.Tensor) and a.is_cuda and a.is_contiguous()):
+                raise TypeError("device mode expects a contiguous CUDA tensor")
+            want = torch.complex128 if dtype == np.complex128 else torch.float64
+            if a.dtype != want or tuple(a.shape) != tuple(shape):
+                raise TypeError(f"expected {want} tensor of shape {shape}, got {a.dtype} {tuple(a.shape)}")
+            return a.data_ptr(), a
+        arr = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+        if arr.shape != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {arr.shape}")
+        return arr.ctypes.data, arr
+
+    def _new(self, dtype, shape):
+        if self.device_ptrs:
+            import torch
+            return torch.empty(shape, dtype=torch.complex128 if dtype == np.complex128 else torch.float64,
+                               device="cuda")
+        return np.empty(shape, dtype=dtype)
+
+    def chi0_apply(self, phi, out=None, allow_notconv=False):
+        """chi0bar applied to the rows of phi [n_pert, N_pw - 1]; returns (result, stats)."""
+        n_pert = int(phi.shape[0])
+        shape = (n_pert, self.n_pw - 1)
+        p, keep = self._ptr(phi, np.complex128, shape)
+        if out is None:
+            out = self._new(np.complex128, shape)
+        o, keep_o = self._ptr(out, np.complex128, shape, out=True)
+        st = ApplyStats()
+        _check(self._lib.chi0_apply(self._h, n_pert, p, o, C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        return (keep_o if not self.device_ptrs else out), st.as_dict()
+
+    def chi0_apply_raw(self, dv, allow_notconv=False):
+        """Density response (real grids [n_pert, N_g]) to real grid potentials dv."""
+        n_pert = int(dv.shape[0])
+        shape = (n_pert, self.n_grid)
+        p, keep = self._ptr(dv, np.float64, shape)
+        out = self._new(np.float64, shape)
+        o, keep_o = self._ptr(out, np.float64, shape, out=True)
+        st = ApplyStats()
+        _check(self._lib.chi0_apply_raw(self._h, n_pert, p, o, C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        return (keep_o if not self.device_ptrs else out), st.as_dict()
+
+    def eigs(self, n_pdep, seed=0, phi0=None, tol=1e-9, maxit=60, max_subspace=0, n_buffer=0,
+             want_basis=False, allow_notconv=False):
+        """PDEP: (eps descending [n_pdep], basis [n_pdep, N_pw-1] or None, stats)."""
+        eps = np.empty(n_pdep, dtype=np.float64)
+        p0 = None
+        keep = None
+        if phi0 is not None:
+            p0, keep = self._ptr(phi0, np.complex128, (n_pdep, self.n_pw - 1))
+        basis = self._new(np.complex128, (n_pdep, self.n_pw - 1)) if want_basis else None
+        bptr = None
+        keep_b = None
+        if basis is not None:
+            bptr, keep_b = self._ptr(basis, np.complex128, (n_pdep, self.n_pw - 1), out=True)
+        eo = EigOpts(float(tol), int(maxit), int(max_subspace), int(n_buffer))
+        st = EigStats()
+        _check(self._lib.pdep_eigs(self._h, int(n_pdep), C.c_uint64(int(seed)), p0, C.byref(eo),
+                                   eps.ctypes.data_as(C.POINTER(C.c_double)), bptr, C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        if basis is not None and not self.device_ptrs:
+            basis = keep_b
+        return eps, basis, st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(self._lib.pdep_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
