@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <vector>
 
 #include "pdep_internal.h"
@@ -94,11 +95,11 @@ struct Solver {
     }
 };
 
-enum DSlot { D_V = 0, D_AV, D_X, D_AX, D_R, D_T, D_T2, D_M, D_W, D_TH, D_INFO };
+enum DSlot { D_V = 0, D_AV, D_X, D_AX, D_R, D_T, D_T2, D_M, D_W, D_TH, D_INFO, D_ROWS, D_COUNT };
 
 struct Workspace {
     Ctx& c;
-    Buf b[11];
+    Buf b[D_COUNT];
     explicit Workspace(Ctx& cc) : c(cc) {}
     void* get(int i, size_t bytes) { b[i].ensure(&c.al, bytes); return b[i].get(); }
 };
@@ -167,46 +168,100 @@ void combine(Ctx& c, const double2* X, int M, int N, long ld, const std::vector<
     PDEP_HIP(hipStreamSynchronize(c.stream));   // C is pageable host memory owned by the caller
 }
 
-// Orthonormalise the nt rows of T (in place, via T2) against the m rows of V (twice)
-// and among themselves (eigen-decomposition of the Gram matrix; directions with
-// relative weight below 1e-10 are dropped).  Returns the number of rows kept.
+// Scale every row of T to unit norm and drop rows whose norm is below `drop` (relative
+// to their norm before the last projection, i.e. rows that were already in span(V)).
+// Returns the number of rows kept (compacted to the front of T).
+int normalise_rows(Ctx& c, Workspace& ws, double2* T, int nt, long ld, const std::vector<double>& ref, double drop,
+                   std::vector<double>& norms_out) {
+    const int npw = c.basis.npw;
+    hipStream_t s = c.stream;
+    double* dn = static_cast<double*>(ws.get(D_TH, 2 * (size_t)std::max(nt, 1) * sizeof(double) + 64));
+    launch_row_dots<double>(nt, npw, T, ld, T, ld, dn, nullptr, s);
+    std::vector<double> n2(nt);
+    PDEP_HIP(hipMemcpyAsync(n2.data(), dn, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    std::vector<int> keep;
+    std::vector<double> scale;
+    norms_out.clear();
+    for (int j = 0; j < nt; ++j) {
+        const double nj = std::sqrt(std::max(n2[j], 0.0));
+        const double r = ref.empty() ? 1.0 : ref[j];
+        if (nj > drop * r && nj > 1e-300) {
+            keep.push_back(j);
+            scale.push_back(1.0 / nj);
+            norms_out.push_back(1.0);
+        }
+    }
+    const int nk = (int)keep.size();
+    if (nk == 0) return 0;
+    char* rb = static_cast<char*>(ws.get(D_ROWS, (size_t)nk * (sizeof(double) + sizeof(int)) + 64));
+    double* dscale = reinterpret_cast<double*>(rb);
+    int* drows = reinterpret_cast<int*>(dscale + nk);
+    double2* T2 = static_cast<double2*>(ws.get(D_T2, (size_t)nk * ld * sizeof(double2)));
+    PDEP_HIP(hipMemcpyAsync(dscale, scale.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
+    PDEP_HIP(hipMemcpyAsync(drows, keep.data(), nk * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_convert_rows<double, double>(nk, npw, T, ld, drows, dscale, T2, ld, s);
+    PDEP_HIP(hipMemcpyAsync(T, T2, (size_t)nk * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    return nk;
+}
+
+// Orthonormalise the nt rows of T (in place) against the m orthonormal rows of V and
+// among themselves.  Each of two rounds: unit-normalise the rows, project out V twice
+// (classical Gram-Schmidt, twice), drop rows that lost all but 1e-8 of their norm
+// (already in span(V)), renormalise, and orthonormalise the block through the
+// eigen-decomposition of its Gram matrix (directions with relative weight below
+// 1e-12 dropped).  real_coef keeps every combination coefficient real (Hermitian-
+// symmetric vectors stay Hermitian-symmetric).  Returns the number of rows kept.
 int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, double2* T, int nt, long ld,
                    bool real_coef) {
     const int npw = c.basis.npw;
     hipStream_t s = c.stream;
-    double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
-    double2* T2 = static_cast<double2*>(ws.get(D_T2, (size_t)nt * ld * sizeof(double2)));
-    for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, nullptr, Cdev, m, s);   // C[j][i] = <V_i, T_j>
-        if (real_coef) {
-            std::vector<double2> C = d2h(Cdev, (size_t)nt * m, s);
-            for (auto& x : C) x.y = 0.0;
-            PDEP_HIP(hipMemcpyAsync(Cdev, C.data(), C.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-            PDEP_HIP(hipStreamSynchronize(s));
+    std::vector<double> unit, unit2;
+    for (int round = 0; round < 2 && nt > 0; ++round) {
+        nt = normalise_rows(c, ws, T, nt, ld, {}, 1e-300, unit);
+        if (nt == 0) break;
+        if (m > 0) {
+            double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, nullptr, Cdev, m, s);   // C[j][i] = <V_i, T_j>
+                if (real_coef) {
+                    std::vector<double2> C = d2h(Cdev, (size_t)nt * m, s);
+                    for (auto& x : C) x.y = 0.0;
+                    PDEP_HIP(hipMemcpyAsync(Cdev, C.data(), C.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+                    PDEP_HIP(hipStreamSynchronize(s));
+                }
+                launch_gemm_update<double>(m, nt, npw, V, ld, Cdev, m, -1.0, 1.0, T, ld, nullptr, s);
+            }
+            nt = normalise_rows(c, ws, T, nt, ld, unit, 1e-8, unit2);
+            if (nt == 0) break;
         }
-        launch_gemm_update<double>(m, nt, npw, V, ld, Cdev, m, -1.0, 1.0, T, ld, nullptr, s);
-    }
-    launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, nullptr, Cdev, nt, s);
-    std::vector<double2> G = d2h(Cdev, (size_t)nt * nt, s);
-    std::vector<double> w;
-    std::vector<double2> Q;
-    dense_eig(ws, sv, G, nt, real_coef, w, Q);
-    const double wmax = std::max(w.empty() ? 0.0 : w.back(), 1e-300);
-    std::vector<double2> C;
-    int kept = 0;
-    for (int j = nt - 1; j >= 0; --j) {
-        if (w[j] <= 1e-10 * wmax || w[j] <= 1e-28) continue;
-        const double f = 1.0 / std::sqrt(w[j]);
-        for (int i = 0; i < nt; ++i) {
-            const double2 q = Q[(size_t)j * nt + i];   // column j, row i
-            C.push_back(make_double2(q.x * f, q.y * f));
+        double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
+        launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, nullptr, Cdev, nt, s);
+        std::vector<double2> G = d2h(Cdev, (size_t)nt * nt, s);
+        std::vector<double> w;
+        std::vector<double2> Q;
+        dense_eig(ws, sv, G, nt, real_coef, w, Q);
+        const double wmax = std::max(w.empty() ? 0.0 : w.back(), 1e-300);
+        std::vector<double2> C;
+        int kept = 0;
+        for (int j = nt - 1; j >= 0; --j) {
+            if (w[j] <= 1e-12 * wmax) continue;
+            const double f = 1.0 / std::sqrt(w[j]);
+            for (int i = 0; i < nt; ++i) {
+                const double2 q = Q[(size_t)j * nt + i];   // column j, row i
+                C.push_back(make_double2(q.x * f, real_coef ? 0.0 : q.y * f));
+            }
+            ++kept;
         }
-        ++kept;
+        if (kept == 0) return 0;
+        double2* T2 = static_cast<double2*>(ws.get(D_T2, (size_t)kept * ld * sizeof(double2)));
+        combine(c, T, nt, kept, ld, C, T2, Cdev);
+        PDEP_HIP(hipMemcpyAsync(T, T2, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        nt = kept;
     }
-    if (kept == 0) return 0;
-    combine(c, T, nt, kept, ld, C, T2, Cdev);
-    PDEP_HIP(hipMemcpyAsync(T, T2, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    return kept;
+    PDEP_HIP(hipStreamSynchronize(s));
+    return nt;
 }
 
 }  // namespace
@@ -277,6 +332,8 @@ void ground_state(Ctx& c) {
             if (j < want) maxres = std::max(maxres, rn[j]);
             if (rn[j] > tol) unconv.push_back(j);
         }
+        if (verbose() && (it % 10 == 1))
+            fprintf(stderr, "[pdep] ground state it %d: subspace %d, max residual %.2e\n", it, m, maxres), fflush(stderr);
         if (maxres <= tol) { conv = true; break; }
         // expansion vectors: preconditioned residuals of unconverged pairs
         const int nt = (int)unconv.size();
@@ -394,6 +451,9 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
             if (j < npdep) maxres = std::max(maxres, rj);
             if (rj > eo.tol) unconv.push_back(j);
         }
+        if (verbose())
+            fprintf(stderr, "[pdep] PDEP it %d: subspace %d, max residual %.2e, lambda_0 %.10f\n", it, m, maxres,
+                    theta[0]), fflush(stderr);
         if (maxres <= eo.tol) { res.converged = true; break; }
         if (it == eo.maxit) break;
         const int nt = (int)unconv.size();

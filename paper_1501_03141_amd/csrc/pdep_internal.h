@@ -68,6 +68,11 @@ class Buf {
     Allocator* al_ = nullptr;
 };
 
+// ---------------------------------------------------------------- logging --------
+// Progress lines on stderr when the environment variable PDEP_VERBOSE is set (long
+// solves report each refinement step / eigensolver iteration).
+bool verbose();
+
 // ---------------------------------------------------------------- profiling ------
 // Kernel classes timed by the opt-in profiler (prof.hip; see pdep_profile_enable).
 enum KernelId : int {

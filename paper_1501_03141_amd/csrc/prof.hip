@@ -2,6 +2,7 @@
 // pair of HIP events recorded on the launch stream.  Durations are resolved when the
 // totals are read (after the caller synchronised), so timing adds two event records
 // per launch and no synchronisation.
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -88,6 +89,11 @@ ProfScope::~ProfScope() {
         return;
     }
     p.pending.push_back({kid_, a_, b_, bytes_, flops_});
+}
+
+bool verbose() {
+    static const bool v = std::getenv("PDEP_VERBOSE") != nullptr;
+    return v;
 }
 
 }  // namespace pdep

@@ -25,6 +25,7 @@
 // 1/max(1, 1/2|G|^2 - e_v) (the paper does not fix K; it only changes iteration counts).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "pdep_internal.h"
 
@@ -247,11 +248,18 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         launch_row_dots<double>(na, npw, qa, ld, qa, ld, sc.rr, nullptr, s);
         PDEP_HIP(hipMemcpyAsync(dots.data(), sc.rr, na * sizeof(double), hipMemcpyDeviceToHost, s));
         PDEP_HIP(hipStreamSynchronize(s));
+        int itmax = 0;
+        double worst = 0.0;
         for (int j = 0; j < na; ++j) {
             rr[rows[j]] = dots[j];
             it_row[rows[j]] += its[j];
+            itmax = std::max(itmax, its[j]);
+            worst = std::max(worst, std::sqrt(dots[j] / bb[rows[j]]));
         }
         st.refine_steps = std::max(st.refine_steps, step + 1);
+        if (verbose())
+            fprintf(stderr, "[pdep] refinement step %d: %d systems, inner CG %d iterations, worst FP64 residual %.2e\n",
+                    step + 1, na, itmax, worst), fflush(stderr);
     }
     for (int i = 0; i < n; ++i) {
         st.cg_iter_total += it_row[i];
