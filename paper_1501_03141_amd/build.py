@@ -22,7 +22,7 @@ ARCH = "gfx950"
 SOURCES = ["basis.hip", "fft.hip", "linalg.hip", "solver.hip", "davidson.hip", "capi.hip", "prof.hip"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     f"-I{ROCM}/include",

@@ -2,8 +2,8 @@
 //
 // The basis is every G = 2 pi (mx/Lx, my/Ly, mz/Lz) with 1/2 |G|^2 <= ecut (the
 // plane-wave expansion of Sec. 2.1), enumerated lexicographically in (mx, my, mz).
-// Because mx is the slowest index, the sphere is naturally stored plane by plane,
-// which is what the plane passes of the transforms read and write.
+// Because mz is the fastest index, every (mx, my) z-stick of the sphere is a
+// contiguous run, which is what the stick passes of the transforms read and write.
 #include <cmath>
 
 #include "pdep_internal.h"
@@ -116,18 +116,23 @@ void build_basis(const pdep_cell& cell, Basis& b) {
     PDEP_REQUIRE(b.g0 >= 0 && b.npw >= 2, PDEP_EINVAL, "cutoff too small");
     b.mxmax = mabs[0];
     b.ax = 2 * b.mxmax + 1;
-    b.plane_start.assign(b.ax + 1, 0);
-    b.stick_k.assign(b.ax, 0);
-    b.lds_idx.resize(b.npw);
+    // z-sticks: maximal runs of equal (mx, my) in the lexicographic order
+    b.stick_start.clear();
+    b.slab_pos.clear();
+    b.stick_pos.resize(b.npw);
     for (int k = 0; k < b.npw; ++k) {
-        const int a = b.miller[3 * k] + b.mxmax;
-        b.plane_start[a + 1] = k + 1;
-        b.stick_k[a] = std::max(b.stick_k[a], std::abs(b.miller[3 * k + 1]));
-        const int iy = ((b.miller[3 * k + 1] % b.n[1]) + b.n[1]) % b.n[1];
-        const int iz = ((b.miller[3 * k + 2] % b.n[2]) + b.n[2]) % b.n[2];
-        b.lds_idx[k] = iy * b.n[2] + iz;
+        const int mx = b.miller[3 * k], my = b.miller[3 * k + 1], mz = b.miller[3 * k + 2];
+        if (k == 0 || mx != b.miller[3 * (k - 1)] || my != b.miller[3 * (k - 1) + 1]) {
+            b.stick_start.push_back(k);
+            const int ix = ((mx % b.n[0]) + b.n[0]) % b.n[0];
+            const int iy = ((my % b.n[1]) + b.n[1]) % b.n[1];
+            b.slab_pos.push_back(ix * b.n[1] + iy);
+        }
+        const int s = (int)b.stick_start.size() - 1;
+        const int iz = ((mz % b.n[2]) + b.n[2]) % b.n[2];
+        b.stick_pos[k] = s * b.n[2] + iz;
     }
-    for (int a = 1; a <= b.ax; ++a) b.plane_start[a] = std::max(b.plane_start[a], b.plane_start[a - 1]);
+    b.stick_start.push_back(b.npw);
     FftDims& d = b.dims;
     d.nx = b.n[0];
     d.ny = b.n[1];
@@ -135,16 +140,11 @@ void build_basis(const pdep_cell& cell, Basis& b) {
     d.ax = b.ax;
     d.mxmax = b.mxmax;
     d.npw = b.npw;
+    d.ns = (int)b.slab_pos.size();
+    d.sld = (d.ns + 31) / 32 * 32;
     d.px = make_axis_plan(d.nx);
     d.py = make_axis_plan(d.ny);
     d.pz = make_axis_plan(d.nz);
-    // z chunk of the pencil kernels: the largest divisor of nz whose FP64 tile stays <= 40 KB
-    d.zc = 1;
-    for (int zc = d.nz; zc >= 1; --zc)
-        if (d.nz % zc == 0 && (size_t)d.nx * zc * 16 <= 40 * 1024 && d.nx * zc <= 256 * 24) {
-            d.zc = zc;
-            break;
-        }
 }
 
 void upload_basis(Basis& b, Allocator* al, hipStream_t s) {
@@ -152,9 +152,9 @@ void upload_basis(Basis& b, Allocator* al, hipStream_t s) {
         dst.ensure(al, bytes);
         PDEP_HIP(hipMemcpyAsync(dst.get(), src, bytes, hipMemcpyHostToDevice, s));
     };
-    up(b.d_plane_start, b.plane_start.data(), b.plane_start.size() * sizeof(int));
-    up(b.d_stick_k, b.stick_k.data(), b.stick_k.size() * sizeof(int));
-    up(b.d_lds_idx, b.lds_idx.data(), b.lds_idx.size() * sizeof(int));
+    up(b.d_stick_start, b.stick_start.data(), b.stick_start.size() * sizeof(int));
+    up(b.d_stick_pos, b.stick_pos.data(), b.stick_pos.size() * sizeof(int));
+    up(b.d_slab_pos, b.slab_pos.data(), b.slab_pos.size() * sizeof(int));
     up(b.d_kin64, b.kin.data(), b.kin.size() * sizeof(double));
     std::vector<float> k32(b.kin.begin(), b.kin.end());
     up(b.d_kin32, k32.data(), k32.size() * sizeof(float));
@@ -168,9 +168,9 @@ void upload_basis(Basis& b, Allocator* al, hipStream_t s) {
     up(b.d_tw32, tw32.data(), tw32.size() * sizeof(float));
     PDEP_HIP(hipStreamSynchronize(s));
     BasisTables& t = b.tables;
-    t.plane_start = b.d_plane_start.as<int>();
-    t.stick_k = b.d_stick_k.as<int>();
-    t.lds_idx = b.d_lds_idx.as<int>();
+    t.stick_start = b.d_stick_start.as<int>();
+    t.stick_pos = b.d_stick_pos.as<int>();
+    t.slab_pos = b.d_slab_pos.as<int>();
     const double* t64 = b.d_tw64.as<double>();
     const float* t32 = b.d_tw32.as<float>();
     t.twx64 = t64;

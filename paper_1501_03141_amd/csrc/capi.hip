@@ -60,10 +60,10 @@ void finish_setup(Ctx& c) {
     const int nv = c.nv, npw = b.npw;
     hipStream_t s = c.stream;
     c.u64.ensure(&c.al, (size_t)nv * b.ng * sizeof(double2));
-    double2* planes = static_cast<double2*>(c.ws(pdep::W_STAGE_PLANES, (size_t)nv * b.ax * b.dims.ny * b.dims.nz *
+    double2* sticks = static_cast<double2*>(c.ws(pdep::W_STAGE_PLANES, (size_t)nv * b.dims.nz * b.dims.sld *
                                                                            sizeof(double2)));
-    pdep::launch_sphere_to_planes<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nullptr, nv, nullptr, planes, s);
-    pdep::launch_pencil_inv_store<double>(b.dims, b.tables, planes, nv, c.u64.as<double2>(), nullptr, s);
+    pdep::launch_sphere_to_sticks<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nv, nullptr, sticks, s);
+    pdep::launch_slab_inv_store<double>(b.dims, b.tables, sticks, nv, c.u64.as<double2>(), nullptr, s);
     c.psi32.ensure(&c.al, (size_t)nv * npw * sizeof(float2));
     pdep::launch_convert_rows<double, float>(nv, npw, c.psi64.as<double2>(), npw, nullptr, nullptr,
                                              c.psi32.as<float2>(), npw, s);
@@ -72,7 +72,7 @@ void finish_setup(Ctx& c) {
     // residual of the orbitals in use
     const long ld = npw;
     double2* hx = static_cast<double2*>(c.ws(C_OUT, (size_t)nv * ld * sizeof(double2)));
-    pdep::apply_h64(c, c.psi64.as<double2>(), ld, nv, c.eps_dev.as<double>(), nv, hx, ld, planes);
+    pdep::apply_h64(c, c.psi64.as<double2>(), ld, nv, c.eps_dev.as<double>(), nv, hx, ld, sticks);
     double* dots = static_cast<double*>(c.ws(C_STAGE, (size_t)nv * sizeof(double)));
     pdep::launch_row_dots<double>(nv, npw, hx, ld, hx, ld, dots, nullptr, s);
     std::vector<double> r2(nv);
@@ -137,9 +137,15 @@ int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
     PDEP_HIP(hipGetDevice(&c.device));
     pdep::upload_basis(c.basis, &c.al, c.stream);
     c.nv = opts->n_v;
+    // the slab passes read V in z-major order [iz][ix][iy]
+    std::vector<double> vz((size_t)b.ng);
+    for (int ix = 0; ix < b.n[0]; ++ix)
+        for (int iy = 0; iy < b.n[1]; ++iy)
+            for (int iz = 0; iz < b.n[2]; ++iz)
+                vz[((size_t)iz * b.n[0] + ix) * b.n[1] + iy] = vloc[((size_t)ix * b.n[1] + iy) * b.n[2] + iz];
     c.vloc64.ensure(&c.al, (size_t)b.ng * sizeof(double));
-    PDEP_HIP(hipMemcpyAsync(c.vloc64.get(), vloc, (size_t)b.ng * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    std::vector<float> v32(vloc, vloc + b.ng);
+    PDEP_HIP(hipMemcpyAsync(c.vloc64.get(), vz.data(), (size_t)b.ng * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    std::vector<float> v32(vz.begin(), vz.end());
     c.vloc32.ensure(&c.al, (size_t)b.ng * sizeof(float));
     PDEP_HIP(hipMemcpyAsync(c.vloc32.get(), v32.data(), (size_t)b.ng * sizeof(float), hipMemcpyHostToDevice, c.stream));
     PDEP_HIP(hipStreamSynchronize(c.stream));
@@ -268,18 +274,27 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
     const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
     hipStream_t s = c.stream;
     Timer tm(s);
-    const double* dv = dv_r;
-    double* dn = dn_r;
+    const pdep::Basis& b = c.basis;
+    const size_t bytes = (size_t)n_pert * ng * sizeof(double);
+    // grids cross the ABI in C order and are z-major inside
+    double* stage = static_cast<double*>(c.ws(C_STAGE, bytes));
+    double* dvz = static_cast<double*>(c.ws(C_IN, bytes));
+    double* dnz = static_cast<double*>(c.ws(C_OUT, bytes));
+    const double* dv_dev = dv_r;
     if (!dev) {
         PDEP_REQUIRE(all_finite(dv_r, (size_t)n_pert * ng), PDEP_EINVAL, "dv contains NaN or Inf");
-        double* in_d = static_cast<double*>(c.ws(C_IN, (size_t)n_pert * ng * sizeof(double)));
-        PDEP_HIP(hipMemcpyAsync(in_d, dv_r, (size_t)n_pert * ng * sizeof(double), hipMemcpyHostToDevice, s));
-        dv = in_d;
-        dn = static_cast<double*>(c.ws(C_OUT, (size_t)n_pert * ng * sizeof(double)));
+        PDEP_HIP(hipMemcpyAsync(stage, dv_r, bytes, hipMemcpyHostToDevice, s));
+        dv_dev = stage;
     }
+    pdep::launch_transpose_grid(b.n[0], b.n[1], b.n[2], n_pert, dv_dev, dvz, true, s);
     pdep::ApplyStats as;
-    pdep::chi0_grid(c, n_pert, dv, dn, as);
-    if (!dev) PDEP_HIP(hipMemcpyAsync(dn_r, dn, (size_t)n_pert * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+    pdep::chi0_grid(c, n_pert, dvz, dnz, as);
+    if (dev) {
+        pdep::launch_transpose_grid(b.n[0], b.n[1], b.n[2], n_pert, dnz, dn_r, false, s);
+    } else {
+        pdep::launch_transpose_grid(b.n[0], b.n[1], b.n[2], n_pert, dnz, stage, false, s);
+        PDEP_HIP(hipMemcpyAsync(dn_r, stage, bytes, hipMemcpyDeviceToHost, s));
+    }
     const double ms = tm.stop();
     if (st) {
         st->n_rhs = as.n_rhs;

@@ -283,8 +283,7 @@ void ground_state(Ctx& c) {
     double2* X = static_cast<double2*>(ws.get(D_X, (size_t)nb * ld * sizeof(double2)));
     double2* AX = static_cast<double2*>(ws.get(D_AX, (size_t)nb * ld * sizeof(double2)));
     double2* R = static_cast<double2*>(ws.get(D_R, (size_t)nb * ld * sizeof(double2)));
-    double2* planes = static_cast<double2*>(
-        c.ws(20, (size_t)mmax * b.ax * b.dims.ny * b.dims.nz * sizeof(double2)));
+    double2* sticks = static_cast<double2*>(c.ws(20, (size_t)mmax * b.dims.nz * b.dims.sld * sizeof(double2)));
     double* dtheta = static_cast<double*>(c.ws(21, (size_t)mmax * sizeof(double) * 2 + 64));
     double* dzero = dtheta + mmax;
     launch_fill_zero(dzero, (size_t)mmax * sizeof(double), s);
@@ -303,7 +302,7 @@ void ground_state(Ctx& c) {
         }
     PDEP_HIP(hipMemcpyAsync(V, h0.data(), h0.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     int m = orthonormalise(c, ws, sv, nullptr, 0, V, nb, ld, false);
-    apply_h64(c, V, ld, m, dzero, 1, AV, ld, planes);
+    apply_h64(c, V, ld, m, dzero, 1, AV, ld, sticks);
     const double tol = c.opts.gs_tol;
     std::vector<double> theta, rn(nb);
     int it = 0;
@@ -354,7 +353,7 @@ void ground_state(Ctx& c) {
         const int kept = orthonormalise(c, ws, sv, V, m, T, nt, ld, false);
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        apply_h64(c, V + (size_t)m * ld, ld, kept, dzero, 1, AV + (size_t)m * ld, ld, planes);
+        apply_h64(c, V + (size_t)m * ld, ld, kept, dzero, 1, AV + (size_t)m * ld, ld, sticks);
         m += kept;
     }
     PDEP_REQUIRE(conv, PDEP_ENOTCONV,

@@ -2,21 +2,26 @@
 //
 // A sphere vector (coefficients c_G, G in S) and a grid function are related by
 //   Inv(c)(r) = sum_G c_G exp(iG.r),   Fwd(f)(G) = N_g^-1 sum_r f(r) exp(-iG.r).
-// The 3D transform is split into three passes so that each pass keeps one 2D slab
-// or one set of pencils in LDS:
-//   plane pass  (one workgroup per (row, active x-plane)): z transforms of the
-//               non-empty sticks and y transforms of every z column, in LDS;
-//   pencil pass (one workgroup per (row, y, z-chunk)): x transforms of pencils, with
-//               the real-space work (multiply by V, density accumulation, products)
-//               fused between the inverse and the forward transform;
-//   plane pass back to the sphere with a fused epilogue (kinetic term and shift,
-//               scaling).
-// Only the 2 mx_max + 1 x-planes that intersect the sphere travel through HBM
-// between passes ("planes" buffer, layout [row][a][iy][iz]).  Each 1D transform is a
-// mixed-radix (2, 3, 4, 8) Stockham FFT executed by the whole workgroup: every stage
-// loads its butterfly inputs into registers, synchronises, and writes the outputs
-// back in place.  Twiddles come from a table exp(-2 pi i m / n) built in double
-// precision on the host and staged in LDS.
+// The sphere is a union of z-sticks: for each (mx, my) with at least one G in S, the
+// entries with that (mx, my) are contiguous in the lexicographic sphere order and
+// cover mz = -k..k.  The 3D transform is done in two kinds of passes:
+//   stick pass (one workgroup per (row, group of sticks)): the length-nz transforms
+//               of the non-empty sticks only, read from / written to the sphere with
+//               a fused epilogue on the way back (kinetic term and shift, scaling);
+//   slab pass  (one workgroup per (row, z)): the 2D (x, y) transform of one z slab in
+//               LDS -- y transforms of the non-empty x columns only, x transforms of
+//               every y row -- with the real-space work (multiply by V, products,
+//               density accumulation) fused between the inverse and forward halves.
+// Between passes only the stick values travel through HBM ("sticks" buffer, layout
+// [row][iz][stick], stick index fastest so that both passes move contiguous runs).
+// Real-space grids handed to or produced by the slab pass are z-major ([iz][ix][iy]).
+//
+// Each 1D transform is a mixed-radix (2, 3, 4, 8) Stockham FFT run by the whole
+// workgroup on lines held in LDS: every stage loads its butterfly inputs into
+// registers, synchronises, and writes the outputs back in place.  The common grid
+// sizes are compile-time template parameters (all index arithmetic is then by
+// constants); other sizes use the same code with run-time sizes.  Twiddles come from
+// tables exp(-2 pi i m / n) built in extended precision on the host.
 #include "pdep_internal.h"
 
 namespace pdep {
@@ -25,6 +30,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxElems = 24;   // register budget of one stage: items * radix <= 24
+
+// Sticks per stick-pass workgroup for a given nz: about 1.5k elements per workgroup.
+__host__ __device__ constexpr int sticks_per_group(int nz) {
+    return nz >= 96 ? 16 : (nz >= 48 ? 32 : (nz >= 24 ? 48 : 64));
+}
 
 template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
 // (generic over the vector type: cplx<T> is not deducible)
@@ -100,12 +110,35 @@ struct LineMap {
     }
 };
 
+// Radix plan as a compile-time value (make_axis_plan uses the same factorisation).
+struct CPlan {
+    int nst;
+    int rad[8];
+};
+constexpr CPlan cplan(int n) {
+    CPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    int m = n;
+    while (m % 3 == 0 && m > 1) { p.rad[p.nst++] = 3; m /= 3; }
+    int twos = 0;
+    while (m % 2 == 0 && m > 1) { ++twos; m /= 2; }
+    if (twos % 2 == 1 && twos >= 3) { p.rad[p.nst++] = 8; twos -= 3; }
+    while (twos >= 2) { p.rad[p.nst++] = 4; twos -= 2; }
+    if (twos == 1) p.rad[p.nst++] = 2;
+    return p;
+}
+
 // One Stockham stage over `nlines` lines of length N in LDS (element stride es).
-// Ns = product of the radices of the previous stages.
-template <typename T, int R, int SIGN>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int N, int Ns, int nlines, LineMap lm, int es,
-                                          const cplx<T>* tw, bool line_fast) {
-    constexpr int MAXI = kMaxElems / R;
+// Ns = product of the radices of the previous stages.  Template arguments that are 0
+// are taken from the run-time arguments.  LF: consecutive threads take consecutive
+// lines (for lines that are adjacent in LDS) instead of consecutive butterflies.
+template <typename T, int R, int SIGN, int N_, int NS_, int NL_, bool LF>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int n_rt, int ns_rt, int nl_rt, LineMap lm, int es,
+                                          const cplx<T>* tw) {
+    constexpr int MAXI_CT = (N_ > 0 && NL_ > 0) ? (NL_ * (N_ / R) + kThreads - 1) / kThreads : kMaxElems / R;
+    constexpr int MAXI = MAXI_CT < kMaxElems / R ? MAXI_CT : kMaxElems / R;
+    const int N = N_ ? N_ : n_rt;
+    const int Ns = N_ ? NS_ : ns_rt;
+    const int nlines = NL_ ? NL_ : nl_rt;
     const int nb = N / R;
     const int total = nlines * nb;
     const int stride = N / (Ns * R);
@@ -118,7 +151,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int N, int Ns, int nline
         ob[it] = -1;
         if (item < total) {
             int line, j;
-            if (line_fast) { line = item % nlines; j = item / nlines; }
+            if (LF) { line = item % nlines; j = item / nlines; }
             else { j = item % nb; line = item / nb; }
             const int base = lm.base(line);
             const int jm = j % Ns;
@@ -147,17 +180,32 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int N, int Ns, int nline
     __syncthreads();
 }
 
-template <typename T, int SIGN>
-__device__ void fft_lines(cplx<T>* buf, const AxisPlan& p, int nlines, LineMap lm, int es,
-                          const cplx<T>* tw, bool line_fast) {
-    int Ns = 1;
-    for (int s = 0; s < p.nst; ++s) {
-        const int R = p.rad[s];
-        if (R == 4) fft_stage<T, 4, SIGN>(buf, p.n, Ns, nlines, lm, es, tw, line_fast);
-        else if (R == 8) fft_stage<T, 8, SIGN>(buf, p.n, Ns, nlines, lm, es, tw, line_fast);
-        else if (R == 3) fft_stage<T, 3, SIGN>(buf, p.n, Ns, nlines, lm, es, tw, line_fast);
-        else fft_stage<T, 2, SIGN>(buf, p.n, Ns, nlines, lm, es, tw, line_fast);
-        Ns *= R;
+template <typename T, int SIGN, int N, int NL, bool LF, int S, int NS>
+__device__ __forceinline__ void fft_ct(cplx<T>* buf, int nl_rt, LineMap lm, int es, const cplx<T>* tw) {
+    constexpr CPlan P = cplan(N);
+    if constexpr (S < P.nst) {
+        constexpr int R = P.rad[S];
+        fft_stage<T, R, SIGN, N, NS, NL, LF>(buf, N, NS, nl_rt, lm, es, tw);
+        fft_ct<T, SIGN, N, NL, LF, S + 1, NS * R>(buf, nl_rt, lm, es, tw);
+    }
+}
+
+// All stages of a length-N transform over nlines lines.  N == 0: run-time plan p.
+template <typename T, int SIGN, int N, int NL, bool LF>
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, const AxisPlan& p, int nlines, LineMap lm, int es,
+                                          const cplx<T>* tw) {
+    if constexpr (N > 0) {
+        fft_ct<T, SIGN, N, NL, LF, 0, 1>(buf, nlines, lm, es, tw);
+    } else {
+        int Ns = 1;
+        for (int s = 0; s < p.nst; ++s) {
+            const int R = p.rad[s];
+            if (R == 4) fft_stage<T, 4, SIGN, 0, 0, NL, LF>(buf, p.n, Ns, nlines, lm, es, tw);
+            else if (R == 8) fft_stage<T, 8, SIGN, 0, 0, NL, LF>(buf, p.n, Ns, nlines, lm, es, tw);
+            else if (R == 3) fft_stage<T, 3, SIGN, 0, 0, NL, LF>(buf, p.n, Ns, nlines, lm, es, tw);
+            else fft_stage<T, 2, SIGN, 0, 0, NL, LF>(buf, p.n, Ns, nlines, lm, es, tw);
+            Ns *= R;
+        }
     }
 }
 
@@ -175,29 +223,30 @@ __device__ __forceinline__ void load_tw(cplx<T>* dst, const BasisTables& t, int 
     for (int e = threadIdx.x; e < n; e += kThreads) dst[e] = mk<T>(src[2 * e], src[2 * e + 1]);
 }
 
-// ------------------------------------------------------------------ plane passes ---
+// ------------------------------------------------------------------ stick passes ---
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_sphere_to_planes(FftDims d, BasisTables t,
+// sphere rows -> sticks (inverse z transforms).  gscale (per G, may be null)
+// multiplies the coefficients while scattering.
+template <typename T, int NZ_>
+__global__ __launch_bounds__(kThreads) void k_sphere_to_sticks(FftDims d, BasisTables t,
                                                                const cplx<T>* __restrict__ in, long ld_in,
-                                                               const int* __restrict__ rows,
                                                                const double* __restrict__ gscale,
-                                                               cplx<T>* __restrict__ planes) {
+                                                               cplx<T>* __restrict__ sticks) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = cplx<T>;
-    const int psz = d.ny * d.nz;
+    const int NZ = NZ_ ? NZ_ : d.nz;
+    const int SG = sticks_per_group(NZ);
     C* buf = reinterpret_cast<C*>(smem);
-    C* twy = buf + psz;
-    C* twz = twy + d.ny;
-    const int a = blockIdx.x;
+    C* twz = buf + SG * NZ;
+    const int s0 = blockIdx.x * SG;
+    const int ns_here = min(SG, d.ns - s0);
     const int row = blockIdx.y;
-    const int src_row = rows ? rows[row] : row;
-    for (int e = threadIdx.x; e < psz; e += kThreads) buf[e] = mk<T>(0, 0);
-    load_tw<T>(twy, t, 1, d.ny);
-    load_tw<T>(twz, t, 2, d.nz);
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) buf[e] = mk<T>(0, 0);
+    load_tw<T>(twz, t, 2, NZ);
     __syncthreads();
-    const int k0 = t.plane_start[a], k1 = t.plane_start[a + 1];
-    const C* src = in + (long)src_row * ld_in;
+    const int k0 = t.stick_start[s0], k1 = t.stick_start[s0 + ns_here];
+    const C* src = in + (long)row * ld_in;
+    const int off = s0 * NZ;
     for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
         C v = src[k];
         if (gscale) {
@@ -205,224 +254,238 @@ __global__ __launch_bounds__(kThreads) void k_sphere_to_planes(FftDims d, BasisT
             v.x *= g;
             v.y *= g;
         }
-        buf[t.lds_idx[k]] = v;
+        buf[t.stick_pos[k] - off] = v;
     }
     __syncthreads();
-    const int kk = t.stick_k[a];
-    fft_lines<T, +1>(buf, d.pz, 2 * kk + 1, LineMap{(d.ny - kk) % d.ny, d.ny, d.nz}, 1, twz, false);
-    fft_lines<T, +1>(buf, d.py, d.nz, LineMap{0, d.nz, 1}, d.nz, twy, true);
-    C* dst = planes + ((long)row * d.ax + a) * psz;
-    for (int e = threadIdx.x; e < psz; e += kThreads) dst[e] = buf[e];
+    fft_lines<T, +1, NZ_, 0, false>(buf, d.pz, ns_here, LineMap{0, SG, NZ}, 1, twz);
+    C* dst = sticks + (long)row * NZ * d.sld + s0;
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) {
+        const int sl = e % SG, z = e / SG;
+        if (sl < ns_here) dst[(long)z * d.sld + sl] = buf[sl * NZ + z];
+    }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_planes_to_sphere(
-    FftDims d, BasisTables t, const cplx<T>* __restrict__ planes, const int* __restrict__ rows,
-    cplx<T>* __restrict__ out, long ld_out, int epi, double alpha, const cplx<T>* __restrict__ x, long ld_x,
-    const T* __restrict__ kin, const double* __restrict__ shift, int nshift, const double* __restrict__ gscale) {
+// sticks -> sphere rows (forward z transforms, 1/N_g) with an epilogue.
+template <typename T, int NZ_>
+__global__ __launch_bounds__(kThreads) void k_sticks_to_sphere(
+    FftDims d, BasisTables t, const cplx<T>* __restrict__ sticks, cplx<T>* __restrict__ out, long ld_out, int epi,
+    double alpha, const cplx<T>* __restrict__ x, long ld_x, const T* __restrict__ kin,
+    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = cplx<T>;
-    const int psz = d.ny * d.nz;
+    const int NZ = NZ_ ? NZ_ : d.nz;
+    const int SG = sticks_per_group(NZ);
     C* buf = reinterpret_cast<C*>(smem);
-    C* twy = buf + psz;
-    C* twz = twy + d.ny;
-    const int a = blockIdx.x;
+    C* twz = buf + SG * NZ;
+    const int s0 = blockIdx.x * SG;
+    const int ns_here = min(SG, d.ns - s0);
     const int row = blockIdx.y;
-    const C* src = planes + ((long)row * d.ax + a) * psz;
-    for (int e = threadIdx.x; e < psz; e += kThreads) buf[e] = src[e];
-    load_tw<T>(twy, t, 1, d.ny);
-    load_tw<T>(twz, t, 2, d.nz);
+    const C* src = sticks + (long)row * NZ * d.sld + s0;
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) {
+        const int sl = e % SG, z = e / SG;
+        if (sl < ns_here) buf[sl * NZ + z] = src[(long)z * d.sld + sl];
+    }
+    load_tw<T>(twz, t, 2, NZ);
     __syncthreads();
-    fft_lines<T, -1>(buf, d.py, d.nz, LineMap{0, d.nz, 1}, d.nz, twy, true);
-    const int kk = t.stick_k[a];
-    fft_lines<T, -1>(buf, d.pz, 2 * kk + 1, LineMap{(d.ny - kk) % d.ny, d.ny, d.nz}, 1, twz, false);
-    const int orow = rows ? rows[row] : row;
-    const int k0 = t.plane_start[a], k1 = t.plane_start[a + 1];
+    fft_lines<T, -1, NZ_, 0, false>(buf, d.pz, ns_here, LineMap{0, SG, NZ}, 1, twz);
+    const int k0 = t.stick_start[s0], k1 = t.stick_start[s0 + ns_here];
+    const int off = s0 * NZ;
     const T inv_ng = T(1.0 / ((double)d.nx * d.ny * d.nz));
-    C* o = out + (long)orow * ld_out;
+    C* o = out + (long)row * ld_out;
     if (epi == EPI_SHIFTED_H) {
-        const T sh = (T)shift[orow % nshift];
-        const C* xr = x + (long)orow * ld_x;
+        const T sh = (T)shift[row % nshift];
+        const C* xr = x + (long)row * ld_x;
         for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
-            const C f = buf[t.lds_idx[k]];
+            const C f = buf[t.stick_pos[k] - off];
             const C xv = xr[k];
             const T dk = kin[k] - sh;
             o[k] = mk<T>(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
         }
     } else if (epi == EPI_GSCALE) {
         for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
-            const C f = buf[t.lds_idx[k]];
+            const C f = buf[t.stick_pos[k] - off];
             const T g = (T)gscale[k] * inv_ng;
             o[k] = mk<T>(f.x * g, f.y * g);
         }
     } else {
-        const T s = (T)alpha * inv_ng;
+        const T sc = (T)alpha * inv_ng;
         for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
-            const C f = buf[t.lds_idx[k]];
-            o[k] = mk<T>(f.x * s, f.y * s);
+            const C f = buf[t.stick_pos[k] - off];
+            o[k] = mk<T>(f.x * sc, f.y * sc);
         }
     }
 }
 
-// ------------------------------------------------------------------ pencil passes --
-// A workgroup owns the x pencils of one (row, iy, z-chunk): an nx x zc tile in LDS with
-// element (ix, z) at ix * zc + z.
+// ------------------------------------------------------------------- slab passes ---
+// A workgroup owns one z slab of one row: an nx x ny tile in LDS, element (ix, iy) at
+// ix * ny + iy.  The non-empty x columns are ix = mx mod nx for |mx| <= mxmax.
+
+template <typename T, int NX_, int NY_>
+__device__ __forceinline__ void slab_inverse(cplx<T>* buf, const FftDims& d, const cplx<T>* twx, const cplx<T>* twy) {
+    const int NX = NX_ ? NX_ : d.nx;
+    const int NY = NY_ ? NY_ : d.ny;
+    // y transforms of the non-empty columns (contiguous lines of length NY)
+    fft_lines<T, +1, NY_, 0, false>(buf, d.py, d.ax, LineMap{(NX - d.mxmax) % NX, NX, NY}, 1, twy);
+    // x transforms of every row iy (lines adjacent in LDS, element stride NY)
+    fft_lines<T, +1, NX_, NY_, true>(buf, d.px, NY, LineMap{0, NY, 1}, NY, twx);
+}
+
+template <typename T, int NX_, int NY_>
+__device__ __forceinline__ void slab_forward(cplx<T>* buf, const FftDims& d, const cplx<T>* twx, const cplx<T>* twy) {
+    const int NX = NX_ ? NX_ : d.nx;
+    const int NY = NY_ ? NY_ : d.ny;
+    fft_lines<T, -1, NX_, NY_, true>(buf, d.px, NY, LineMap{0, NY, 1}, NY, twx);
+    fft_lines<T, -1, NY_, 0, false>(buf, d.py, d.ax, LineMap{(NX - d.mxmax) % NX, NX, NY}, 1, twy);
+}
 
 template <typename T>
-__device__ __forceinline__ void load_active_rows(cplx<T>* buf, const FftDims& d, const cplx<T>* planes_row,
-                                                 int iy, int z0) {
-    const int zc = d.zc;
-    for (int e = threadIdx.x; e < d.nx * zc; e += kThreads) buf[e] = mk<T>(0, 0);
+__device__ __forceinline__ void slab_scatter(cplx<T>* buf, int nxy, const BasisTables& t, int ns,
+                                             const cplx<T>* src) {
+    for (int e = threadIdx.x; e < nxy; e += kThreads) buf[e] = mk<T>(0, 0);
     __syncthreads();
-    for (int e = threadIdx.x; e < d.ax * zc; e += kThreads) {
-        const int a = e / zc, z = e - (e / zc) * zc;
-        int ix = a - d.mxmax;
-        if (ix < 0) ix += d.nx;
-        buf[ix * zc + z] = planes_row[((long)a * d.ny + iy) * d.nz + z0 + z];
-    }
+    for (int s = threadIdx.x; s < ns; s += kThreads) buf[t.slab_pos[s]] = src[s];
     __syncthreads();
 }
 
 template <typename T>
-__device__ __forceinline__ void store_active_rows(const cplx<T>* buf, const FftDims& d, cplx<T>* planes_row,
-                                                  int iy, int z0) {
-    const int zc = d.zc;
-    for (int e = threadIdx.x; e < d.ax * zc; e += kThreads) {
-        const int a = e / zc, z = e - (e / zc) * zc;
-        int ix = a - d.mxmax;
-        if (ix < 0) ix += d.nx;
-        planes_row[((long)a * d.ny + iy) * d.nz + z0 + z] = buf[ix * zc + z];
-    }
+__device__ __forceinline__ void slab_gather(const cplx<T>* buf, const BasisTables& t, int ns, cplx<T>* dst) {
+    for (int s = threadIdx.x; s < ns; s += kThreads) dst[s] = buf[t.slab_pos[s]];
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pencil_hv(FftDims d, BasisTables t, cplx<T>* __restrict__ planes,
-                                                        const T* __restrict__ V, long v_stride,
-                                                        const int* __restrict__ vsel) {
+enum SlabMode : int { SLAB_HV = 0, SLAB_INV_C, SLAB_INV_R, SLAB_FWD_PRODUCT, SLAB_FWD_REAL };
+
+// One kernel for the slab work of every operation (MODE is a template argument):
+//   SLAB_HV          sticks -> inverse -> * V(z, x, y) -> forward -> sticks (in place)
+//   SLAB_INV_C / _R  sticks -> inverse -> complex / real grid [row][z][x][y]
+//   SLAB_FWD_PRODUCT grid Vr[row / nv] * u[row % nv] -> forward -> sticks
+//   SLAB_FWD_REAL    real grid Vr[row] -> forward -> sticks
+template <typename T, int NX_, int NY_, int MODE>
+__global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cplx<T>* __restrict__ sticks,
+                                                   const T* __restrict__ Vr, const cplx<T>* __restrict__ u,
+                                                   int nv, cplx<T>* __restrict__ grid_c, T* __restrict__ grid_r) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = cplx<T>;
+    const int NX = NX_ ? NX_ : d.nx;
+    const int NY = NY_ ? NY_ : d.ny;
+    const int nxy = NX * NY;
     C* buf = reinterpret_cast<C*>(smem);
-    C* twx = buf + d.nx * d.zc;
-    const int nzc = d.nz / d.zc;
-    const int iy = blockIdx.x / nzc, z0 = (blockIdx.x - iy * nzc) * d.zc;
+    C* twx = buf + nxy;
+    C* twy = twx + NX;
+    const int z = blockIdx.x;
     const int row = blockIdx.y;
-    load_tw<T>(twx, t, 0, d.nx);
-    C* prow = planes + (long)row * d.ax * d.ny * d.nz;
-    load_active_rows<T>(buf, d, prow, iy, z0);
-    fft_lines<T, +1>(buf, d.px, d.zc, LineMap{0, d.zc, 1}, d.zc, twx, true);
-    const T* Vr = V + (vsel ? (long)vsel[row] * v_stride : 0);
-    for (int e = threadIdx.x; e < d.nx * d.zc; e += kThreads) {
-        const int ix = e / d.zc, z = e - (e / d.zc) * d.zc;
-        const T vv = Vr[((long)ix * d.ny + iy) * d.nz + z0 + z];
-        buf[e].x *= vv;
-        buf[e].y *= vv;
-    }
-    __syncthreads();
-    fft_lines<T, -1>(buf, d.px, d.zc, LineMap{0, d.zc, 1}, d.zc, twx, true);
-    store_active_rows<T>(buf, d, prow, iy, z0);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pencil_inv_store(FftDims d, BasisTables t,
-                                                               const cplx<T>* __restrict__ planes,
-                                                               cplx<T>* __restrict__ grid_c, T* __restrict__ grid_r) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    using C = cplx<T>;
-    C* buf = reinterpret_cast<C*>(smem);
-    C* twx = buf + d.nx * d.zc;
-    const int nzc = d.nz / d.zc;
-    const int iy = blockIdx.x / nzc, z0 = (blockIdx.x - iy * nzc) * d.zc;
-    const int row = blockIdx.y;
-    const long ng = (long)d.nx * d.ny * d.nz;
-    load_tw<T>(twx, t, 0, d.nx);
-    load_active_rows<T>(buf, d, planes + (long)row * d.ax * d.ny * d.nz, iy, z0);
-    fft_lines<T, +1>(buf, d.px, d.zc, LineMap{0, d.zc, 1}, d.zc, twx, true);
-    for (int e = threadIdx.x; e < d.nx * d.zc; e += kThreads) {
-        const int ix = e / d.zc, z = e - (e / d.zc) * d.zc;
-        const long g = ((long)ix * d.ny + iy) * d.nz + z0 + z;
-        if (grid_c) grid_c[row * ng + g] = buf[e];
-        else grid_r[row * ng + g] = buf[e].x;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pencil_fwd_product(FftDims d, BasisTables t, const T* __restrict__ Vr,
-                                                                 const cplx<T>* __restrict__ u, int nv,
-                                                                 cplx<T>* __restrict__ planes) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    using C = cplx<T>;
-    C* buf = reinterpret_cast<C*>(smem);
-    C* twx = buf + d.nx * d.zc;
-    const int nzc = d.nz / d.zc;
-    const int iy = blockIdx.x / nzc, z0 = (blockIdx.x - iy * nzc) * d.zc;
-    const int row = blockIdx.y;
-    const long ng = (long)d.nx * d.ny * d.nz;
-    load_tw<T>(twx, t, 0, d.nx);
-    const T* vrow = Vr + (u ? (long)(row / nv) : (long)row) * ng;
-    const C* urow = u ? u + (long)(row % nv) * ng : nullptr;
-    for (int e = threadIdx.x; e < d.nx * d.zc; e += kThreads) {
-        const int ix = e / d.zc, z = e - (e / d.zc) * d.zc;
-        const long g = ((long)ix * d.ny + iy) * d.nz + z0 + z;
-        const T vv = vrow[g];
-        if (urow) {
-            const C uu = urow[g];
-            buf[e] = mk<T>(vv * uu.x, vv * uu.y);
+    const long ng = (long)nxy * d.nz;
+    load_tw<T>(twx, t, 0, NX);
+    load_tw<T>(twy, t, 1, NY);
+    C* srow = sticks + ((long)row * d.nz + z) * d.sld;
+    if constexpr (MODE == SLAB_HV || MODE == SLAB_INV_C || MODE == SLAB_INV_R) {
+        slab_scatter<T>(buf, nxy, t, d.ns, srow);
+        slab_inverse<T, NX_, NY_>(buf, d, twx, twy);
+        if constexpr (MODE == SLAB_HV) {
+            const T* vz = Vr + (long)z * nxy;
+            for (int e = threadIdx.x; e < nxy; e += kThreads) {
+                const T vv = vz[e];
+                buf[e].x *= vv;
+                buf[e].y *= vv;
+            }
+            __syncthreads();
+            slab_forward<T, NX_, NY_>(buf, d, twx, twy);
+            slab_gather<T>(buf, t, d.ns, srow);
+        } else if constexpr (MODE == SLAB_INV_C) {
+            C* g = grid_c + row * ng + (long)z * nxy;
+            for (int e = threadIdx.x; e < nxy; e += kThreads) g[e] = buf[e];
         } else {
-            buf[e] = mk<T>(vv, 0);
+            T* g = grid_r + row * ng + (long)z * nxy;
+            for (int e = threadIdx.x; e < nxy; e += kThreads) g[e] = buf[e].x;
         }
+    } else {
+        const T* vz = Vr + (MODE == SLAB_FWD_PRODUCT ? (long)(row / nv) : (long)row) * ng + (long)z * nxy;
+        if constexpr (MODE == SLAB_FWD_PRODUCT) {
+            const C* uz = u + (long)(row % nv) * ng + (long)z * nxy;
+            for (int e = threadIdx.x; e < nxy; e += kThreads) {
+                const T vv = vz[e];
+                const C uu = uz[e];
+                buf[e] = mk<T>(vv * uu.x, vv * uu.y);
+            }
+        } else {
+            for (int e = threadIdx.x; e < nxy; e += kThreads) buf[e] = mk<T>(vz[e], 0);
+        }
+        __syncthreads();
+        slab_forward<T, NX_, NY_>(buf, d, twx, twy);
+        slab_gather<T>(buf, t, d.ns, srow);
     }
-    __syncthreads();
-    fft_lines<T, -1>(buf, d.px, d.zc, LineMap{0, d.zc, 1}, d.zc, twx, true);
-    store_active_rows<T>(buf, d, planes + (long)row * d.ax * d.ny * d.nz, iy, z0);
 }
 
 constexpr int kMaxAcc = 24;
 
-__global__ __launch_bounds__(kThreads) void k_pencil_density(FftDims d, BasisTables t,
-                                                             const double2* __restrict__ planes, int nv,
-                                                             const double2* __restrict__ u, double scale,
-                                                             double* __restrict__ dn) {
+// Density: dn_i(z, x, y) = scale * Re sum_v conj(u_v(z, x, y)) Inv(sticks[i * nv + v])(z, x, y).
+template <int NX_, int NY_>
+__global__ __launch_bounds__(kThreads) void k_slab_density(FftDims d, BasisTables t,
+                                                           const double2* __restrict__ sticks, int nv,
+                                                           const double2* __restrict__ u, double scale,
+                                                           double* __restrict__ dn) {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int NX = NX_ ? NX_ : d.nx;
+    const int NY = NY_ ? NY_ : d.ny;
+    const int nxy = NX * NY;
     double2* buf = reinterpret_cast<double2*>(smem);
-    double2* twx = buf + d.nx * d.zc;
-    const int nzc = d.nz / d.zc;
-    const int iy = blockIdx.x / nzc, z0 = (blockIdx.x - iy * nzc) * d.zc;
+    double2* twx = buf + nxy;
+    double2* twy = twx + NX;
+    const int z = blockIdx.x;
     const int pert = blockIdx.y;
-    const long ng = (long)d.nx * d.ny * d.nz;
-    const long plane_row = (long)d.ax * d.ny * d.nz;
-    load_tw<double>(twx, t, 0, d.nx);
+    const long ng = (long)nxy * d.nz;
+    load_tw<double>(twx, t, 0, NX);
+    load_tw<double>(twy, t, 1, NY);
     double acc[kMaxAcc];
 #pragma unroll
     for (int j = 0; j < kMaxAcc; ++j) acc[j] = 0.0;
-    const int nel = d.nx * d.zc;
     for (int v = 0; v < nv; ++v) {
-        load_active_rows<double>(buf, d, planes + ((long)pert * nv + v) * plane_row, iy, z0);
-        fft_lines<double, +1>(buf, d.px, d.zc, LineMap{0, d.zc, 1}, d.zc, twx, true);
-        const double2* uv = u + (long)v * ng;
+        const double2* srow = sticks + (((long)pert * nv + v) * d.nz + z) * d.sld;
+        slab_scatter<double>(buf, nxy, t, d.ns, srow);
+        slab_inverse<double, NX_, NY_>(buf, d, twx, twy);
+        const double2* uz = u + (long)v * ng + (long)z * nxy;
 #pragma unroll
         for (int j = 0; j < kMaxAcc; ++j) {
             const int e = threadIdx.x + j * kThreads;
-            if (e < nel) {
-                const int ix = e / d.zc, z = e - (e / d.zc) * d.zc;
-                const double2 uu = uv[((long)ix * d.ny + iy) * d.nz + z0 + z];
+            if (e < nxy) {
+                const double2 uu = uz[e];
                 const double2 f = buf[e];
                 acc[j] += uu.x * f.x + uu.y * f.y;     // Re(conj(u) f)
             }
         }
         __syncthreads();
     }
-    double* out = dn + (long)pert * ng;
+    double* out = dn + (long)pert * ng + (long)z * nxy;
 #pragma unroll
     for (int j = 0; j < kMaxAcc; ++j) {
         const int e = threadIdx.x + j * kThreads;
-        if (e < nel) {
-            const int ix = e / d.zc, z = e - (e / d.zc) * d.zc;
-            out[((long)ix * d.ny + iy) * d.nz + z0 + z] = scale * acc[j];
-        }
+        if (e < nxy) out[e] = scale * acc[j];
     }
 }
 
-// ------------------------------------------------------------------ host checks ----
+// Grid layout change between C order [ix][iy][iz] and z-major [iz][ix][iy]; g indexes
+// the output.
+__global__ void k_transpose_grid(int nx, int ny, int nz, const double* __restrict__ in, double* __restrict__ out,
+                                 int to_zmajor) {
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long ng = (long)nx * ny * nz;
+    if (g >= ng) return;
+    const int row = blockIdx.y;
+    long src;
+    if (to_zmajor) {
+        const int iz = (int)(g / ((long)nx * ny));
+        const int rem = (int)(g - (long)iz * nx * ny);
+        const int ix = rem / ny, iy = rem - (rem / ny) * ny;
+        src = ((long)ix * ny + iy) * nz + iz;
+    } else {
+        const int ix = (int)(g / ((long)ny * nz));
+        const int rem = (int)(g - (long)ix * ny * nz);
+        const int iy = rem / nz, iz = rem - (rem / nz) * nz;
+        src = ((long)iz * nx + ix) * ny + iy;
+    }
+    out[(long)row * ng + g] = in[(long)row * ng + src];
+}
+
+// ------------------------------------------------------------------ host side ------
 
 void check_stages(const AxisPlan& p, int nlines, const char* what) {
     int Ns = 1;
@@ -435,144 +498,173 @@ void check_stages(const AxisPlan& p, int nlines, const char* what) {
     }
     PDEP_REQUIRE(Ns == p.n, PDEP_EINVAL, "bad radix plan");
 }
-
-template <typename T> size_t plane_lds(const FftDims& d) {
-    return sizeof(cplx<T>) * ((size_t)d.ny * d.nz + d.ny + d.nz);
-}
-template <typename T> size_t pencil_lds(const FftDims& d) {
-    return sizeof(cplx<T>) * ((size_t)d.nx * d.zc + d.nx);
-}
-
-void check_plane(const FftDims& d, const BasisTables&) {
-    check_stages(d.pz, d.ny, "z sticks");
-    check_stages(d.py, d.nz, "y columns");
-}
-void check_pencil(const FftDims& d) { check_stages(d.px, d.zc, "x pencils"); }
 void check_rows(int nrows) { PDEP_REQUIRE(nrows <= 65535, PDEP_EINVAL, "too many rows for one transform launch"); }
+void check_sticks(const FftDims& d) { check_stages(d.pz, sticks_per_group(d.nz), "z sticks"); }
+void check_slab(const FftDims& d) {
+    check_stages(d.py, d.ax, "y columns");
+    check_stages(d.px, d.ny, "x rows");
+}
+
+template <typename T> size_t stick_lds(const FftDims& d) {
+    return sizeof(cplx<T>) * ((size_t)sticks_per_group(d.nz) * d.nz + d.nz);
+}
+template <typename T> size_t slab_lds(const FftDims& d) {
+    return sizeof(cplx<T>) * ((size_t)d.nx * d.ny + d.nx + d.ny);
+}
+dim3 stick_grid(const FftDims& d, int nrows) {
+    return dim3((d.ns + sticks_per_group(d.nz) - 1) / sticks_per_group(d.nz), nrows);
+}
+
+// Compile-time size dispatch: f.template operator()<N>() for the supported constant
+// sizes, N = 0 (run-time sizes) otherwise.
+template <typename F> void with_n(int n, F&& f) {
+    switch (n) {
+        case 16: f.template operator()<16>(); break;
+        case 24: f.template operator()<24>(); break;
+        case 32: f.template operator()<32>(); break;
+        case 48: f.template operator()<48>(); break;
+        case 64: f.template operator()<64>(); break;
+        case 96: f.template operator()<96>(); break;
+        default: f.template operator()<0>(); break;
+    }
+}
+template <typename F> void with_nxy(int nx, int ny, F&& f) {
+    if (nx != ny) { f.template operator()<0>(); return; }
+    with_n(nx, f);
+}
 
 }  // namespace
 
 AxisPlan make_axis_plan(int n) {
     AxisPlan p;
     p.n = n;
-    int m = n;
-    while (m % 3 == 0) { p.rad[p.nst++] = 3; m /= 3; }
-    int twos = 0;
-    while (m % 2 == 0) { ++twos; m /= 2; }
-    PDEP_REQUIRE(m == 1, PDEP_EINVAL, "grid sizes must be products of 2s and 3s");
-    if (twos % 2 == 1 && twos >= 3) { p.rad[p.nst++] = 8; twos -= 3; }
-    while (twos >= 2) { p.rad[p.nst++] = 4; twos -= 2; }
-    if (twos == 1) p.rad[p.nst++] = 2;
-    PDEP_REQUIRE(p.nst <= 8, PDEP_EINVAL, "radix plan too long");
+    const CPlan c = cplan(n);
+    int prod = 1;
+    for (int s = 0; s < c.nst; ++s) { p.rad[p.nst++] = c.rad[s]; prod *= c.rad[s]; }
+    PDEP_REQUIRE(prod == n && n > 1, PDEP_EINVAL, "grid sizes must be products of 2s and 3s");
     return p;
 }
 
 template <typename T>
-void launch_sphere_to_planes(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in,
-                             const int* rows, int nrows, const double* gscale, cplx<T>* planes, hipStream_t s) {
+void launch_sphere_to_sticks(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
+                             const double* gscale, cplx<T>* sticks, hipStream_t s) {
     if (nrows <= 0) return;
-    check_plane(d, t);
+    check_sticks(d);
     check_rows(nrows);
-    dim3 grid(d.ax, nrows);
-    const double pl_ = (double)d.ax * d.ny * d.nz * sizeof(cplx<T>);   // one row of planes
-    const double sp_ = (double)d.npw * sizeof(cplx<T>);                 // one sphere vector
-    ProfScope prof_(K_SPHERE_TO_PLANES, s, (double)nrows * (sp_ + pl_));
-    hipLaunchKernelGGL(k_sphere_to_planes<T>, grid, dim3(kThreads), plane_lds<T>(d), s, d, t, in, ld_in, rows,
-                       gscale, planes);
+    const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    ProfScope prof_(K_SPHERE_TO_STICKS, s, (double)nrows * (sp + sk));
+    with_n(d.nz, [&]<int NZ>() {
+        hipLaunchKernelGGL((k_sphere_to_sticks<T, NZ>), stick_grid(d, nrows), dim3(kThreads), stick_lds<T>(d), s, d, t,
+                           in, ld_in, gscale, sticks);
+    });
     PDEP_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_planes_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* planes, int nrows,
-                             const int* rows, cplx<T>* out, long ld_out, int epi, double alpha, const cplx<T>* x,
-                             long ld_x, const T* kin, const double* shift, int nshift, const double* gscale,
-                             hipStream_t s) {
+void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows, cplx<T>* out,
+                             long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x, const T* kin,
+                             const double* shift, int nshift, const double* gscale, hipStream_t s) {
     if (nrows <= 0) return;
-    check_plane(d, t);
+    check_sticks(d);
     check_rows(nrows);
-    dim3 grid(d.ax, nrows);
-    const double pl_ = (double)d.ax * d.ny * d.nz * sizeof(cplx<T>);   // one row of planes
-    const double sp_ = (double)d.npw * sizeof(cplx<T>);                 // one sphere vector
-    ProfScope prof_(K_PLANES_TO_SPHERE, s, (double)nrows * (pl_ + sp_ + (epi == EPI_SHIFTED_H ? sp_ : 0.0)));
-    hipLaunchKernelGGL(k_planes_to_sphere<T>, grid, dim3(kThreads), plane_lds<T>(d), s, d, t, planes, rows, out,
-                       ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, gscale);
+    const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    ProfScope prof_(K_STICKS_TO_SPHERE, s, (double)nrows * (sk + sp + (epi == EPI_SHIFTED_H ? sp : 0.0)));
+    with_n(d.nz, [&]<int NZ>() {
+        hipLaunchKernelGGL((k_sticks_to_sphere<T, NZ>), stick_grid(d, nrows), dim3(kThreads), stick_lds<T>(d), s, d,
+                           t, sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, gscale);
+    });
     PDEP_HIP(hipGetLastError());
+}
+
+namespace {
+
+template <typename T, int MODE>
+void launch_slab(const FftDims& d, const BasisTables& t, int nrows, cplx<T>* sticks, const T* Vr, const cplx<T>* u,
+                 int nv, cplx<T>* grid_c, T* grid_r, hipStream_t s, int kid, double bytes) {
+    if (nrows <= 0) return;
+    check_slab(d);
+    check_rows(nrows);
+    ProfScope prof_(kid, s, bytes);
+    with_nxy(d.nx, d.ny, [&]<int N>() {
+        hipLaunchKernelGGL((k_slab<T, N, N, MODE>), dim3(d.nz, nrows), dim3(kThreads), slab_lds<T>(d), s, d, t,
+                           sticks, Vr, u, nv > 0 ? nv : 1, grid_c, grid_r);
+    });
+    PDEP_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+template <typename T>
+void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s) {
+    const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    launch_slab<T, SLAB_HV>(d, t, nrows, sticks, Vz, nullptr, 1, nullptr, nullptr, s, K_SLAB_HV,
+                            (double)nrows * 2.0 * sk + (double)d.nx * d.ny * d.nz * sizeof(T));
 }
 
 template <typename T>
-void launch_pencil_hv(const FftDims& d, const BasisTables& t, cplx<T>* planes, int nrows, const T* V,
-                      long v_stride, const int* vsel, hipStream_t s) {
-    if (nrows <= 0) return;
-    check_pencil(d);
-    check_rows(nrows);
-    dim3 grid(d.ny * (d.nz / d.zc), nrows);
-    const double pl_ = (double)d.ax * d.ny * d.nz * sizeof(cplx<T>);   // one row of planes
-    const double sp_ = (double)d.npw * sizeof(cplx<T>);                 // one sphere vector
-    ProfScope prof_(K_PENCIL_HV, s, (double)nrows * 2.0 * pl_ + (double)d.nx * d.ny * d.nz * sizeof(T));
-    hipLaunchKernelGGL(k_pencil_hv<T>, grid, dim3(kThreads), pencil_lds<T>(d), s, d, t, planes, V, v_stride, vsel);
-    PDEP_HIP(hipGetLastError());
+void launch_slab_inv_store(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, cplx<T>* grid_c,
+                           T* grid_r, hipStream_t s) {
+    const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    const double g = (double)d.nx * d.ny * d.nz * (grid_c ? sizeof(cplx<T>) : sizeof(T));
+    if (grid_c)
+        launch_slab<T, SLAB_INV_C>(d, t, nrows, sticks, nullptr, nullptr, 1, grid_c, nullptr, s, K_SLAB_INV_STORE,
+                                   (double)nrows * (sk + g));
+    else
+        launch_slab<T, SLAB_INV_R>(d, t, nrows, sticks, nullptr, nullptr, 1, nullptr, grid_r, s, K_SLAB_INV_STORE,
+                                   (double)nrows * (sk + g));
 }
 
 template <typename T>
-void launch_pencil_inv_store(const FftDims& d, const BasisTables& t, const cplx<T>* planes, int nrows,
-                             cplx<T>* grid_c, T* grid_r, hipStream_t s) {
-    if (nrows <= 0) return;
-    check_pencil(d);
-    check_rows(nrows);
-    dim3 grid(d.ny * (d.nz / d.zc), nrows);
-    const double pl_ = (double)d.ax * d.ny * d.nz * sizeof(cplx<T>);   // one row of planes
-    const double sp_ = (double)d.npw * sizeof(cplx<T>);                 // one sphere vector
-    ProfScope prof_(K_PENCIL_INV_STORE, s,
-                    (double)nrows * (pl_ + (double)d.nx * d.ny * d.nz * (grid_c ? sizeof(cplx<T>) : sizeof(T))));
-    hipLaunchKernelGGL(k_pencil_inv_store<T>, grid, dim3(kThreads), pencil_lds<T>(d), s, d, t, planes, grid_c,
-                       grid_r);
-    PDEP_HIP(hipGetLastError());
+void launch_slab_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr, const cplx<T>* u, int nv, int nrows,
+                             cplx<T>* sticks, hipStream_t s) {
+    const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    const double g = (double)d.nx * d.ny * d.nz;
+    if (u)
+        launch_slab<T, SLAB_FWD_PRODUCT>(d, t, nrows, sticks, Vr, u, nv, nullptr, nullptr, s, K_SLAB_FWD_PRODUCT,
+                                         (double)nrows * (sk + g * sizeof(cplx<T>)) + g * sizeof(T) * (nrows / nv));
+    else
+        launch_slab<T, SLAB_FWD_REAL>(d, t, nrows, sticks, Vr, nullptr, 1, nullptr, nullptr, s, K_SLAB_FWD_PRODUCT,
+                                      (double)nrows * (sk + g * sizeof(T)));
 }
 
-template <typename T>
-void launch_pencil_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr, const cplx<T>* u, int nv,
-                               int nrows, cplx<T>* planes, hipStream_t s) {
-    if (nrows <= 0) return;
-    check_pencil(d);
-    check_rows(nrows);
-    dim3 grid(d.ny * (d.nz / d.zc), nrows);
-    const double pl_ = (double)d.ax * d.ny * d.nz * sizeof(cplx<T>);   // one row of planes
-    const double sp_ = (double)d.npw * sizeof(cplx<T>);                 // one sphere vector
-    const double g_ = (double)d.nx * d.ny * d.nz;
-    ProfScope prof_(K_PENCIL_FWD_PRODUCT, s,
-                    (double)nrows * (pl_ + g_ * (u ? sizeof(cplx<T>) : 0)) + g_ * sizeof(T) * (u ? nrows / nv : nrows));
-    hipLaunchKernelGGL(k_pencil_fwd_product<T>, grid, dim3(kThreads), pencil_lds<T>(d), s, d, t, Vr, u,
-                       nv > 0 ? nv : 1, planes);
-    PDEP_HIP(hipGetLastError());
-}
-
-void launch_pencil_density(const FftDims& d, const BasisTables& t, const double2* planes, int npert, int nv,
-                           const double2* u, double scale, double* dn, hipStream_t s) {
+void launch_slab_density(const FftDims& d, const BasisTables& t, const double2* sticks, int npert, int nv,
+                         const double2* u, double scale, double* dn, hipStream_t s) {
     if (npert <= 0) return;
-    check_pencil(d);
-    PDEP_REQUIRE(d.nx * d.zc <= kThreads * kMaxAcc, PDEP_EINVAL, "density tile too large");
+    check_slab(d);
     check_rows(npert);
-    dim3 grid(d.ny * (d.nz / d.zc), npert);
-    const double g_ = (double)d.nx * d.ny * d.nz;
-    ProfScope prof_(K_PENCIL_DENSITY, s,
-                    (double)npert * nv * ((double)d.ax * d.ny * d.nz * 16.0 + g_ * 16.0) + (double)npert * g_ * 8.0);
-    hipLaunchKernelGGL(k_pencil_density, grid, dim3(kThreads), pencil_lds<double>(d), s, d, t, planes, nv, u, scale,
-                       dn);
+    PDEP_REQUIRE(d.nx * d.ny <= kThreads * kMaxAcc, PDEP_EINVAL, "density slab too large");
+    const double g = (double)d.nx * d.ny * d.nz;
+    ProfScope prof_(K_SLAB_DENSITY, s,
+                    (double)npert * nv * ((double)d.nz * d.ns * 16.0 + g * 16.0) + (double)npert * g * 8.0);
+    with_nxy(d.nx, d.ny, [&]<int N>() {
+        hipLaunchKernelGGL((k_slab_density<N, N>), dim3(d.nz, npert), dim3(kThreads), slab_lds<double>(d), s, d, t,
+                           sticks, nv, u, scale, dn);
+    });
     PDEP_HIP(hipGetLastError());
 }
 
-#define PDEP_INST_FFT(T)                                                                                       \
-    template void launch_sphere_to_planes<T>(const FftDims&, const BasisTables&, const cplx<T>*, long,         \
-                                             const int*, int, const double*, cplx<T>*, hipStream_t);           \
-    template void launch_planes_to_sphere<T>(const FftDims&, const BasisTables&, const cplx<T>*, int,          \
-                                             const int*, cplx<T>*, long, int, double, const cplx<T>*, long,     \
-                                             const T*, const double*, int, const double*, hipStream_t);         \
-    template void launch_pencil_hv<T>(const FftDims&, const BasisTables&, cplx<T>*, int, const T*, long,       \
-                                      const int*, hipStream_t);                                                \
-    template void launch_pencil_inv_store<T>(const FftDims&, const BasisTables&, const cplx<T>*, int,          \
-                                             cplx<T>*, T*, hipStream_t);                                        \
-    template void launch_pencil_fwd_product<T>(const FftDims&, const BasisTables&, const T*, const cplx<T>*,   \
-                                               int, int, cplx<T>*, hipStream_t);
+void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, double* out, bool to_zmajor,
+                           hipStream_t s) {
+    if (nrows <= 0) return;
+    check_rows(nrows);
+    const long ng = (long)nx * ny * nz;
+    ProfScope prof_(K_MISC, s, 16.0 * ng * nrows);
+    hipLaunchKernelGGL(k_transpose_grid, dim3((unsigned)((ng + 255) / 256), nrows), dim3(256), 0, s, nx, ny, nz, in,
+                       out, to_zmajor ? 1 : 0);
+    PDEP_HIP(hipGetLastError());
+}
+
+#define PDEP_INST_FFT(T)                                                                                          \
+    template void launch_sphere_to_sticks<T>(const FftDims&, const BasisTables&, const cplx<T>*, long, int,       \
+                                             const double*, cplx<T>*, hipStream_t);                               \
+    template void launch_sticks_to_sphere<T>(const FftDims&, const BasisTables&, const cplx<T>*, int, cplx<T>*,   \
+                                             long, int, double, const cplx<T>*, long, const T*, const double*,     \
+                                             int, const double*, hipStream_t);                                    \
+    template void launch_slab_hv<T>(const FftDims&, const BasisTables&, cplx<T>*, int, const T*, hipStream_t);    \
+    template void launch_slab_inv_store<T>(const FftDims&, const BasisTables&, cplx<T>*, int, cplx<T>*, T*,       \
+                                           hipStream_t);                                                          \
+    template void launch_slab_fwd_product<T>(const FftDims&, const BasisTables&, const T*, const cplx<T>*, int,   \
+                                             int, cplx<T>*, hipStream_t);
 
 PDEP_INST_FFT(double)
 PDEP_INST_FFT(float)

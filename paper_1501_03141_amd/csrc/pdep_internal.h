@@ -76,8 +76,8 @@ bool verbose();
 // ---------------------------------------------------------------- profiling ------
 // Kernel classes timed by the opt-in profiler (prof.hip; see pdep_profile_enable).
 enum KernelId : int {
-    K_SPHERE_TO_PLANES = 0, K_PENCIL_HV, K_PLANES_TO_SPHERE, K_PENCIL_INV_STORE, K_PENCIL_FWD_PRODUCT,
-    K_PENCIL_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_COUNT
+    K_SPHERE_TO_STICKS = 0, K_SLAB_HV, K_STICKS_TO_SPHERE, K_SLAB_INV_STORE, K_SLAB_FWD_PRODUCT,
+    K_SLAB_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_COUNT
 };
 // Records HIP events around the launch made during its lifetime (when profiling is on),
 // with the launch's algorithmic HBM bytes and flops.
@@ -104,62 +104,62 @@ struct AxisPlan {
 };
 
 // Everything a transform kernel needs to know about the grid and the sphere, passed
-// by value.  The sphere is stored plane by plane: plane a (0 <= a < ax) holds the G
-// with mx = a - mxmax, at offsets [plane_start[a], plane_start[a+1]); within a plane
-// the G with my = -k..k (k = stick_k[a]) form the z-sticks that can be non-zero.
+// by value.  The sphere is a union of ns z-sticks (one per (mx, my) that has a G in S),
+// each a contiguous run of the lexicographic sphere order.  The x columns that can be
+// non-empty in a z slab are mx = -mxmax..mxmax (ax of them).
 struct FftDims {
     int nx, ny, nz;
     int ax, mxmax;
     int npw;
-    int zc;                   // z chunk of the x-pencil kernels (divides nz)
+    int ns;                   // number of sticks
+    int sld;                  // stick leading dimension of the sticks buffer (>= ns)
     AxisPlan px, py, pz;
 };
 
 // Device tables of the sphere / grid (one set per context).
 struct BasisTables {
-    const int* plane_start;   // [ax + 1]
-    const int* stick_k;       // [ax]
-    const int* lds_idx;       // [npw]  iy*nz + iz inside a plane
+    const int* stick_start;   // [ns + 1] first sphere index of each stick
+    const int* stick_pos;     // [npw]    stick * nz + (mz mod nz)
+    const int* slab_pos;      // [ns]     (mx mod nx) * ny + (my mod ny)
     const double* twx64; const double* twy64; const double* twz64;  // n complex each: exp(-2 pi i m / n)
     const float* twx32; const float* twy32; const float* twz32;
 };
 
 // ------------------------------------------------------------- launchers (fft.hip)
-// sphere vectors -> planes (inverse z then y transforms); rows of `in` have stride ld_in;
-// rows selected through rows[] when non-null.  gscale (per G, may be null) multiplies
-// the coefficients while scattering.
+// Buffers: "sticks" rows of nz * sld complex ([row][iz][stick]); real-space grids are
+// z-major ([row][iz][ix][iy]).
+// sphere rows (stride ld_in) -> sticks (inverse z transforms); gscale (per G, may be
+// null) multiplies the coefficients on the way in.
 template <typename T>
-void launch_sphere_to_planes(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in,
-                             const int* rows, int nrows, const double* gscale, cplx<T>* planes,
-                             hipStream_t s);
-// planes -> x pencils: inverse x-FFT, * V, forward x-FFT (in place in planes).
-template <typename T>
-void launch_pencil_hv(const FftDims& d, const BasisTables& t, cplx<T>* planes, int nrows,
-                      const T* V, long v_stride, const int* vsel, hipStream_t s);
-// planes -> full complex grid (inverse x-FFT), optional real part only.
-template <typename T>
-void launch_pencil_inv_store(const FftDims& d, const BasisTables& t, const cplx<T>* planes, int nrows,
-                             cplx<T>* grid_c, T* grid_r, hipStream_t s);
-// full grids -> planes: f(r) = Vr(r) * u(r) (Vr row = row / nv, u row = row % nv), or, with u
-// null, f(r) = Vr(r) (real data).  Forward x-FFT, active planes kept.
-template <typename T>
-void launch_pencil_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr, const cplx<T>* u,
-                               int nv, int nrows, cplx<T>* planes, hipStream_t s);
-// density: for each perturbation i, dn_i(r) = scale * Re sum_v conj(u_v(r)) Inv-x(planes[i*nv+v]).
-void launch_pencil_density(const FftDims& d, const BasisTables& t, const double2* planes, int npert,
-                           int nv, const double2* u, double scale, double* dn, hipStream_t s);
-
+void launch_sphere_to_sticks(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
+                             const double* gscale, cplx<T>* sticks, hipStream_t s);
 enum SphereEpilogue : int {
     EPI_SCALE = 0,            // out = alpha * F
     EPI_SHIFTED_H = 1,        // out = F + (kin - shift[row % nshift]) * x
     EPI_GSCALE = 2,           // out = F * gscale
 };
-// planes -> sphere (forward y then z transforms, 1/N_g), with an epilogue.
+// sticks -> sphere rows (forward z transforms, 1/N_g) with an epilogue.
 template <typename T>
-void launch_planes_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* planes, int nrows,
-                             const int* rows, cplx<T>* out, long ld_out, int epi, double alpha,
-                             const cplx<T>* x, long ld_x, const T* kin, const double* shift, int nshift,
-                             const double* gscale, hipStream_t s);
+void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows, cplx<T>* out,
+                             long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x, const T* kin,
+                             const double* shift, int nshift, const double* gscale, hipStream_t s);
+// sticks -> inverse (y, x) -> * V(z, x, y) (z-major real grid) -> forward -> sticks, in place.
+template <typename T>
+void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s);
+// sticks -> inverse (y, x) -> complex grid (grid_c) or its real part (grid_r).
+template <typename T>
+void launch_slab_inv_store(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, cplx<T>* grid_c,
+                           T* grid_r, hipStream_t s);
+// grids -> forward (x, y) -> sticks: f = Vr[row / nv] * u[row % nv], or f = Vr[row] (real) when u is null.
+template <typename T>
+void launch_slab_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr, const cplx<T>* u, int nv, int nrows,
+                             cplx<T>* sticks, hipStream_t s);
+// dn_i = scale * Re sum_v conj(u_v) Inv(sticks[i * nv + v]), z-major real grids.
+void launch_slab_density(const FftDims& d, const BasisTables& t, const double2* sticks, int npert, int nv,
+                         const double2* u, double scale, double* dn, hipStream_t s);
+// C-order [ix][iy][iz] <-> z-major [iz][ix][iy] for nrows real grids.
+void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, double* out, bool to_zmajor,
+                           hipStream_t s);
 
 // --------------------------------------------------------- launchers (linalg.hip)
 // S[n][m] = sum_k conj(A[m][k]) * B[brows[n]][k]   (complex; A: M x K, B rows of length K,
@@ -224,10 +224,10 @@ struct Basis {
     int g0;                               // index of G = 0 in S
     int ax, mxmax;
     std::vector<int32_t> miller;          // 3 * npw
-    std::vector<int> plane_start, stick_k, lds_idx;
+    std::vector<int> stick_start, stick_pos, slab_pos;
     std::vector<double> kin, coul;        // coul[g0] = 0
     FftDims dims{};
-    Buf d_plane_start, d_stick_k, d_lds_idx, d_kin64, d_kin32, d_coul, d_tw64, d_tw32;
+    Buf d_stick_start, d_stick_pos, d_slab_pos, d_kin64, d_kin32, d_coul, d_tw64, d_tw32;
     BasisTables tables{};
 };
 
@@ -246,9 +246,9 @@ struct Ctx {
     double gap = 0.0;
     int gs_iterations = 0;
     double gs_residual = 0.0;
-    Buf vloc64, vloc32;                   // [ng]
+    Buf vloc64, vloc32;                   // [ng] z-major
     Buf psi64, psi32;                     // [nv][npw] complex
-    Buf u64;                              // [nv][ng] complex grids
+    Buf u64;                              // [nv][ng] complex grids, z-major
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic
     // solver work space (grown on demand)
@@ -259,7 +259,7 @@ struct Ctx {
 // solver.hip
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
-// Workspace slot used for the plane buffer of one-off transforms at setup.
+// Workspace slot used for the sticks buffer of one-off transforms at setup.
 constexpr int W_STAGE_PLANES = 20;
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
 struct ApplyStats {
@@ -269,9 +269,9 @@ struct ApplyStats {
 };
 // Apply H (shift per row) to `nrows` FP64 sphere vectors: out = (H - shift) x.
 void apply_h64(Ctx& c, const double2* x, long ldx, int nrows, const double* shift, int nshift,
-               double2* out, long ldo, double2* planes);
+               double2* out, long ldo, double2* sticks_buf);
 void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyStats& st, const double* ref2);
-// chi0 on real grid potentials (device): dv [npert][ng] -> dn [npert][ng] (FP64)
+// chi0 on real z-major grid potentials (device): dv [npert][ng] -> dn [npert][ng] (FP64)
 void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st);
 // chi0bar on S (device, FP64, G0 entry ignored/zero): phi [npert][npw] -> out [npert][npw]
 void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st);

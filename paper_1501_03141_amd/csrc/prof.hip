@@ -61,9 +61,9 @@ Profiler& prof() {
     return p;
 }
 
-const char* kNames[K_COUNT] = {"sphere_to_planes", "pencil_hv",     "planes_to_sphere", "pencil_inv_store",
-                               "pencil_fwd_product", "pencil_density", "gemm_ahb",      "gemm_update",
-                               "row_dots",         "cg_update",     "misc"};
+const char* kNames[K_COUNT] = {"sphere_to_sticks", "slab_hv",    "sticks_to_sphere", "slab_inv_store",
+                               "slab_fwd_product", "slab_density", "gemm_ahb",      "gemm_update",
+                               "row_dots",         "cg_update",    "misc"};
 
 }  // namespace
 

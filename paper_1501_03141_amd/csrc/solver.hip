@@ -20,7 +20,7 @@
 //   r = b, z = P_c K r, p = z
 //   q = A p;  alpha = <r,z>/<p,q>;  x += alpha p;  r -= alpha q;  z = P_c K r;
 //   beta = <r,z>_new/<r,z>;  p = z + beta p;  stop when ||r||^2 <= thr2
-// with A = P_c (H - e_v) applied as plane pass -> pencil pass (V_loc) -> plane pass with
+// with A = P_c (H - e_v) applied as stick pass -> slab pass (V_loc) -> stick pass with
 // the kinetic/shift epilogue -> P_c GEMM pair, and K the diagonal kinetic preconditioner
 // 1/max(1, 1/2|G|^2 - e_v) (the paper does not fix K; it only changes iteration counts).
 #include <algorithm>
@@ -34,7 +34,7 @@ namespace pdep {
 namespace {
 
 enum Slot {
-    W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_PLANES, W_S, W_SCAL,
+    W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_STICKS, W_S, W_SCAL,
     W_ROWS, W_VR, W_DN
 };
 
@@ -48,9 +48,10 @@ template <typename T> const T* kin_of(Ctx& c);
 template <> const double* kin_of<double>(Ctx& c) { return c.basis.d_kin64.as<double>(); }
 template <> const float* kin_of<float>(Ctx& c) { return c.basis.d_kin32.as<float>(); }
 
-size_t planes_row_bytes(const Ctx& c) {
+// bytes of one row of the sticks buffer (sized for FP64, also used for FP32)
+size_t sticks_row_bytes(const Ctx& c) {
     const FftDims& d = c.basis.dims;
-    return (size_t)d.ax * d.ny * d.nz * sizeof(double2);
+    return (size_t)d.nz * d.sld * sizeof(double2);
 }
 
 }  // namespace
@@ -65,23 +66,24 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), npw, S, nv, -1.0, 1.0, Y, ld, nullptr, c.stream);
 }
 
-// q = [P_c] (H - shift) p
+// q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
+// kinetic/shift epilogue, then (optionally) the P_c GEMM pair.
 template <typename T>
 void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const double* shift, int nshift,
-              bool project, void* planes, double2* S) {
+              bool project, void* sticks_buf, double2* S) {
     const Basis& b = c.basis;
-    cplx<T>* pl = static_cast<cplx<T>*>(planes);
-    launch_sphere_to_planes<T>(b.dims, b.tables, p, ld, nullptr, nrows, nullptr, pl, c.stream);
-    launch_pencil_hv<T>(b.dims, b.tables, pl, nrows, vloc_of<T>(c), 0, nullptr, c.stream);
-    launch_planes_to_sphere<T>(b.dims, b.tables, pl, nrows, nullptr, q, ld, EPI_SHIFTED_H, 0.0, p, ld, kin_of<T>(c),
-                               shift, nshift, nullptr, c.stream);
+    cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
+    launch_sphere_to_sticks<T>(b.dims, b.tables, p, ld, nrows, nullptr, sk, c.stream);
+    launch_slab_hv<T>(b.dims, b.tables, sk, nrows, vloc_of<T>(c), c.stream);
+    launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nrows, q, ld, EPI_SHIFTED_H, 0.0, p, ld, kin_of<T>(c), shift,
+                               nshift, nullptr, c.stream);
     if (project) project_c<T>(c, q, ld, nrows, S);
 }
 
 void apply_h64(Ctx& c, const double2* x, long ldx, int nrows, const double* shift, int nshift, double2* out,
-               long ldo, double2* planes) {
+               long ldo, double2* sticks_buf) {
     PDEP_REQUIRE(ldx == ldo, PDEP_EINVAL, "apply_h64: ld mismatch");
-    apply_op<double>(c, x, out, ldx, nrows, shift, nshift, false, planes, nullptr);
+    apply_op<double>(c, x, out, ldx, nrows, shift, nshift, false, sticks_buf, nullptr);
 }
 
 namespace {
@@ -115,7 +117,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     cplx<T>* z = static_cast<cplx<T>*>(c.ws(W_CZ, vbytes));
     cplx<T>* p = static_cast<cplx<T>*>(c.ws(W_CP, vbytes));
     cplx<T>* q = static_cast<cplx<T>*>(c.ws(W_CQ, vbytes));
-    void* planes = c.ws(W_PLANES, (size_t)n * planes_row_bytes(c));
+    void* sticks = c.ws(W_STICKS, (size_t)n * sticks_row_bytes(c));
     double2* S = static_cast<double2*>(c.ws(W_S, (size_t)n * nv * sizeof(double2)));
     const int pre = c.opts.precond;
     const T* kin = kin_of<T>(c);
@@ -136,7 +138,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     while (h_active > 0 && it < maxit) {
         const int nstep = std::min(poll, maxit - it);
         for (int k = 0; k < nstep; ++k) {
-            apply_op<T>(c, p, q, ld, n, sc.shift, n, true, planes, S);
+            apply_op<T>(c, p, q, ld, n, sc.shift, n, true, sticks, S);
             st.op_applications++;
             launch_row_dots<T>(n, npw, p, ld, q, ld, sc.pq, nullptr, s);
             launch_cg_step1<T>(n, npw, x, r, z, p, q, ld, sc.rz, sc.pq, sc.active, kin, sc.shift, n, pre, s);
@@ -240,7 +242,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         PDEP_HIP(hipMemcpyAsync(its.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
         // true FP64 residual of the rows just updated
         launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
-        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, c.ws(W_PLANES, (size_t)na * planes_row_bytes(c)),
+        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, c.ws(W_STICKS, (size_t)na * sticks_row_bytes(c)),
                          static_cast<double2*>(c.ws(W_S, (size_t)na * nv * sizeof(double2))));
         st.op_applications++;
         launch_sub_rows(na, npw, b64, ld, d_rows, qa, ld, qa, ld, s);
@@ -273,7 +275,7 @@ namespace {
 
 size_t row_bytes(const Ctx& c, long ld) {
     const size_t inner = c.opts.precision == PDEP_MIXED_FP32 ? sizeof(float2) : sizeof(double2);
-    return (size_t)ld * sizeof(double2) * 5 + (size_t)ld * inner * 6 + planes_row_bytes(c) +
+    return (size_t)ld * sizeof(double2) * 5 + (size_t)ld * inner * 6 + sticks_row_bytes(c) +
            (size_t)c.nv * sizeof(double2) + 128;
 }
 
@@ -296,8 +298,9 @@ int perturbation_tile(Ctx& c, int npert, long ld) {
     return (int)std::min<size_t>((size_t)npert, std::max<size_t>(tp, 1));
 }
 
-// Core chain for real grid potentials Vr [npert][ng] (device).  Writes dn [npert][ng]
-// (if non-null) and/or the projected result out [npert][ld_out] in S order (if non-null).
+// Core chain for real z-major grid potentials Vr [npert][ng] (device).  Writes dn
+// [npert][ng] z-major (if non-null) and/or the projected result out [npert][ld_out] in
+// S order (if non-null).
 void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out, long ld_out, ApplyStats& st) {
     const Basis& b = c.basis;
     const int nv = c.nv, npw = b.npw;
@@ -308,15 +311,15 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
     for (int p0 = 0; p0 < npert; p0 += tile) {
         const int tp = std::min(tile, npert - p0);
         const int nrow = tp * nv;
-        double2* planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)nrow * planes_row_bytes(c)));
+        double2* sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));
         double2* b64 = static_cast<double2*>(c.ws(W_B64, (size_t)nrow * ld * sizeof(double2)));
         double2* x64 = static_cast<double2*>(c.ws(W_X64, (size_t)nrow * ld * sizeof(double2)));
         double2* S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
         // right-hand sides b = -P_c Fwd(dV_i u_v)
-        launch_pencil_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.u64.as<double2>(), nv, nrow,
-                                          planes, s);
-        launch_planes_to_sphere<double>(b.dims, b.tables, planes, nrow, nullptr, b64, ld, EPI_SCALE, -1.0, nullptr,
-                                        0, nullptr, nullptr, 0, nullptr, s);
+        launch_slab_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.u64.as<double2>(), nv, nrow, sticks,
+                                        s);
+        launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, nrow, b64, ld, EPI_SCALE, -1.0, nullptr, 0, nullptr,
+                                        nullptr, 0, nullptr, s);
         double* ref2 = static_cast<double*>(c.ws(W_DN + 1, (size_t)nrow * sizeof(double)));
         launch_row_dots<double>(nrow, npw, b64, ld, b64, ld, ref2, nullptr, s);
         project_c<double>(c, b64, ld, nrow, S);
@@ -325,16 +328,15 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
         S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
         project_c<double>(c, x64, ld, nrow, S);
         // density response
-        planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)nrow * planes_row_bytes(c)));
-        launch_sphere_to_planes<double>(b.dims, b.tables, x64, ld, nullptr, nrow, nullptr, planes, s);
+        sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));
+        launch_sphere_to_sticks<double>(b.dims, b.tables, x64, ld, nrow, nullptr, sticks, s);
         double* dn = dn_out ? dn_out + (long)p0 * ng
                             : static_cast<double*>(c.ws(W_DN, (size_t)tp * ng * sizeof(double)));
-        launch_pencil_density(b.dims, b.tables, planes, tp, nv, c.u64.as<double2>(), 4.0 / b.omega, dn, s);
+        launch_slab_density(b.dims, b.tables, sticks, tp, nv, c.u64.as<double2>(), 4.0 / b.omega, dn, s);
         if (out) {
-            launch_pencil_fwd_product<double>(b.dims, b.tables, dn, nullptr, 1, tp, planes, s);
-            launch_planes_to_sphere<double>(b.dims, b.tables, planes, tp, nullptr, out + (long)p0 * ld_out, ld_out,
-                                            EPI_GSCALE, 0.0, nullptr, 0, nullptr, nullptr, 0,
-                                            b.d_coul.as<double>(), s);
+            launch_slab_fwd_product<double>(b.dims, b.tables, dn, nullptr, 1, tp, sticks, s);
+            launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, tp, out + (long)p0 * ld_out, ld_out, EPI_GSCALE,
+                                            0.0, nullptr, 0, nullptr, nullptr, 0, b.d_coul.as<double>(), s);
         }
         PDEP_HIP(hipStreamSynchronize(s));
     }
@@ -354,10 +356,10 @@ void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplySt
     const int chunk = 256;
     for (int p0 = 0; p0 < npert; p0 += chunk) {
         const int np = std::min(chunk, npert - p0);
-        double2* planes = static_cast<double2*>(c.ws(W_PLANES, (size_t)np * planes_row_bytes(c)));
-        launch_sphere_to_planes<double>(b.dims, b.tables, phi + (long)p0 * ld, ld, nullptr, np,
-                                        b.d_coul.as<double>(), planes, c.stream);
-        launch_pencil_inv_store<double>(b.dims, b.tables, planes, np, nullptr, Vr + (long)p0 * b.ng, c.stream);
+        double2* sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)np * sticks_row_bytes(c)));
+        launch_sphere_to_sticks<double>(b.dims, b.tables, phi + (long)p0 * ld, ld, np, b.d_coul.as<double>(), sticks,
+                                        c.stream);
+        launch_slab_inv_store<double>(b.dims, b.tables, sticks, np, nullptr, Vr + (long)p0 * b.ng, c.stream);
     }
     chi0_core(c, npert, Vr, nullptr, out, ld, st);
 }
