@@ -50,7 +50,7 @@ struct Timer {
     }
 };
 
-enum CapiSlot { C_IN = 17, C_OUT = 18, C_STAGE = 19 };
+enum CapiSlot { C_IN = pdep::WS_CAPI_IN, C_OUT = pdep::WS_CAPI_OUT, C_STAGE = pdep::WS_CAPI_STAGE };
 
 void check_ctx(pdep_ctx* ctx) { PDEP_REQUIRE(ctx != nullptr, PDEP_EINVAL, "null context"); }
 
@@ -60,7 +60,7 @@ void finish_setup(Ctx& c) {
     const int nv = c.nv, npw = b.npw;
     hipStream_t s = c.stream;
     c.u64.ensure(&c.al, (size_t)nv * b.ng * sizeof(double2));
-    double2* sticks = static_cast<double2*>(c.ws(pdep::W_STAGE_PLANES, (size_t)nv * b.dims.nz * b.dims.sld *
+    double2* sticks = static_cast<double2*>(c.ws(pdep::WS_SETUP_STICKS, (size_t)nv * b.dims.nz * b.dims.sld *
                                                                            sizeof(double2)));
     pdep::launch_sphere_to_sticks<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nv, nullptr, sticks, s);
     pdep::launch_slab_inv_store<double>(b.dims, b.tables, sticks, nv, c.u64.as<double2>(), nullptr, s);

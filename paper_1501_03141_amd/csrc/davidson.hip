@@ -164,7 +164,7 @@ void combine(Ctx& c, const double2* X, int M, int N, long ld, const std::vector<
              double2* Cdev) {
     const int npw = c.basis.npw;
     PDEP_HIP(hipMemcpyAsync(Cdev, C.data(), (size_t)N * M * sizeof(double2), hipMemcpyHostToDevice, c.stream));
-    launch_gemm_update<double>(M, N, npw, X, ld, Cdev, M, 1.0, 0.0, Y, ld, nullptr, c.stream);
+    launch_gemm_update<double>(M, N, npw, X, ld, Cdev, M, 1.0, 0.0, Y, ld, c.stream);
     PDEP_HIP(hipStreamSynchronize(c.stream));   // C is pageable host memory owned by the caller
 }
 
@@ -224,20 +224,20 @@ int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, d
         if (m > 0) {
             double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
             for (int pass = 0; pass < 2; ++pass) {
-                launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, nullptr, Cdev, m, s);   // C[j][i] = <V_i, T_j>
+                launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, Cdev, m, nullptr, 0, s);   // C[j][i] = <V_i, T_j>
                 if (real_coef) {
                     std::vector<double2> C = d2h(Cdev, (size_t)nt * m, s);
                     for (auto& x : C) x.y = 0.0;
                     PDEP_HIP(hipMemcpyAsync(Cdev, C.data(), C.size() * sizeof(double2), hipMemcpyHostToDevice, s));
                     PDEP_HIP(hipStreamSynchronize(s));
                 }
-                launch_gemm_update<double>(m, nt, npw, V, ld, Cdev, m, -1.0, 1.0, T, ld, nullptr, s);
+                launch_gemm_update<double>(m, nt, npw, V, ld, Cdev, m, -1.0, 1.0, T, ld, s);
             }
             nt = normalise_rows(c, ws, T, nt, ld, unit, 1e-8, unit2);
             if (nt == 0) break;
         }
         double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
-        launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, nullptr, Cdev, nt, s);
+        launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, Cdev, nt, nullptr, 0, s);
         std::vector<double2> G = d2h(Cdev, (size_t)nt * nt, s);
         std::vector<double> w;
         std::vector<double2> Q;
@@ -283,12 +283,12 @@ void ground_state(Ctx& c) {
     double2* X = static_cast<double2*>(ws.get(D_X, (size_t)nb * ld * sizeof(double2)));
     double2* AX = static_cast<double2*>(ws.get(D_AX, (size_t)nb * ld * sizeof(double2)));
     double2* R = static_cast<double2*>(ws.get(D_R, (size_t)nb * ld * sizeof(double2)));
-    double2* sticks = static_cast<double2*>(c.ws(20, (size_t)mmax * b.dims.nz * b.dims.sld * sizeof(double2)));
-    double* dtheta = static_cast<double*>(c.ws(21, (size_t)mmax * sizeof(double) * 2 + 64));
+    double2* sticks = static_cast<double2*>(c.ws(WS_SETUP_STICKS, (size_t)mmax * b.dims.nz * b.dims.sld * sizeof(double2)));
+    double* dtheta = static_cast<double*>(c.ws(WS_DAV_THETA, (size_t)mmax * sizeof(double) * 2 + 64));
     double* dzero = dtheta + mmax;
     launch_fill_zero(dzero, (size_t)mmax * sizeof(double), s);
-    double2* Cdev = static_cast<double2*>(c.ws(22, (size_t)mmax * mmax * sizeof(double2)));
-    double* dots = static_cast<double*>(c.ws(23, (size_t)mmax * sizeof(double) + 64));
+    double2* Cdev = static_cast<double2*>(c.ws(WS_DAV_C, (size_t)mmax * mmax * sizeof(double2)));
+    double* dots = static_cast<double*>(c.ws(WS_DAV_DOTS, (size_t)mmax * sizeof(double) + 64));
 
     // random start weighted towards low kinetic energy
     std::vector<double2> h0((size_t)nb * ld, make_double2(0, 0));
@@ -309,7 +309,7 @@ void ground_state(Ctx& c) {
     bool conv = false;
     double maxres = 0.0;
     for (it = 1; it <= c.opts.gs_maxit; ++it) {
-        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, nullptr, Cdev, m, s);
+        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, nullptr, 0, s);
         std::vector<double2> M = d2h(Cdev, (size_t)m * m, s);
         std::vector<double2> Y;
         dense_eig(ws, sv, M, m, false, theta, Y);
@@ -386,9 +386,9 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     double2* X = static_cast<double2*>(ws.get(D_X, (size_t)nb * ld * sizeof(double2)));
     double2* AX = static_cast<double2*>(ws.get(D_AX, (size_t)nb * ld * sizeof(double2)));
     double2* R = static_cast<double2*>(ws.get(D_R, (size_t)nb * ld * sizeof(double2)));
-    double* dtheta = static_cast<double*>(c.ws(21, (size_t)mmax * sizeof(double) * 2 + 64));
-    double2* Cdev = static_cast<double2*>(c.ws(22, (size_t)mmax * mmax * sizeof(double2)));
-    double* dots = static_cast<double*>(c.ws(23, (size_t)mmax * sizeof(double) + 64));
+    double* dtheta = static_cast<double*>(c.ws(WS_DAV_THETA, (size_t)mmax * sizeof(double) * 2 + 64));
+    double2* Cdev = static_cast<double2*>(c.ws(WS_DAV_C, (size_t)mmax * mmax * sizeof(double2)));
+    double* dots = static_cast<double*>(c.ws(WS_DAV_DOTS, (size_t)mmax * sizeof(double) + 64));
 
     // start block: caller's vectors, or the library's own random Hermitian-symmetric ones
     if (phi0_dev)
@@ -429,7 +429,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     double maxres = 0.0;
     int it;
     for (it = 1; it <= eo.maxit; ++it) {
-        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, nullptr, Cdev, m, s);
+        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, nullptr, 0, s);
         std::vector<double2> M = d2h(Cdev, (size_t)m * m, s);
         std::vector<double2> Y;
         dense_eig(ws, sv, M, m, true, theta, Y);

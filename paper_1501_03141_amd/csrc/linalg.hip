@@ -3,6 +3,8 @@
 //  - per-row inner products and norms (accumulated in FP64),
 //  - the element-wise parts of the batched preconditioned CG,
 //  - precision conversion, row gathers and updates used by the refinement loop.
+#include <algorithm>
+
 #include "pdep_internal.h"
 
 namespace pdep {
@@ -12,112 +14,208 @@ namespace {
 template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
 
 // ------------------------------------------------------------------------ GEMMs ---
-// S[n][m] = sum_k conj(A[m][k]) B[n][k]; 32 x 32 output tile per workgroup, each thread
-// a 2 x 2 sub-tile, K staged through LDS 16 columns at a time.
+// Complex GEMMs on the matrix cores.  A complex product is written as a real one of
+// twice the size: with interleaved storage (re, im), the pair of real rows
+// (a_re, a_im) and (-a_im, a_re) dotted with an interleaved vector y give Re and Im of
+// conj(a) . y, and the real 2x2 block [[a_re, a_im], [-a_im, a_re]] applied to an
+// interleaved coefficient (s_re, s_im) gives the interleaved a * s.  The expansion is
+// done while staging tiles in LDS, so memory holds only the complex data.
+//
+// Matrix-core instruction: 16x16x4 (f32 or f64), one wave, A[m][k] from lane
+// (m + 16 k), B[k][n] from lane (n + 16 k); result slot i of lane l is row
+// 4*(l/16) + i (f32) or 4*i + l/16 (f64) of column l % 16.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc = mfma_f4;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <> struct Mfma<double> {
+    using acc = mfma_d4;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+
+constexpr int kPad = 4;
+
+// S[n][m] = sum_k conj(A[m][k]) B[n][k].  Real form C[m'][n] = sum_k' A'[m'][k'] B'[n][k']
+// with m' = 2m + s.  Workgroup tile: 32 complex rows of A (64 real) x 64 rows of B,
+// K staged 16 complex (32 real) at a time; 4 waves in a 2 x 2 arrangement, each 32 x 32.
+// Split-K: workgroup z covers k in [z * kchunk, (z + 1) * kchunk) and writes its
+// partial product to S + z * N * lds (reduced afterwards in a fixed order).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cplx<T>* __restrict__ A, long lda,
-                                                  const cplx<T>* __restrict__ B, long ldb,
-                                                  const int* __restrict__ brows, double2* __restrict__ S, long lds) {
-    constexpr int TM = 32, TN = 32, TK = 16;
-    __shared__ cplx<T> As[TK][TM + 1];
-    __shared__ cplx<T> Bs[TK][TN + 1];
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    T ar[2][2] = {{0, 0}, {0, 0}}, ai[2][2] = {{0, 0}, {0, 0}};
-    for (int k0 = 0; k0 < K; k0 += TK) {
+                                                  const cplx<T>* __restrict__ B, long ldb, cplx<T>* __restrict__ S,
+                                                  long lds, int kchunk) {
+    constexpr int BMC = 32, BN = 64, BKC = 16;
+    constexpr int BMR = 2 * BMC, BKR = 2 * BKC;
+    __shared__ T As[BKR][BMR + kPad];
+    __shared__ T Bs[BKR][BN + kPad];
+    using Op = Mfma<T>;
+    const int m0 = blockIdx.x * BMC, n0 = blockIdx.y * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    typename Op::acc acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = typename Op::acc{0, 0, 0, 0};
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    S += (long)blockIdx.z * N * lds;
+    for (int kc = kbeg; kc < kend; kc += BKC) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int e = tid + 256 * j;
-            const int rr = e / TK, kk = e % TK;
-            const int gk = k0 + kk;
-            const int gm = m0 + rr;
-            As[kk][rr] = (gm < M && gk < K) ? A[(long)gm * lda + gk] : mk<T>(0, 0);
-            const int gn = n0 + rr;
-            cplx<T> bv = mk<T>(0, 0);
-            if (gn < N && gk < K) {
-                const long brow = brows ? brows[gn] : gn;
-                bv = B[brow * ldb + gk];
-            }
-            Bs[kk][rr] = bv;
+            const int r = e / BKC, g = e % BKC;
+            cplx<T> v;
+            v.x = 0; v.y = 0;
+            if (m0 + r < M && kc + g < kend) v = A[(long)(m0 + r) * lda + kc + g];
+            As[2 * g][2 * r] = v.x;
+            As[2 * g + 1][2 * r] = v.y;
+            As[2 * g][2 * r + 1] = -v.y;
+            As[2 * g + 1][2 * r + 1] = v.x;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j;
+            const int r = e / BKC, g = e % BKC;
+            cplx<T> v;
+            v.x = 0; v.y = 0;
+            if (n0 + r < N && kc + g < kend) v = B[(long)(n0 + r) * ldb + kc + g];
+            Bs[2 * g][r] = v.x;
+            Bs[2 * g + 1][r] = v.y;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < TK; ++kk) {
-            const cplx<T> a0 = As[kk][tx], a1 = As[kk][tx + 16];
-            const cplx<T> b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
-            // conj(a) * b
-            ar[0][0] += a0.x * b0.x + a0.y * b0.y; ai[0][0] += a0.x * b0.y - a0.y * b0.x;
-            ar[0][1] += a0.x * b1.x + a0.y * b1.y; ai[0][1] += a0.x * b1.y - a0.y * b1.x;
-            ar[1][0] += a1.x * b0.x + a1.y * b0.y; ai[1][0] += a1.x * b0.y - a1.y * b0.x;
-            ar[1][1] += a1.x * b1.x + a1.y * b1.y; ai[1][1] += a1.x * b1.y - a1.y * b1.x;
+#pragma unroll
+        for (int kk = 0; kk < BKR; kk += 4) {
+            const int kr = kk + (lane >> 4), c = lane & 15;
+            const T a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
+            const T b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
+            acc[0][0] = Op::mma(a0, b0, acc[0][0]);
+            acc[0][1] = Op::mma(a0, b1, acc[0][1]);
+            acc[1][0] = Op::mma(a1, b0, acc[1][0]);
+            acc[1][1] = Op::mma(a1, b1, acc[1][1]);
         }
         __syncthreads();
     }
+    T* So = reinterpret_cast<T*>(S);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int m = m0 + tx + 16 * i, n = n0 + ty + 16 * j;
-            if (m < M && n < N) S[(long)n * lds + m] = make_double2((double)ar[i][j], (double)ai[i][j]);
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mr = wm + 16 * a + Op::row(lane, i);       // real row in the tile
+                const int m = m0 + (mr >> 1), part = mr & 1;
+                const int n = n0 + wn + 16 * b + (lane & 15);
+                if (m < M && n < N) So[((long)n * lds + m) * 2 + part] = acc[a][b][i];
+            }
 }
 
-// Y[n][k] = beta Y[n][k] + alpha sum_m A[m][k] S[n][m]; tile 16 rows x 128 columns.
+// S[n][m] = sum_z P[z][n][m] in the order z = 0, 1, ... (deterministic split-K sum).
+template <typename T>
+__global__ void k_splitk_reduce(int M, int N, long lds, int splits, const cplx<T>* __restrict__ P,
+                                cplx<T>* __restrict__ S) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)N * M) return;
+    const long n = e / M, m = e - (e / M) * M;
+    const long stride = (long)N * lds;
+    T re = 0, im = 0;
+    for (int z = 0; z < splits; ++z) {
+        const cplx<T> v = P[z * stride + n * lds + m];
+        re += v.x;
+        im += v.y;
+    }
+    cplx<T> o;
+    o.x = re;
+    o.y = im;
+    S[n * lds + m] = o;
+}
+
+// Y[n][k] = beta Y[n][k] + alpha sum_m A[m][k] S[n][m].  Real form over k' = 2k + c
+// (columns) and m' = 2m + s (contraction).  Workgroup tile: 64 rows n x 64 complex
+// columns (128 real), contraction staged 16 complex (32 real) at a time; 4 waves in a
+// 2 x 2 arrangement, each 32 rows x 64 real columns.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const cplx<T>* __restrict__ A, long lda,
-                                                     const double2* __restrict__ S, long lds, double alpha,
-                                                     double beta, cplx<T>* __restrict__ Y, long ldy,
-                                                     const int* __restrict__ yrows) {
-    constexpr int TN = 16, TK = 128, TMc = 16;
-    __shared__ cplx<T> As[TMc][TK];
-    __shared__ cplx<T> Ss[TN][TMc + 1];
-    const int k0 = blockIdx.x * TK, n0 = blockIdx.y * TN;
-    const int tid = threadIdx.x;
-    const int nl = tid / 16, kl = tid % 16;
-    T accr[8], acci[8];
+                                                     const cplx<T>* __restrict__ S, long lds, double alpha,
+                                                     double beta, cplx<T>* __restrict__ Y, long ldy) {
+    constexpr int BN = 64, BKC = 64, BMC = 16;
+    constexpr int BKR = 2 * BKC, BMR = 2 * BMC;
+    __shared__ T Ss[BMR][BN + kPad];    // [m'][n]
+    __shared__ T Bs[BMR][BKR + kPad];   // [m'][k']
+    using Op = Mfma<T>;
+    const int k0 = blockIdx.x * BKC, n0 = blockIdx.y * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = (wave & 1) * 32, wk = (wave >> 1) * 64;
+    typename Op::acc acc[2][4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) { accr[j] = 0; acci[j] = 0; }
-    for (int m0 = 0; m0 < M; m0 += TMc) {
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int b = 0; b < 4; ++b) acc[a][b] = typename Op::acc{0, 0, 0, 0};
+    for (int mc = 0; mc < M; mc += BMC) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {        // S: 64 rows x 16 complex
             const int e = tid + 256 * j;
-            const int mm = e / TK, kk = e % TK;
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[mm][kk] = (gm < M && gk < K) ? A[(long)gm * lda + gk] : mk<T>(0, 0);
+            const int r = e / BMC, mm = e % BMC;
+            cplx<T> v;
+            v.x = 0; v.y = 0;
+            if (n0 + r < N && mc + mm < M) v = S[(long)(n0 + r) * lds + mc + mm];
+            Ss[2 * mm][r] = v.x;
+            Ss[2 * mm + 1][r] = v.y;
         }
-        {
-            const int nn = tid / 16, mm = tid % 16;
-            const int gn = n0 + nn, gm = m0 + mm;
-            double2 sv = make_double2(0.0, 0.0);
-            if (gn < N && gm < M) sv = S[(long)gn * lds + gm];
-            Ss[nn][mm] = mk<T>((T)sv.x, (T)sv.y);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {        // A: 16 complex rows x 64 complex columns
+            const int e = tid + 256 * j;
+            const int mm = e / BKC, g = e % BKC;
+            cplx<T> v;
+            v.x = 0; v.y = 0;
+            if (mc + mm < M && k0 + g < K) v = A[(long)(mc + mm) * lda + k0 + g];
+            Bs[2 * mm][2 * g] = v.x;
+            Bs[2 * mm][2 * g + 1] = v.y;
+            Bs[2 * mm + 1][2 * g] = -v.y;
+            Bs[2 * mm + 1][2 * g + 1] = v.x;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int mm = 0; mm < TMc; ++mm) {
-            const cplx<T> s = Ss[nl][mm];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const cplx<T> a = As[mm][kl + 16 * j];
-                accr[j] += a.x * s.x - a.y * s.y;
-                acci[j] += a.x * s.y + a.y * s.x;
+        for (int kk = 0; kk < BMR; kk += 4) {
+            const int kr = kk + (lane >> 4), c = lane & 15;
+            const T a0 = Ss[kr][wn + c], a1 = Ss[kr][wn + 16 + c];
+            T b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = Bs[kr][wk + 16 * q + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[0][q] = Op::mma(a0, b[q], acc[0][q]);
+                acc[1][q] = Op::mma(a1, b[q], acc[1][q]);
             }
         }
         __syncthreads();
     }
-    const int n = n0 + nl;
-    if (n >= N) return;
-    const long yr = yrows ? yrows[n] : n;
-    cplx<T>* y = Y + yr * ldy;
+    T* Yo = reinterpret_cast<T*>(Y);
+    const T al = (T)alpha, be = (T)beta;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kl + 16 * j;
-        if (k < K) {
-            cplx<T> old = beta != 0.0 ? y[k] : mk<T>(0, 0);
-            y[k] = mk<T>((T)(beta * old.x + alpha * accr[j]), (T)(beta * old.y + alpha * acci[j]));
-        }
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = n0 + wn + 16 * a + Op::row(lane, i);
+                const int kr = k0 * 2 + wk + 16 * q + (lane & 15);   // real column
+                if (n < N && (kr >> 1) < K) {
+                    T* y = Yo + (long)n * ldy * 2 + kr;
+                    const T old = beta != 0.0 ? *y : T(0);
+                    *y = be * old + al * acc[a][q][i];
+                }
+            }
 }
 
 // ------------------------------------------------------------------- reductions ---
@@ -310,26 +408,43 @@ inline dim3 rows_grid(int K, int nrows) {
 }  // namespace
 
 template <typename T>
-void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const int* brows,
-                     double2* S, long lds, hipStream_t s) {
+void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, cplx<T>* S,
+                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
-    PDEP_REQUIRE((N + 31) / 32 <= 65535, PDEP_EINVAL, "gemm_ahb: N too large");
-    dim3 grid((M + 31) / 32, (N + 31) / 32);
-    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * 16.0,
+    PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_ahb: N too large");
+    dim3 grid((M + 31) / 32, (N + 63) / 64);
+    // split K when the output tiles alone cannot fill the chip (about 1k workgroups)
+    int splits = 1;
+    const long tiles = (long)grid.x * grid.y;
+    if (work && tiles < 512) {
+        splits = (int)std::min<long>((1024 + tiles - 1) / tiles, std::max(1, K / 256));
+        while (splits > 1 && (size_t)splits * N * lds > work_elems) --splits;
+    }
+    const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
+    if (splits > 1) splits = (K + kchunk - 1) / kchunk;
+    grid.z = splits;
+    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * sizeof(cplx<T>),
                     8.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_ahb<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, brows, S, lds);
+    hipLaunchKernelGGL(k_gemm_ahb<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, splits > 1 ? work : S, lds,
+                       kchunk);
     PDEP_HIP(hipGetLastError());
+    if (splits > 1) {
+        const long tot = (long)N * M;
+        hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds, splits,
+                           work, S);
+        PDEP_HIP(hipGetLastError());
+    }
 }
 
 template <typename T>
-void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const double2* S, long lds, double alpha,
-                        double beta, cplx<T>* Y, long ldy, const int* yrows, hipStream_t s) {
+void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds, double alpha,
+                        double beta, cplx<T>* Y, long ldy, hipStream_t s) {
     if (N <= 0 || K <= 0) return;
-    PDEP_REQUIRE((N + 15) / 16 <= 65535, PDEP_EINVAL, "gemm_update: N too large");
-    dim3 grid((K + 127) / 128, (N + 15) / 16);
-    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(cplx<T>) + (double)N * M * 16.0 +
+    PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_update: N too large");
+    dim3 grid((K + 63) / 64, (N + 63) / 64);
+    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(cplx<T>) + (double)N * M * sizeof(cplx<T>) +
                     (double)N * K * sizeof(cplx<T>) * (beta != 0.0 ? 2.0 : 1.0), 8.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_update<T>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y, ldy, yrows);
+    hipLaunchKernelGGL(k_gemm_update<T>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y, ldy);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -451,10 +566,10 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
 }
 
 #define PDEP_INST_LA(T)                                                                                         \
-    template void launch_gemm_ahb<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, const int*,    \
-                                     double2*, long, hipStream_t);                                            \
-    template void launch_gemm_update<T>(int, int, int, const cplx<T>*, long, const double2*, long, double,     \
-                                        double, cplx<T>*, long, const int*, hipStream_t);                     \
+    template void launch_gemm_ahb<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, cplx<T>*,      \
+                                     long, cplx<T>*, size_t, hipStream_t);                                    \
+    template void launch_gemm_update<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, double,     \
+                                        double, cplx<T>*, long, hipStream_t);                                 \
     template void launch_row_dots<T>(int, int, const cplx<T>*, long, const cplx<T>*, long, double*, double*,   \
                                      hipStream_t);                                                            \
     template void launch_cg_init<T>(int, int, const cplx<T>*, long, cplx<T>*, cplx<T>*, cplx<T>*, const T*,    \

@@ -162,15 +162,17 @@ void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, 
                            hipStream_t s);
 
 // --------------------------------------------------------- launchers (linalg.hip)
-// S[n][m] = sum_k conj(A[m][k]) * B[brows[n]][k]   (complex; A: M x K, B rows of length K,
-// S: N x M, leading dimensions in elements); brows may be null (identity).
+// S[n][m] = sum_k conj(A[m][k]) * B[n][k]   (complex, matrix cores; A: M x K, B: N x K,
+// S: N x M, leading dimensions in complex elements).  work (work_elems complex, may be
+// null) holds split-K partial products when the output alone is too small to fill the
+// GPU; the partials are summed in a fixed order.
 template <typename T>
-void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb,
-                     const int* brows, double2* S, long lds, hipStream_t s);
-// Y[yrows[n]][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S double2, N x M)
+void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, cplx<T>* S,
+                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s);
+// Y[n][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S: N x M; Y must not alias A or S)
 template <typename T>
-void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const double2* S, long lds,
-                        double alpha, double beta, cplx<T>* Y, long ldy, const int* yrows, hipStream_t s);
+void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds,
+                        double alpha, double beta, cplx<T>* Y, long ldy, hipStream_t s);
 // per-row dot products: out[r] = Re <a_r, b_r>, out2[r] = ||a_r||^2 (out2 may be null)
 template <typename T>
 void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>* b, long ldb,
@@ -235,6 +237,15 @@ void build_basis(const pdep_cell& cell, Basis& b);
 void upload_basis(Basis& b, Allocator* al, hipStream_t s);
 AxisPlan make_axis_plan(int n);
 
+// Context work-space slots (Ctx::ws): solver.hip owns [0, WS_SOLVER_END); the others
+// stay alive across solver calls and must not overlap it.
+enum WsSlot : int {
+    WS_SOLVER_END = 28,
+    WS_CAPI_IN = 28, WS_CAPI_OUT = 29, WS_CAPI_STAGE = 30,
+    WS_SETUP_STICKS = 31, WS_DAV_THETA = 32, WS_DAV_C = 33, WS_DAV_DOTS = 34,
+    WS_COUNT = 36
+};
+
 struct Ctx {
     pdep_opts opts{};
     Allocator al;
@@ -252,15 +263,13 @@ struct Ctx {
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic
     // solver work space (grown on demand)
-    Buf w[24];
+    Buf w[WS_COUNT];
     void* ws(int i, size_t bytes) { w[i].ensure(&al, bytes); return w[i].get(); }
 };
 
 // solver.hip
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
-// Workspace slot used for the sticks buffer of one-off transforms at setup.
-constexpr int W_STAGE_PLANES = 20;
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
 struct ApplyStats {
     int n_rhs = 0, cg_iter_max = 0, refine_steps = 0, n_notconv = 0;

@@ -35,8 +35,9 @@ namespace {
 
 enum Slot {
     W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_STICKS, W_S, W_SCAL,
-    W_ROWS, W_VR, W_DN
+    W_ROWS, W_VR, W_DN, W_REF2, W_CX2, W_CR2, W_CZ2, W_CP2, W_XOUT, W_MAP, W_SPLIT, W_LAST
 };
+static_assert(W_LAST <= WS_SOLVER_END, "solver work-space slots overlap the others");
 
 template <typename T> const cplx<T>* psi_of(Ctx& c);
 template <> const double2* psi_of<double>(Ctx& c) { return c.psi64.as<double2>(); }
@@ -58,12 +59,15 @@ size_t sticks_row_bytes(const Ctx& c) {
 
 long sphere_ld(int npw) { return ((long)npw + 63) / 64 * 64; }
 
-// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.
+// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.  S: work space of nrows * nv double2.
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv;
-    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), npw, Y, ld, nullptr, S, nv, c.stream);
-    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), npw, S, nv, -1.0, 1.0, Y, ld, nullptr, c.stream);
+    cplx<T>* St = reinterpret_cast<cplx<T>*>(S);
+    const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
+    cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
+    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), npw, Y, ld, St, nv, work, split_elems, c.stream);
+    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), npw, St, nv, -1.0, 1.0, Y, ld, c.stream);
 }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
@@ -88,74 +92,206 @@ void apply_h64(Ctx& c, const double2* x, long ldx, int nrows, const double* shif
 
 namespace {
 
+// Per-row inputs/outputs of the inner solver (original row order) and shared scratch.
 struct CgScalars {
-    double *rz, *rz_new, *pq, *rr, *thr2, *shift;
-    int *active, *iters, *n_active;
+    double *rz_new, *pq, *rr, *thr2, *shift;   // thr2 / shift: inputs per original row
+    int *active, *iters, *n_active;            // iters: output per original row
+    // per-slot state of the compacted active set, two sets for ping-pong gathers
+    double *s_rz[2], *s_shift[2], *s_thr2[2];
+    int *s_iters[2], *s_id[2];
 };
 
 CgScalars cg_scalars(Ctx& c, int n) {
-    const size_t nd = 6 * (size_t)n, ni = 2 * (size_t)n + 64;
+    const size_t nd = 5 * (size_t)n + 6 * (size_t)n, ni = 3 * (size_t)n + 4 * (size_t)n + 64;
     char* base = static_cast<char*>(c.ws(W_SCAL, nd * sizeof(double) + ni * sizeof(int)));
     CgScalars s;
     double* d = reinterpret_cast<double*>(base);
-    s.rz = d; s.rz_new = d + n; s.pq = d + 2 * n; s.rr = d + 3 * n; s.thr2 = d + 4 * n; s.shift = d + 5 * n;
+    s.rz_new = d; s.pq = d + n; s.rr = d + 2 * n; s.thr2 = d + 3 * n; s.shift = d + 4 * n;
+    for (int k = 0; k < 2; ++k) {
+        s.s_rz[k] = d + (5 + 3 * k) * (size_t)n;
+        s.s_shift[k] = d + (6 + 3 * k) * (size_t)n;
+        s.s_thr2[k] = d + (7 + 3 * k) * (size_t)n;
+    }
     int* i = reinterpret_cast<int*>(base + nd * sizeof(double));
     s.active = i; s.iters = i + n; s.n_active = i + 2 * n;
+    for (int k = 0; k < 2; ++k) {
+        s.s_iters[k] = i + 2 * n + 64 + 2 * k * (size_t)n;
+        s.s_id[k] = i + 2 * n + 64 + (2 * k + 1) * (size_t)n;
+    }
     return s;
 }
 
+// Compaction kernels.  map[j] = old slot of new slot j.
+template <typename T>
+__global__ void k_gather_state(int K, long ld, const int* __restrict__ map, const cplx<T>* __restrict__ x0,
+                               const cplx<T>* __restrict__ r0, const cplx<T>* __restrict__ z0,
+                               const cplx<T>* __restrict__ p0, cplx<T>* __restrict__ x1, cplx<T>* __restrict__ r1,
+                               cplx<T>* __restrict__ z1, cplx<T>* __restrict__ p1) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (k >= K) return;
+    const long o = (long)map[j] * ld + k, n = (long)j * ld + k;
+    x1[n] = x0[o];
+    r1[n] = r0[o];
+    z1[n] = z0[o];
+    p1[n] = p0[o];
+}
+
+__global__ void k_gather_slots(int n, const int* __restrict__ map, const double* __restrict__ rz0,
+                               const double* __restrict__ sh0, const double* __restrict__ th0,
+                               const int* __restrict__ it0, const int* __restrict__ id0, double* __restrict__ rz1,
+                               double* __restrict__ sh1, double* __restrict__ th1, int* __restrict__ it1,
+                               int* __restrict__ id1, int* __restrict__ active) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int o = map[j];
+    rz1[j] = rz0[o];
+    sh1[j] = sh0[o];
+    th1[j] = th0[o];
+    it1[j] = it0[o];
+    id1[j] = id0[o];
+    active[j] = 1;
+}
+
+// Retire slots: Xout[id[o]] = x[o], iters_out[id[o]] = iters[o] for o in list.
+template <typename T>
+__global__ void k_retire(int K, long ld, const int* __restrict__ list, const int* __restrict__ id,
+                         const cplx<T>* __restrict__ x, cplx<T>* __restrict__ xout) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (k >= K) return;
+    const int o = list[j];
+    xout[(long)id[o] * ld + k] = x[(long)o * ld + k];
+}
+
+__global__ void k_retire_iters(int n, const int* __restrict__ list, const int* __restrict__ id,
+                               const int* __restrict__ it, int* __restrict__ iters_out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int o = list[j];
+    iters_out[id[o]] = it[o];
+}
+
+__global__ void k_iota_copy(int n, const double* __restrict__ sh, const double* __restrict__ th,
+                            double* __restrict__ sh1, double* __restrict__ th1, int* __restrict__ id,
+                            int* __restrict__ it) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    sh1[j] = sh[j];
+    th1[j] = th[j];
+    id[j] = j;
+    it[j] = 0;
+}
+
 // Inner batched PCG in precision T on n rows: solves P_c (H - shift) x = b with x0 = 0.
-// sc.shift / sc.thr2 must be filled by the caller.  Returns the number of iterations
-// run; per-row counts are left in sc.iters.
+// sc.shift / sc.thr2 (per row) must be filled by the caller.  The solution of row i is
+// left in the W_XOUT buffer at row i and its iteration count in sc.iters[i].
+// Rows that converge drop out: whenever fewer than 3/4 of the current slots are still
+// active, converged slots retire their solution and the live CG state is gathered
+// into a compact set of slots, so every kernel runs on active rows only.
 template <typename T>
 int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit, ApplyStats& st) {
     const int npw = c.basis.npw, nv = c.nv;
     hipStream_t s = c.stream;
     const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
-    cplx<T>* x = static_cast<cplx<T>*>(c.ws(W_CX, vbytes));
-    cplx<T>* r = static_cast<cplx<T>*>(c.ws(W_CR, vbytes));
-    cplx<T>* z = static_cast<cplx<T>*>(c.ws(W_CZ, vbytes));
-    cplx<T>* p = static_cast<cplx<T>*>(c.ws(W_CP, vbytes));
+    cplx<T>* X[2] = {static_cast<cplx<T>*>(c.ws(W_CX, vbytes)), static_cast<cplx<T>*>(c.ws(W_CX2, vbytes))};
+    cplx<T>* R[2] = {static_cast<cplx<T>*>(c.ws(W_CR, vbytes)), static_cast<cplx<T>*>(c.ws(W_CR2, vbytes))};
+    cplx<T>* Z[2] = {static_cast<cplx<T>*>(c.ws(W_CZ, vbytes)), static_cast<cplx<T>*>(c.ws(W_CZ2, vbytes))};
+    cplx<T>* P[2] = {static_cast<cplx<T>*>(c.ws(W_CP, vbytes)), static_cast<cplx<T>*>(c.ws(W_CP2, vbytes))};
     cplx<T>* q = static_cast<cplx<T>*>(c.ws(W_CQ, vbytes));
+    cplx<T>* xout = static_cast<cplx<T>*>(c.ws(W_XOUT, vbytes));
+    int* dmap = static_cast<int*>(c.ws(W_MAP, (size_t)2 * n * sizeof(int) + 64));
     void* sticks = c.ws(W_STICKS, (size_t)n * sticks_row_bytes(c));
     double2* S = static_cast<double2*>(c.ws(W_S, (size_t)n * nv * sizeof(double2)));
     const int pre = c.opts.precond;
     const T* kin = kin_of<T>(c);
+    int cur = 0, ncur = n;
 
-    launch_cg_init<T>(n, npw, b, ld, x, r, z, kin, sc.shift, n, pre, s);
-    if (pre) project_c<T>(c, z, ld, n, S);
-    PDEP_HIP(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, s));
-    launch_row_dots<T>(n, npw, r, ld, z, ld, sc.rz, sc.rr, s);
+    hipLaunchKernelGGL(k_iota_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, sc.shift, sc.thr2, sc.s_shift[0],
+                       sc.s_thr2[0], sc.s_id[0], sc.s_iters[0]);
+    PDEP_HIP(hipGetLastError());
+    launch_cg_init<T>(n, npw, b, ld, X[0], R[0], Z[0], kin, sc.s_shift[0], n, pre, s);
+    if (pre) project_c<T>(c, Z[0], ld, n, S);
+    PDEP_HIP(hipMemcpyAsync(P[0], Z[0], vbytes, hipMemcpyDeviceToDevice, s));
+    launch_row_dots<T>(n, npw, R[0], ld, Z[0], ld, sc.s_rz[0], sc.rr, s);
     launch_fill_i32(sc.active, n, 1, s);
-    launch_fill_i32(sc.iters, n, 0, s);
     launch_fill_zero(sc.n_active, sizeof(int), s);
-    launch_cg_check(n, sc.rr, sc.thr2, sc.active, sc.iters, sc.rz, nullptr, sc.n_active, 0, s);
+    launch_cg_check(n, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], sc.s_rz[0], nullptr, sc.n_active, 0, s);
     int h_active = 0;
     PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
     PDEP_HIP(hipStreamSynchronize(s));
+    std::vector<int> flags, keep, ret;
+    // retire the slots in `list` (host) of set `cur`
+    auto retire = [&](const std::vector<int>& list) {
+        if (list.empty()) return;
+        const int nr = (int)list.size();
+        PDEP_HIP(hipMemcpyAsync(dmap + n, list.data(), nr * sizeof(int), hipMemcpyHostToDevice, s));
+        {
+            ProfScope prof_(K_MISC, s, 2.0 * nr * npw * sizeof(cplx<T>));
+            hipLaunchKernelGGL(k_retire<T>, dim3((npw + 255) / 256, nr), dim3(256), 0, s, npw, ld, dmap + n,
+                               sc.s_id[cur], X[cur], xout);
+            hipLaunchKernelGGL(k_retire_iters, dim3((nr + 255) / 256), dim3(256), 0, s, nr, dmap + n, sc.s_id[cur],
+                               sc.s_iters[cur], sc.iters);
+        }
+        PDEP_HIP(hipGetLastError());
+    };
     int it = 0;
     const int poll = 4;
     while (h_active > 0 && it < maxit) {
+        if (h_active < ncur && (4 * h_active < 3 * ncur)) {
+            // compact: retire converged slots, gather live state into the other set
+            flags.resize(ncur);
+            PDEP_HIP(hipMemcpyAsync(flags.data(), sc.active, ncur * sizeof(int), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipStreamSynchronize(s));
+            keep.clear();
+            ret.clear();
+            for (int j = 0; j < ncur; ++j) (flags[j] ? keep : ret).push_back(j);
+            retire(ret);
+            const int nk = (int)keep.size();
+            PDEP_HIP(hipMemcpyAsync(dmap, keep.data(), nk * sizeof(int), hipMemcpyHostToDevice, s));
+            const int nxt = 1 - cur;
+            {
+                ProfScope prof_(K_MISC, s, 8.0 * nk * npw * sizeof(cplx<T>));
+                hipLaunchKernelGGL(k_gather_state<T>, dim3((npw + 255) / 256, nk), dim3(256), 0, s, npw, ld, dmap,
+                                   X[cur], R[cur], Z[cur], P[cur], X[nxt], R[nxt], Z[nxt], P[nxt]);
+                hipLaunchKernelGGL(k_gather_slots, dim3((nk + 255) / 256), dim3(256), 0, s, nk, dmap, sc.s_rz[cur],
+                                   sc.s_shift[cur], sc.s_thr2[cur], sc.s_iters[cur], sc.s_id[cur], sc.s_rz[nxt],
+                                   sc.s_shift[nxt], sc.s_thr2[nxt], sc.s_iters[nxt], sc.s_id[nxt], sc.active);
+            }
+            PDEP_HIP(hipGetLastError());
+            PDEP_HIP(hipStreamSynchronize(s));   // keep / ret host vectors are reused
+            cur = nxt;
+            ncur = nk;
+        }
         const int nstep = std::min(poll, maxit - it);
+        cplx<T> *x = X[cur], *r = R[cur], *z = Z[cur], *p = P[cur];
+        double* rz = sc.s_rz[cur];
+        double* sh = sc.s_shift[cur];
         for (int k = 0; k < nstep; ++k) {
-            apply_op<T>(c, p, q, ld, n, sc.shift, n, true, sticks, S);
+            apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
             st.op_applications++;
-            launch_row_dots<T>(n, npw, p, ld, q, ld, sc.pq, nullptr, s);
-            launch_cg_step1<T>(n, npw, x, r, z, p, q, ld, sc.rz, sc.pq, sc.active, kin, sc.shift, n, pre, s);
-            if (pre) project_c<T>(c, z, ld, n, S);
-            launch_row_dots<T>(n, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
-            launch_cg_step2<T>(n, npw, p, z, ld, sc.rz_new, sc.rz, sc.active, s);
+            launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
+            launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, sc.active, kin, sh, ncur, pre, s);
+            if (pre) project_c<T>(c, z, ld, ncur, S);
+            launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
+            launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
-            launch_cg_check(n, sc.rr, sc.thr2, sc.active, sc.iters, sc.rz, sc.rz_new, sc.n_active, 1, s);
+            launch_cg_check(ncur, sc.rr, sc.s_thr2[cur], sc.active, sc.s_iters[cur], rz, sc.rz_new, sc.n_active, 1,
+                            s);
         }
         it += nstep;
         PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
         PDEP_HIP(hipStreamSynchronize(s));
     }
+    // retire everything that is left (converged or at the iteration cap)
+    std::vector<int> all(ncur);
+    for (int j = 0; j < ncur; ++j) all[j] = j;
+    retire(all);
+    PDEP_HIP(hipStreamSynchronize(s));
     return it;
 }
 
-template <typename T> cplx<T>* cg_solution(Ctx& c) { return c.w[W_CX].as<cplx<T>>(); }
+template <typename T> cplx<T>* cg_solution(Ctx& c) { return c.w[W_XOUT].as<cplx<T>>(); }
 
 }  // namespace
 
@@ -216,7 +352,9 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
             invscale[j] = rn;
             shift[j] = c.eps[i % nv];
             if (mixed) {
-                thr2[j] = c.opts.inner_tol * c.opts.inner_tol;
+                // reduce by inner_tol per step, but no further than the final target needs
+                const double t = std::max(c.opts.inner_tol, 0.5 * tol * std::sqrt(bb[i]) / rn);
+                thr2[j] = t * t;
             } else {
                 const double t = 0.5 * tol * std::sqrt(bb[i]) / rn;
                 thr2[j] = std::max(t * t, 1e-30);
@@ -320,7 +458,7 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
                                         s);
         launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, nrow, b64, ld, EPI_SCALE, -1.0, nullptr, 0, nullptr,
                                         nullptr, 0, nullptr, s);
-        double* ref2 = static_cast<double*>(c.ws(W_DN + 1, (size_t)nrow * sizeof(double)));
+        double* ref2 = static_cast<double*>(c.ws(W_REF2, (size_t)nrow * sizeof(double)));
         launch_row_dots<double>(nrow, npw, b64, ld, b64, ld, ref2, nullptr, s);
         project_c<double>(c, b64, ld, nrow, S);
         PDEP_HIP(hipStreamSynchronize(s));
