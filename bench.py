@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=12)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this size 3 times (reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path would shard by "
@@ -165,6 +168,14 @@ def main():
             log(f"  {kname:20s} {rec['ms']:10.2f} ms  {rec['launches']:7d} launches  "
                 f"{rec['bytes'] / max(rec['ms'], 1e-9) / 1e6:8.1f} GB/s  {rec['flops'] / max(rec['ms'], 1e-9) / 1e9:8.2f} TF/s")
     kname, roof = dominant_roofline(prof, 8)
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written per copy")
+        del src, dst
 
     # ---- FP64 path on the same block (speedup and the 1e-6 eigenvalue check)
     fp64 = None
