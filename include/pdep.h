@@ -189,6 +189,71 @@ int pdep_destroy(pdep_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
 const char* pdep_last_error(void);
 
+/* ------------------------------------------------------------------ serving ------
+ * A server runs PDEP jobs (setup + pdep_eigs) submitted from any thread.  Jobs are
+ * admitted in submission order while the sum of the HBM estimates of running jobs stays
+ * within the server budget and fewer than max_running jobs run; each running job has
+ * its own HIP stream and stream-ordered device memory, so jobs admitted while others
+ * run overlap on the device.  Results stay in the server until polled; a job's
+ * failure (any pdep_status) does not affect the others. */
+typedef struct pdep_server pdep_server;
+
+#define PDEP_SERVER_FAKE 1u   /* test hook: no GPU work; each job sleeps for
+                                 fake_ms_per_gb * (HBM estimate in GB) and returns
+                                 eps_i = 1 + (seed % 97 + 1) / (i + 1) */
+
+typedef struct {
+    int max_running;          /* jobs on the GPU at once (>= 1) */
+    size_t hbm_budget;        /* bytes for running jobs; 0 = 80 % of free device memory */
+    int queue_capacity;       /* queued jobs beyond this -> PDEP_EBUSY (0 = 1024) */
+    uint32_t flags;           /* PDEP_SERVER_FAKE */
+    double fake_ms_per_gb;    /* fake executor run time per GB of estimate */
+} pdep_server_opts;
+
+typedef struct {
+    pdep_cell cell;
+    const double* vloc;       /* N_g doubles, host; copied by pdep_submit */
+    pdep_opts opts;           /* stream, alloc and flags are set by the server */
+    int n_pdep;
+    uint64_t seed;            /* start block of pdep_eigs (library generator) */
+    pdep_eig_opts eig;
+} pdep_job;
+
+enum { PDEP_JOB_QUEUED = 0, PDEP_JOB_RUNNING = 1, PDEP_JOB_DONE = 2, PDEP_JOB_FAILED = 3 };
+
+typedef struct {
+    int status;               /* pdep_status of the finished job (PDEP_OK when DONE) */
+    int n_pdep;
+    int eig_iterations;
+    double gap;               /* HOMO-LUMO gap of the job's ground state (Ha) */
+    double queue_ms;          /* submit -> start */
+    double run_ms;            /* start -> finish */
+    double latency_ms;        /* submit -> finish */
+    size_t hbm_estimate;      /* bytes reserved by admission */
+} pdep_job_result;
+
+typedef struct {
+    int queued, running, done, failed;
+    size_t committed_bytes;       /* HBM estimates of the running jobs */
+    size_t peak_committed_bytes;  /* maximum of committed_bytes so far */
+    int peak_running;
+} pdep_server_stats;
+
+int pdep_server_create(const pdep_server_opts* o, pdep_server** out);
+/* Queue a job; *ticket identifies it.  PDEP_EINVAL for a bad job (checked here),
+ * PDEP_ENOMEM if its estimate exceeds the whole budget, PDEP_EBUSY if the queue is full. */
+int pdep_submit(pdep_server* s, const pdep_job* job, uint64_t* ticket);
+/* Non-blocking.  *state is PDEP_JOB_*; when DONE, res and up to eps_cap dielectric
+ * eigenvalues (descending) are filled; when FAILED, res->status holds the error and
+ * pdep_last_error() its message.  PDEP_ENOTFOUND for an unknown ticket.  res / eps_out
+ * may be NULL. */
+int pdep_poll(pdep_server* s, uint64_t ticket, int* state, pdep_job_result* res, double* eps_out, int eps_cap);
+/* Block until the job is DONE or FAILED or timeout_ms passes (< 0: no limit). */
+int pdep_server_wait(pdep_server* s, uint64_t ticket, double timeout_ms, int* state);
+int pdep_server_stats_get(pdep_server* s, pdep_server_stats* st);
+/* Stop admitting, drop queued jobs, wait for running ones, free everything. */
+int pdep_server_destroy(pdep_server* s);
+
 /* Kernel timing (instrumentation, process-wide).  While enabled, every kernel launch
  * of the library is bracketed by two HIP events recorded on its launch stream.
  * pdep_profile_read returns, per kernel class k < max_kernels, the summed device time

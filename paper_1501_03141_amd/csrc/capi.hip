@@ -113,8 +113,17 @@ void pdep_default_opts(pdep_opts* o) {
 
 const char* pdep_last_error(void) { return g_err.c_str(); }
 
+void pdep_set_error_message(const char* m) { g_err = m ? m : ""; }
+
 int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts, const double* psi_in,
                const double* eps_in, pdep_ctx** out) {
+    return pdep::setup_context(cell, vloc, opts, psi_in, eps_in, nullptr, out);
+}
+
+}  // extern "C"
+
+int pdep::setup_context(const pdep_cell* cell, const double* vloc, const pdep_opts* opts, const double* psi_in,
+                        const double* eps_in, void* blas, pdep_ctx** out) {
     if (out) *out = nullptr;
     pdep_ctx* ctx = nullptr;
     API_BEGIN
@@ -127,6 +136,8 @@ int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
     PDEP_REQUIRE((psi_in == nullptr) == (eps_in == nullptr), PDEP_EINVAL, "psi_in and eps_in go together");
     ctx = new pdep_ctx();
     Ctx& c = ctx->c;
+    c.blas = blas;
+    c.own_blas = false;
     c.opts = *opts;
     c.al.a = opts->alloc;
     c.stream = static_cast<hipStream_t>(opts->stream);
@@ -177,6 +188,8 @@ int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
     g_err.clear();
     return PDEP_OK;
 }
+
+extern "C" {
 
 int pdep_get_info(pdep_ctx* ctx, pdep_info* info) {
     API_BEGIN

@@ -84,24 +84,33 @@ struct SplitMix64 {
     }
 };
 
+// rocBLAS handle for rocSOLVER calls: the context's (created on first use and kept for
+// the context's lifetime, or supplied by the server worker), bound to the context stream.
 struct Solver {
     rocblas_handle h = nullptr;
-    explicit Solver(hipStream_t s) {
-        if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(PDEP_EDEVICE, "rocblas_create_handle failed");
-        rocblas_set_stream(h, s);
-    }
-    ~Solver() {
-        if (h) rocblas_destroy_handle(h);
+    explicit Solver(Ctx& c) {
+        if (!c.blas) {
+            rocblas_handle nh = nullptr;
+            if (rocblas_create_handle(&nh) != rocblas_status_success)
+                throw Error(PDEP_EDEVICE, "rocblas_create_handle failed");
+            c.blas = nh;
+            c.own_blas = true;
+        }
+        h = static_cast<rocblas_handle>(c.blas);
+        rocblas_set_stream(h, c.stream);
     }
 };
 
-enum DSlot { D_V = 0, D_AV, D_X, D_AX, D_R, D_T, D_T2, D_M, D_W, D_TH, D_INFO, D_ROWS, D_COUNT };
+enum DSlot { D_V = 0, D_AV, D_X, D_AX, D_R, D_T, D_T2, D_M, D_W, D_TH, D_INFO, D_ROWS, D_SPLIT, D_COUNT };
 
 struct Workspace {
     Ctx& c;
     Buf b[D_COUNT];
     explicit Workspace(Ctx& cc) : c(cc) {}
     void* get(int i, size_t bytes) { b[i].ensure(&c.al, bytes); return b[i].get(); }
+    // split-K partial products for the projected-matrix GEMMs
+    static constexpr size_t kSplitElems = (size_t)4 << 20;
+    double2* split() { return static_cast<double2*>(get(D_SPLIT, kSplitElems * sizeof(double2))); }
 };
 
 // Host copy of S[n][m] (double2, N x M, ld lds) -> complex vector.
@@ -155,7 +164,8 @@ void dense_eig(Workspace& ws, Solver& sv, std::vector<double2>& A, int m, bool r
         PDEP_HIP(hipStreamSynchronize(s));
     }
     int info = 0;
-    PDEP_HIP(hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost));
+    PDEP_HIP(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    PDEP_HIP(hipStreamSynchronize(s));
     PDEP_REQUIRE(info == 0, PDEP_EDEVICE, "dense eigensolver did not converge");
 }
 
@@ -224,7 +234,7 @@ int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, d
         if (m > 0) {
             double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
             for (int pass = 0; pass < 2; ++pass) {
-                launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, Cdev, m, nullptr, 0, s);   // C[j][i] = <V_i, T_j>
+                launch_gemm_ahb<double>(m, nt, npw, V, ld, T, ld, Cdev, m, ws.split(), Workspace::kSplitElems, s);   // C[j][i] = <V_i, T_j>
                 if (real_coef) {
                     std::vector<double2> C = d2h(Cdev, (size_t)nt * m, s);
                     for (auto& x : C) x.y = 0.0;
@@ -237,7 +247,7 @@ int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, d
             if (nt == 0) break;
         }
         double2* Cdev = static_cast<double2*>(ws.get(D_W, (size_t)std::max(m, nt) * nt * sizeof(double2) + 64));
-        launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, Cdev, nt, nullptr, 0, s);
+        launch_gemm_ahb<double>(nt, nt, npw, T, ld, T, ld, Cdev, nt, ws.split(), Workspace::kSplitElems, s);
         std::vector<double2> G = d2h(Cdev, (size_t)nt * nt, s);
         std::vector<double> w;
         std::vector<double2> Q;
@@ -266,13 +276,17 @@ int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, d
 
 }  // namespace
 
+Ctx::~Ctx() {
+    if (own_blas && blas) rocblas_destroy_handle(static_cast<rocblas_handle>(blas));
+}
+
 // ------------------------------------------------------------------ ground state ---
 void ground_state(Ctx& c) {
     const Basis& b = c.basis;
     const int npw = b.npw, nv = c.nv;
     const long ld = sphere_ld(npw);
     hipStream_t s = c.stream;
-    Solver sv(s);
+    Solver sv(c);
     Workspace ws(c);
     const int want = nv + 1;                       // the LUMO gives the gap
     const int nb = std::min(npw - 1, want + std::max(4, want / 8));
@@ -309,7 +323,7 @@ void ground_state(Ctx& c) {
     bool conv = false;
     double maxres = 0.0;
     for (it = 1; it <= c.opts.gs_maxit; ++it) {
-        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, nullptr, 0, s);
+        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, ws.split(), Workspace::kSplitElems, s);
         std::vector<double2> M = d2h(Cdev, (size_t)m * m, s);
         std::vector<double2> Y;
         dense_eig(ws, sv, M, m, false, theta, Y);
@@ -375,7 +389,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     const int npw = b.npw;
     const long ld = sphere_ld(npw);
     hipStream_t s = c.stream;
-    Solver sv(s);
+    Solver sv(c);
     Workspace ws(c);
     EigResult res;
     const int nb = std::min(npw - 1, npdep + std::max(0, eo.n_buffer));
@@ -429,7 +443,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     double maxres = 0.0;
     int it;
     for (it = 1; it <= eo.maxit; ++it) {
-        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, nullptr, 0, s);
+        launch_gemm_ahb<double>(m, m, npw, V, ld, AV, ld, Cdev, m, ws.split(), Workspace::kSplitElems, s);
         std::vector<double2> M = d2h(Cdev, (size_t)m * m, s);
         std::vector<double2> Y;
         dense_eig(ws, sv, M, m, true, theta, Y);

@@ -13,6 +13,9 @@
 
 #include "../../include/pdep.h"
 
+// capi.hip: sets the calling thread's pdep_last_error() message (internal)
+extern "C" void pdep_set_error_message(const char* m);
+
 namespace pdep {
 
 // ---------------------------------------------------------------- errors --------
@@ -247,6 +250,10 @@ enum WsSlot : int {
 };
 
 struct Ctx {
+    Ctx() = default;
+    Ctx(const Ctx&) = delete;
+    Ctx& operator=(const Ctx&) = delete;
+    ~Ctx();
     pdep_opts opts{};
     Allocator al;
     hipStream_t stream = nullptr;
@@ -263,6 +270,8 @@ struct Ctx {
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic
     // solver work space (grown on demand)
+    void* blas = nullptr;                 // rocblas_handle for rocSOLVER calls
+    bool own_blas = false;
     Buf w[WS_COUNT];
     void* ws(int i, size_t bytes) { w[i].ensure(&al, bytes); return w[i].get(); }
 };
@@ -284,6 +293,14 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
 void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st);
 // chi0bar on S (device, FP64, G0 entry ignored/zero): phi [npert][npw] -> out [npert][npw]
 void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st);
+
+// capi.hip: pdep_setup with an optional caller-owned rocblas_handle (server workers)
+int setup_context(const pdep_cell* cell, const double* vloc, const pdep_opts* opts, const double* psi_in,
+                  const double* eps_in, void* blas, pdep_ctx** out);
+// bytes a job needs on the device (setup + Davidson + one chi0 tile); chi0_budget
+// receives the part reserved for the chi0 work space (the job's opts.hbm_budget)
+size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, const pdep_eig_opts& eo,
+                        size_t* chi0_budget);
 
 // davidson.hip
 void ground_state(Ctx& c);

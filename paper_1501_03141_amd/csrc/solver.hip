@@ -326,7 +326,8 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     for (int i = 0; i < n; ++i) PDEP_REQUIRE(std::isfinite(bb[i]), PDEP_EINVAL, "non-finite right-hand side");
     if (ref2) {
         std::vector<double> w2(n);
-        PDEP_HIP(hipMemcpy(w2.data(), ref2, n * sizeof(double), hipMemcpyDeviceToHost));
+        PDEP_HIP(hipMemcpyAsync(w2.data(), ref2, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        PDEP_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < n; ++i)
             if (bb[i] <= 1e-26 * w2[i]) bb[i] = 0.0;
     }

@@ -87,6 +87,36 @@ class EigStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("max_running", C.c_int), ("hbm_budget", C.c_size_t), ("queue_capacity", C.c_int),
+                ("flags", C.c_uint32), ("fake_ms_per_gb", C.c_double)]
+
+
+class Job(C.Structure):
+    _fields_ = [("cell", Cell), ("vloc", C.c_void_p), ("opts", Opts), ("n_pdep", C.c_int),
+                ("seed", C.c_uint64), ("eig", EigOpts)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_pdep", C.c_int), ("eig_iterations", C.c_int), ("gap", C.c_double),
+                ("queue_ms", C.c_double), ("run_ms", C.c_double), ("latency_ms", C.c_double),
+                ("hbm_estimate", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int), ("running", C.c_int), ("done", C.c_int), ("failed", C.c_int),
+                ("committed_bytes", C.c_size_t), ("peak_committed_bytes", C.c_size_t), ("peak_running", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PDEP_SERVER_FAKE = 1
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -125,6 +155,15 @@ def load(path: str = LIB_PATH):
     lib.pdep_profile_read.restype = C.c_int
     lib.pdep_profile_kernel_name.argtypes = [C.c_int]
     lib.pdep_profile_kernel_name.restype = C.c_char_p
+    lib.pdep_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]
+    lib.pdep_submit.argtypes = [P, C.POINTER(Job), C.POINTER(C.c_uint64)]
+    lib.pdep_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(JobResult), D, C.c_int]
+    lib.pdep_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_int)]
+    lib.pdep_server_stats_get.argtypes = [P, C.POINTER(ServerStats)]
+    lib.pdep_server_destroy.argtypes = [P]
+    for name in ("pdep_server_create", "pdep_submit", "pdep_poll", "pdep_server_wait", "pdep_server_stats_get",
+                 "pdep_server_destroy"):
+        getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
                  "chi0_apply_raw", "pdep_eigs", "pdep_destroy"):
         getattr(lib, name).restype = C.c_int
@@ -322,6 +361,80 @@ class Context:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             _check(self._lib.pdep_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (pdep_server_*): jobs of (cell, V_loc, N_v, N_pdep, seed, options)
+    admitted under an HBM budget and run concurrently on their own streams."""
+
+    def __init__(self, max_running=4, hbm_budget=0, queue_capacity=0, fake=False, fake_ms_per_gb=100.0):
+        self._lib = load()
+        o = ServerOpts(int(max_running), int(hbm_budget), int(queue_capacity),
+                       PDEP_SERVER_FAKE if fake else 0, float(fake_ms_per_gb))
+        self._h = C.c_void_p()
+        _check(self._lib.pdep_server_create(C.byref(o), C.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, L, n, ecut, vloc, n_v, n_pdep, seed=0, precision=PDEP_MIXED_FP32, cg_tol=1e-8,
+               eig_tol=1e-7, eig_maxit=60, n_buffer=0, max_subspace=0, **opt):
+        o = Opts()
+        self._lib.pdep_default_opts(C.byref(o))
+        o.n_v = int(n_v)
+        o.precision = int(precision)
+        o.cg_tol = float(cg_tol)
+        for k, v in opt.items():
+            setattr(o, k, v)
+        v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
+        job = Job(Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut)),
+                  v.ctypes.data, o, int(n_pdep), C.c_uint64(int(seed)),
+                  EigOpts(float(eig_tol), int(eig_maxit), int(max_subspace), int(n_buffer)))
+        t = C.c_uint64()
+        _check(self._lib.pdep_submit(self._h, C.byref(job), C.byref(t)))
+        self._keep[t.value] = int(n_pdep)
+        return t.value
+
+    def poll(self, ticket):
+        """(state, result dict or None, eps or None); never blocks."""
+        st = C.c_int()
+        res = JobResult()
+        n = self._keep.get(ticket, 0)
+        eps = np.empty(max(n, 1), dtype=np.float64)
+        _check(self._lib.pdep_poll(self._h, C.c_uint64(ticket), C.byref(st), C.byref(res),
+                                   eps.ctypes.data_as(C.POINTER(C.c_double)), n))
+        if st.value == JOB_DONE:
+            return st.value, res.as_dict(), eps[:n].copy()
+        if st.value == JOB_FAILED:
+            d = res.as_dict()
+            d["error"] = self._lib.pdep_last_error().decode()
+            return st.value, d, None
+        return st.value, None, None
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        st = C.c_int()
+        _check(self._lib.pdep_server_wait(self._h, C.c_uint64(ticket), float(timeout_ms), C.byref(st)))
+        return st.value
+
+    def stats(self):
+        s = ServerStats()
+        _check(self._lib.pdep_server_stats_get(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.pdep_server_destroy(self._h)
             self._h = C.c_void_p()
 
     def __enter__(self):
