@@ -93,6 +93,58 @@ def cpu_baseline(w, V, eps, psi, phi_host, n_bands: int):
             "seconds": round(dt, 2)}
 
 
+def serving_bench(n_jobs: int, max_running: int, log):
+    """Serving stream of the shape of the paper-scale job mix (grids 24^3/32^3/48^3,
+    N_v 8..128, N_pdep 16..64, wells scaled with the cell volume).  Phase 1 submits all
+    jobs at once to measure capacity (jobs/s); phase 2 replays the stream with Poisson
+    arrivals at 0.8 x capacity and reports latency percentiles."""
+    from paper_1501_03141_amd import inputs, pdep
+
+    def run(jobs, arrivals):
+        lat, ok = [], 0
+        with pdep.Server(max_running=max_running) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for job, ta in zip(jobs, arrivals):
+                dt = ta - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                w = job.workload
+                tickets.append(srv.submit(w.L, w.n, w.ecut, inputs.vloc(w), w.n_v, w.n_pdep, seed=w.seed,
+                                          precision=pdep.PDEP_MIXED_FP32, cg_tol=1e-8, eig_tol=1e-6,
+                                          eig_maxit=60, n_buffer=8, gap_min=1e-4))
+            for job, t in zip(jobs, tickets):
+                srv.wait(t, -1)
+                state, res, _ = srv.poll(t)
+                if state == pdep.JOB_DONE:
+                    ok += 1
+                    lat.append(res["latency_ms"])
+                else:
+                    w = job.workload
+                    log(f"  job {w.name} grid {w.n[0]} N_v {w.n_v} N_pdep {w.n_pdep} failed: "
+                        f"{res.get('error')} ({res['run_ms']:.0f} ms)")
+            wall = time.perf_counter() - t0
+            peak = srv.stats()["peak_running"]
+        return wall, lat, ok, peak
+
+    jobs = inputs.serving_stream(n_jobs, rate_hz=1.0)
+    wall, lat, ok, peak = run(jobs, [0.0] * len(jobs))
+    capacity = ok / wall
+    log(f"serving burst: {ok}/{len(jobs)} jobs in {wall:.1f} s -> capacity {capacity:.2f} jobs/s")
+    rate = 0.8 * capacity
+    jobs2 = inputs.serving_stream(n_jobs, rate_hz=rate, base_seed=2506)
+    arrivals = [j.arrival_s - jobs2[0].arrival_s for j in jobs2]
+    wall2, lat2, ok2, peak2 = run(jobs2, arrivals)
+    log(f"serving stream at {rate:.2f} jobs/s: {ok2}/{len(jobs2)} done in {wall2:.1f} s")
+    return {"jobs": n_jobs, "max_running": max_running, "capacity_jobs_per_s": round(capacity, 3),
+            "offered_rate_jobs_per_s": round(rate, 3), "jobs_per_s": round(ok2 / wall2, 3),
+            "p50_ms": round(float(np.percentile(lat2, 50)), 1) if lat2 else None,
+            "p99_ms": round(float(np.percentile(lat2, 99)), 1) if lat2 else None,
+            "failed": len(jobs2) - ok2, "peak_running": peak2,
+            "sample": f"{n_jobs}-job Poisson stream (grids 24^3/32^3/48^3, N_v 8..128, N_pdep 16..64), "
+                      "mixed precision, Davidson to 1e-6 with 8 buffer vectors"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +154,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=12)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=24, help="0 disables the serving phase")
+    ap.add_argument("--serving-max-running", type=int, default=4)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size 3 times (reference "
                          "kernel for scaling HBM byte counters)")
@@ -197,6 +251,11 @@ def main():
         log("fp64", st64, f"{ms64:.1f} ms; ritz eps err mixed vs fp64 {eps_err:.2e}")
         ctx64.close()
 
+    serving = None
+    if args.serving_jobs > 0:
+        serving = serving_bench(args.serving_jobs, args.serving_max_running, log)
+        log("serving", serving)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, V, eps_occ, psi, phi_host, min(args.cpu_bands, w.n_v))
@@ -230,6 +289,7 @@ def main():
         "dominant_kernel": kname,
         "roofline": roof,
         "kernels": {k: {"ms": round(v["ms"], 2), "launches": v["launches"]} for k, v in prof.items() if v["launches"]},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

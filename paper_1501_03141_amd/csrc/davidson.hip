@@ -125,6 +125,12 @@ std::vector<double2> d2h(const double2* d, size_t n, hipStream_t s) {
 // false) or real symmetric (true; the input is the real part of the complex buffer).
 // On return `vec` holds eigenvectors as columns (column-major, ld m) in complex form
 // (imaginary parts zero for real_sym) and `w` the ascending eigenvalues (host).
+//
+// Divide and conquer (syevd/heevd) first.  rocSOLVER's complex divide and conquer can
+// return non-finite eigenvectors with info = 0 for a (numerically) diagonal input of
+// order above 64, which is exactly what the Gram matrix of an already orthonormal
+// block is; every result is therefore checked and a non-finite one is recomputed by
+// QR iteration (syev/heev) from the kept host copy of the matrix.
 void dense_eig(Workspace& ws, Solver& sv, std::vector<double2>& A, int m, bool real_sym, std::vector<double>& w,
                std::vector<double2>& vec) {
     hipStream_t s = ws.c.stream;
@@ -140,33 +146,64 @@ void dense_eig(Workspace& ws, Solver& sv, std::vector<double2>& A, int m, bool r
     double* dW = static_cast<double*>(ws.get(D_TH, 2 * (size_t)m * sizeof(double) + 64));
     double* dE = dW + m;
     int* dinfo = static_cast<int*>(ws.get(D_INFO, 64));
-    w.assign(m, 0.0);
-    vec.assign((size_t)m * m, make_double2(0, 0));
-    if (real_sym) {
-        std::vector<double> Ar((size_t)m * m);
-        for (size_t i = 0; i < Ar.size(); ++i) Ar[i] = A[i].x;
-        double* dA = static_cast<double*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
-        PDEP_HIP(hipMemcpyAsync(dA, Ar.data(), Ar.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        rocblas_status st = rocsolver_dsyevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo);
-        PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_dsyevd failed");
-        PDEP_HIP(hipMemcpyAsync(Ar.data(), dA, Ar.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    auto solve = [&](bool divide_conquer) -> int {
+        w.assign(m, 0.0);
+        vec.assign((size_t)m * m, make_double2(0, 0));
+        rocblas_status st;
+        if (real_sym) {
+            std::vector<double> Ar((size_t)m * m);
+            for (size_t i = 0; i < Ar.size(); ++i) Ar[i] = A[i].x;
+            double* dA = static_cast<double*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
+            PDEP_HIP(hipMemcpyAsync(dA, Ar.data(), Ar.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            st = divide_conquer
+                     ? rocsolver_dsyevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo)
+                     : rocsolver_dsyev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo);
+            PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_dsyev(d) failed");
+            PDEP_HIP(hipMemcpyAsync(Ar.data(), dA, Ar.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipStreamSynchronize(s));
+            for (size_t i = 0; i < Ar.size(); ++i) vec[i] = make_double2(Ar[i], 0.0);
+        } else {
+            double2* dA = static_cast<double2*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
+            auto* zA = reinterpret_cast<rocblas_double_complex*>(dA);
+            PDEP_HIP(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+            st = divide_conquer
+                     ? rocsolver_zheevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo)
+                     : rocsolver_zheev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo);
+            PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_zheev(d) failed");
+            PDEP_HIP(hipMemcpyAsync(vec.data(), dA, vec.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipStreamSynchronize(s));
+        }
+        int info = 0;
+        PDEP_HIP(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
         PDEP_HIP(hipStreamSynchronize(s));
-        for (size_t i = 0; i < Ar.size(); ++i) vec[i] = make_double2(Ar[i], 0.0);
-    } else {
-        double2* dA = static_cast<double2*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
-        PDEP_HIP(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-        rocblas_status st = rocsolver_zheevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m,
-                                             reinterpret_cast<rocblas_double_complex*>(dA), m, dW, dE, dinfo);
-        PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_zheevd failed");
-        PDEP_HIP(hipMemcpyAsync(vec.data(), dA, vec.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-        PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));
-        PDEP_HIP(hipStreamSynchronize(s));
+        return info;
+    };
+    auto finite = [&]() {
+        for (double x : w)
+            if (!std::isfinite(x)) return false;
+        for (const double2& v : vec)
+            if (!std::isfinite(v.x) || !std::isfinite(v.y)) return false;
+        return true;
+    };
+    int info = solve(true);
+    if (info != 0 || !finite()) info = solve(false);
+    if (info != 0 || !finite()) {
+        double amax = 0.0, herm = 0.0;
+        bool fin = true;
+        for (int n = 0; n < m; ++n)
+            for (int k = 0; k < m; ++k) {
+                const double2 a = A[(size_t)n * m + k], b = A[(size_t)k * m + n];
+                fin = fin && std::isfinite(a.x) && std::isfinite(a.y);
+                amax = std::max(amax, std::hypot(a.x, a.y));
+                herm = std::max(herm, std::hypot(a.x - b.x, a.y + b.y));
+            }
+        throw Error(PDEP_EDEVICE, "dense eigensolver failed (info " + std::to_string(info) + ", n " +
+                                      std::to_string(m) + (real_sym ? ", real" : ", complex") +
+                                      (fin ? ", finite input" : ", NON-FINITE input") + ", max " +
+                                      std::to_string(amax) + ", hermitian defect " + std::to_string(herm) + ")");
     }
-    int info = 0;
-    PDEP_HIP(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
-    PDEP_HIP(hipStreamSynchronize(s));
-    PDEP_REQUIRE(info == 0, PDEP_EDEVICE, "dense eigensolver did not converge");
 }
 
 // Y[j] = sum_i X[i] * C[j][i]  (C host, N x M complex, row j = coefficients of output j)
@@ -274,6 +311,20 @@ int orthonormalise(Ctx& c, Workspace& ws, Solver& sv, const double2* V, int m, d
     return nt;
 }
 
+// Throws PDEP_EDEVICE naming `what` if any of the nrows rows holds a non-finite value.
+void check_finite_rows(Ctx& c, Workspace& ws, const double2* X, int nrows, long ld, const char* what) {
+    if (nrows <= 0) return;
+    double* dn = static_cast<double*>(ws.get(D_TH, 2 * (size_t)nrows * sizeof(double) + 64));
+    launch_row_dots<double>(nrows, c.basis.npw, X, ld, X, ld, dn, nullptr, c.stream);
+    std::vector<double> n2(nrows);
+    PDEP_HIP(hipMemcpyAsync(n2.data(), dn, nrows * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    PDEP_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < nrows; ++i)
+        if (!std::isfinite(n2[i]))
+            throw Error(PDEP_EDEVICE, std::string("non-finite values in ") + what + " (row " + std::to_string(i) +
+                                          " of " + std::to_string(nrows) + ")");
+}
+
 }  // namespace
 
 Ctx::~Ctx() {
@@ -316,7 +367,9 @@ void ground_state(Ctx& c) {
         }
     PDEP_HIP(hipMemcpyAsync(V, h0.data(), h0.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     int m = orthonormalise(c, ws, sv, nullptr, 0, V, nb, ld, false);
+    check_finite_rows(c, ws, V, m, ld, "the orthonormalised start block");
     apply_h64(c, V, ld, m, dzero, 1, AV, ld, sticks);
+    check_finite_rows(c, ws, AV, m, ld, "H applied to the start block");
     const double tol = c.opts.gs_tol;
     std::vector<double> theta, rn(nb);
     int it = 0;
@@ -367,7 +420,9 @@ void ground_state(Ctx& c) {
         const int kept = orthonormalise(c, ws, sv, V, m, T, nt, ld, false);
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        check_finite_rows(c, ws, V + (size_t)m * ld, kept, ld, "the ground-state expansion vectors");
         apply_h64(c, V + (size_t)m * ld, ld, kept, dzero, 1, AV + (size_t)m * ld, ld, sticks);
+        check_finite_rows(c, ws, AV + (size_t)m * ld, kept, ld, "H applied to the expansion vectors");
         m += kept;
     }
     PDEP_REQUIRE(conv, PDEP_ENOTCONV,
@@ -438,6 +493,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     PDEP_REQUIRE(m == nb, PDEP_EINVAL, "start vectors are linearly dependent");
     ApplyStats st;
     chi0bar_sphere(c, m, V, AV, st);
+    check_finite_rows(c, ws, AV, m, ld, "chi0bar applied to the start block");
     res.columns += m;
     std::vector<double> theta;
     double maxres = 0.0;
@@ -483,6 +539,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
         chi0bar_sphere(c, kept, V + (size_t)m * ld, AV + (size_t)m * ld, st);
+        check_finite_rows(c, ws, AV + (size_t)m * ld, kept, ld, "chi0bar applied to the expansion vectors");
         res.columns += kept;
         m += kept;
     }
