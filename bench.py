@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
 
 
 def ritz_eps(phi: np.ndarray, chi_phi: np.ndarray) -> np.ndarray:
@@ -48,17 +48,21 @@ def make_context(w, V, precision, psi=None, eps=None, **kw):
                         psi=psi, eps=eps, device_ptrs=True, **kw)
 
 
-def dominant_roofline(prof: dict, dtype_bytes: int):
-    """Roofline object for the kernel class with the largest device time."""
+def dominant_roofline(prof: dict, mfma_dtype: str):
+    """Roofline object for the kernel class with the largest device time.  Matrix-core
+    kernels are priced at the dense peak of the type they run on (bf16 for the BF16x3
+    split, whose three products per product cap algorithmic flops at a third of it)."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     t = rec["ms"] / 1e3
     if rec["flops"] > 0:
         ach = rec["flops"] / t / 1e12
-        peak = MFMA_PEAK_TFLOPS["f32" if dtype_bytes == 8 else "f64"]
-        return name, {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                      "frac": round(ach / peak, 4), "traffic": None,
-                      "avg_launch_ms": round(rec["ms"] / max(rec["launches"], 1), 4),
-                      "launches": rec["launches"]}
+        peak = MFMA_PEAK_TFLOPS[mfma_dtype]
+        r = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+             "frac": round(ach / peak, 4), "traffic": None,
+             "avg_launch_ms": round(rec["ms"] / max(rec["launches"], 1), 4), "launches": rec["launches"]}
+        if mfma_dtype == "bf16":
+            r["peak_algorithmic_bf16x3"] = round(peak / 3, 1)
+        return name, r
     ach = rec["bytes"] / t / 1e9
     return name, {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -154,6 +158,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=12)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--precision", choices=["bf16x3", "mixed_fp32"], default="bf16x3",
+                    help="mixed mode of the timed steps (the other one is timed once beside it)")
+    ap.add_argument("--no-other-mode", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=24, help="0 disables the serving phase")
     ap.add_argument("--serving-max-running", type=int, default=4)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -196,32 +203,43 @@ def main():
     out = torch.empty_like(phi)
     eps_occ, psi = ctx.orbitals()
 
-    # ---- warmup and timed steps (mixed)
-    for _ in range(args.warmup):
-        _, st = ctx.chi0_apply(phi, out=out)
-        log("warmup", st)
-    torch.cuda.synchronize()
-    pdep.profile_read(reset=True)
-    pdep.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        _, st = ctx.chi0_apply(phi, out=out)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pdep.profile_enable(False)
-    prof = pdep.profile_read(reset=True)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    modes = {"mixed_fp32": pdep.PDEP_MIXED_FP32, "bf16x3": pdep.PDEP_MIXED_BF16X3}
+    main_mode = args.precision
+    other_mode = "mixed_fp32" if main_mode == "bf16x3" else "bf16x3"
+    ctx_main = ctx if main_mode == "mixed_fp32" else make_context(w, V, modes[main_mode], psi=psi, eps=eps_occ)
+
+    def run_steps(c, o, steps, warmup, profile):
+        for _ in range(warmup):
+            _, st = c.chi0_apply(phi, out=o)
+            log("warmup", st)
+        torch.cuda.synchronize()
+        if profile:
+            pdep.profile_read(reset=True)
+            pdep.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = []
+        for _ in range(steps):
+            _, st = c.chi0_apply(phi, out=o)
+            sts.append(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pr = None
+        if profile:
+            pdep.profile_enable(False)
+            pr = pdep.profile_read(reset=True)
+        return (t1 - t0) * 1e3 / steps, sts, pr
+
+    # ---- warmup and timed steps (main mixed mode)
+    ms_step, stats, prof = run_steps(ctx_main, out, args.steps, args.warmup, True)
     value = w.n_pdep / (ms_step / 1e3)
     chi_mixed = out.cpu().numpy()
-    log("timed", stats[-1], f"{ms_step:.1f} ms/step")
+    log(f"timed ({main_mode})", stats[-1], f"{ms_step:.1f} ms/step")
     for kname, rec in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
         if rec["launches"]:
             log(f"  {kname:20s} {rec['ms']:10.2f} ms  {rec['launches']:7d} launches  "
                 f"{rec['bytes'] / max(rec['ms'], 1e-9) / 1e6:8.1f} GB/s  {rec['flops'] / max(rec['ms'], 1e-9) / 1e9:8.2f} TF/s")
-    kname, roof = dominant_roofline(prof, 8)
+    kname, roof = dominant_roofline(prof, "bf16" if main_mode == "bf16x3" else "f32")
     if args.copy_probe_mib > 0:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -234,22 +252,31 @@ def main():
     # ---- FP64 path on the same block (speedup and the 1e-6 eigenvalue check)
     fp64 = None
     eps_err = None
+    other = None
     if not args.no_fp64:
         ctx64 = make_context(w, V, pdep.PDEP_FP64, psi=psi, eps=eps_occ)
         out64 = torch.empty_like(phi)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        _, st64 = ctx64.chi0_apply(phi, out=out64)
-        torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - t2) * 1e3
+        ms64, sts64, _ = run_steps(ctx64, out64, 1, 0, False)
+        st64 = sts64[-1]
         chi64 = out64.cpu().numpy()
-        e_mixed = ritz_eps(phi_host, chi_mixed)
         e_fp64 = ritz_eps(phi_host, chi64)
-        eps_err = float(np.max(np.abs(e_mixed - e_fp64)))
+        eps_err = float(np.max(np.abs(ritz_eps(phi_host, chi_mixed) - e_fp64)))
         fp64 = {"ms_per_step": round(ms64, 2), "value": round(w.n_pdep / (ms64 / 1e3), 3),
                 "cg_iter_max": st64["cg_iter_max"], "speedup_mixed_over_fp64": round(ms64 / ms_step, 3)}
-        log("fp64", st64, f"{ms64:.1f} ms; ritz eps err mixed vs fp64 {eps_err:.2e}")
+        log("fp64", st64, f"{ms64:.1f} ms; ritz eps err {main_mode} vs fp64 {eps_err:.2e}")
         ctx64.close()
+        # the other mixed mode, one warm-up and one timed step
+        if not args.no_other_mode:
+            ctx_o = ctx if other_mode == "mixed_fp32" else make_context(w, V, modes[other_mode], psi=psi, eps=eps_occ)
+            out_o = torch.empty_like(phi)
+            ms_o, sts_o, _ = run_steps(ctx_o, out_o, 1, 1, False)
+            err_o = float(np.max(np.abs(ritz_eps(phi_host, out_o.cpu().numpy()) - e_fp64)))
+            other = {"precision": other_mode, "ms_per_step": round(ms_o, 2),
+                     "value": round(w.n_pdep / (ms_o / 1e3), 3), "eps_err_vs_fp64": err_o,
+                     "cg_iter_max": sts_o[-1]["cg_iter_max"], "refine_steps": sts_o[-1]["refine_steps"]}
+            log(f"{other_mode}", sts_o[-1], f"{ms_o:.1f} ms; ritz eps err vs fp64 {err_o:.2e}")
+            if ctx_o is not ctx:
+                ctx_o.close()
 
     serving = None
     if args.serving_jobs > 0:
@@ -260,10 +287,12 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, V, eps_occ, psi, phi_host, min(args.cpu_bands, w.n_v))
         log("cpu baseline", cpu)
+    if ctx_main is not ctx:
+        ctx_main.close()
     ctx.close()
 
     rec = {
-        "metric": "chi0*dV applications/s (mixed FP32+FP64 refinement; eps err vs FP64 <= 1e-6)",
+        "metric": "chi0*dV applications/s (mixed precision + FP64 refinement; eps err vs FP64 <= 1e-6)",
         "value": round(value, 3),
         "unit": "applications/s",
         "n_gpus": 1,
@@ -273,15 +302,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "bf16x3+f32+f64" if main_mode == "bf16x3" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.L[0]:g}x{w.L[1]:g}x{w.L[2]:g} bohr, grid "
                                f"{w.n[0]}x{w.n[1]}x{w.n[2]}, ecut {w.ecut:g} Ha, N_pw {ctx.n_pw}, "
                                f"{w.n_wells} wells, N_v {w.n_v}, N_pdep {w.n_pdep}, seed {w.seed}",
-                   "rhs_per_step": w.n_v * w.n_pdep, "cg_tol": w.cg_tol, "precision": "mixed_fp32"},
+                   "rhs_per_step": w.n_v * w.n_pdep, "cg_tol": w.cg_tol, "precision": main_mode},
         "eps_err_vs_fp64": eps_err,
         "eps_err_ok": (eps_err is not None and eps_err <= 1e-6),
         "fp64": fp64,
+        "other_mixed_mode": other,
         "cg_iter_max": stats[-1]["cg_iter_max"],
         "cg_iter_mean": round(stats[-1]["cg_iter_total"] / max(stats[-1]["n_rhs"], 1), 2),
         "refine_steps": stats[-1]["refine_steps"],

@@ -67,8 +67,12 @@ typedef enum {
 
 typedef enum {
     PDEP_FP64 = 0,        /* every step in FP64 */
-    PDEP_MIXED_FP32 = 1   /* FP32 inner CG (transforms, H, P_c) with FP64 residual
+    PDEP_MIXED_FP32 = 1,  /* FP32 inner CG (transforms, H, P_c) with FP64 residual
                              refinement; FP64 right-hand sides, density, projection */
+    PDEP_MIXED_BF16X3 = 2 /* as PDEP_MIXED_FP32, but the inner P_c GEMMs split each FP32
+                             operand into two bfloat16 parts and sum three bf16 products
+                             with FP32 accumulation (about 16 significant bits); the FP64
+                             refinement restores the requested tolerance */
 } pdep_precision;
 
 #define PDEP_DEVICE_PTRS 1u

@@ -64,9 +64,12 @@ void finish_setup(Ctx& c) {
                                                                            sizeof(double2)));
     pdep::launch_sphere_to_sticks<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nv, nullptr, sticks, s);
     pdep::launch_slab_inv_store<double>(b.dims, b.tables, sticks, nv, c.u64.as<double2>(), nullptr, s);
-    c.psi32.ensure(&c.al, (size_t)nv * npw * sizeof(float2));
+    // FP32 copy with the padded sphere row stride (zero padding): 16-byte aligned rows
+    const long ld32 = pdep::sphere_ld(npw);
+    c.psi32.ensure(&c.al, (size_t)nv * ld32 * sizeof(float2));
+    pdep::launch_fill_zero(c.psi32.get(), (size_t)nv * ld32 * sizeof(float2), s);
     pdep::launch_convert_rows<double, float>(nv, npw, c.psi64.as<double2>(), npw, nullptr, nullptr,
-                                             c.psi32.as<float2>(), npw, s);
+                                             c.psi32.as<float2>(), ld32, s);
     c.eps_dev.ensure(&c.al, (size_t)nv * sizeof(double));
     PDEP_HIP(hipMemcpyAsync(c.eps_dev.get(), c.eps.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
     // residual of the orbitals in use
@@ -129,7 +132,9 @@ int pdep::setup_context(const pdep_cell* cell, const double* vloc, const pdep_op
     API_BEGIN
     PDEP_REQUIRE(cell && vloc && opts && out, PDEP_EINVAL, "null argument");
     PDEP_REQUIRE(opts->n_v >= 1, PDEP_EINVAL, "n_v must be >= 1");
-    PDEP_REQUIRE(opts->precision == PDEP_FP64 || opts->precision == PDEP_MIXED_FP32, PDEP_EINVAL, "bad precision");
+    PDEP_REQUIRE(opts->precision == PDEP_FP64 || opts->precision == PDEP_MIXED_FP32 ||
+                     opts->precision == PDEP_MIXED_BF16X3,
+                 PDEP_EINVAL, "bad precision");
     PDEP_REQUIRE(opts->cg_tol > 0 && opts->cg_tol < 1 && opts->cg_maxit >= 1, PDEP_EINVAL, "bad CG tolerance/cap");
     PDEP_REQUIRE(opts->precision == PDEP_FP64 || (opts->inner_tol > 0 && opts->inner_tol < 1), PDEP_EINVAL,
                  "bad inner tolerance");

@@ -1,0 +1,331 @@
+// The occupied-space projection GEMM pair in the BF16x3 precision mode: FP32 complex
+// operands, each split into a high and a low bfloat16 part (x = hi + lo + O(2^-17 x)),
+// and every product taken as lo*hi + hi*lo + hi*hi on the bf16 matrix cores with FP32
+// accumulation.  The dropped lo*lo term and the residual of the split leave about
+// 16 significant bits per product, so this mode is used only inside the inner solve,
+// whose result is corrected by the FP64 residual refinement.
+//
+// Matrix-core instruction: v_mfma_f32_16x16x32_bf16, one wave.  Lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] (j = 0..7, eight bf16 in
+// four dwords, element j in the low half of dword j / 2 when j is even); result slot
+// i of lane l is D[4 (l / 16) + i][l % 16].
+//
+// Complex products are taken as real ones with interleaved (re, im) storage:
+//   gemm_ahb    S[n][m] = sum_k conj(A[m][k]) B[n][k]: the real row tile of A uses
+//               (a_re, a_im) pairs, the imaginary row tile (-a_im, a_re) pairs, both
+//               dotted with the interleaved B row; both tiles are formed from one load.
+//   gemm_update Y[n][k] += sum_m S[n][m] A[m][k]: the interleaved S row is the left
+//               operand; the right operand has the column tile of Re (pairs
+//               (a_re, -a_im) down the contraction) and of Im (pairs (a_im, a_re)).
+#include <cstdint>
+
+#include "pdep_internal.h"
+
+namespace pdep {
+
+namespace {
+
+typedef float x3_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 x3_bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t x3_u4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (operands are finite)
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Split a pair (x0, x1) into a hi dword (.x) and a lo dword (.y), element 0 in the
+// low half of each.
+__device__ __forceinline__ uint2 split2(float x0, float x1) {
+    const uint32_t h0 = bf16_bits(x0), h1 = bf16_bits(x1);
+    const uint32_t l0 = bf16_bits(x0 - bf16_value(h0)), l1 = bf16_bits(x1 - bf16_value(h1));
+    return make_uint2(h0 | (h1 << 16), l0 | (l1 << 16));
+}
+
+// (a, b) -> (-b, a) on a dword of two bf16
+__device__ __forceinline__ uint32_t rot_neg_first(uint32_t w) { return ((w >> 16) | (w << 16)) ^ 0x00008000u; }
+// (a, b) -> (a, -b)
+__device__ __forceinline__ uint32_t neg_second(uint32_t w) { return w ^ 0x80000000u; }
+// (a, b) -> (b, a)
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+
+__device__ __forceinline__ x3_f4 mma3(const x3_u4& ah, const x3_u4& al, const x3_u4& bh, const x3_u4& bl,
+                                      x3_f4 c) {
+    const x3_bf8 Ah = __builtin_bit_cast(x3_bf8, ah), Al = __builtin_bit_cast(x3_bf8, al);
+    const x3_bf8 Bh = __builtin_bit_cast(x3_bf8, bh), Bl = __builtin_bit_cast(x3_bf8, bl);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, c, 0, 0, 0);
+    return c;
+}
+
+// Four consecutive complex values p[0..3]; entries at or beyond `avail` read as zero.
+__device__ __forceinline__ void load4(const float2* p, int avail, float (&v)[8]) {
+    if (avail >= 4) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        const float4 b = *reinterpret_cast<const float4*>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float2 c = q < avail ? p[q] : make_float2(0.f, 0.f);
+            v[2 * q] = c.x;
+            v[2 * q + 1] = c.y;
+        }
+    }
+}
+
+constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad (conflict-free b128 reads)
+
+// S[n][m] = sum_{k in chunk z} conj(A[m][k]) B[n][k].
+// WM waves along m (32 complex rows each), 4 / WM waves along n (64 rows each).
+// k advances 16 complex (32 real) per step; the B tile goes through LDS (shared by
+// the waves of one n range), the A fragments are loaded by each wave directly.
+// Requires lda, ldb, K-chunk starts multiple of 4 complex (16-byte aligned loads).
+template <int WM>
+__global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
+                                                     const float2* __restrict__ B, long ldb, float2* __restrict__ S,
+                                                     long lds, int kchunk) {
+    constexpr int WN = 4 / WM;
+    constexpr int BMC = 32 * WM, BN = 64 * WN;
+    constexpr int IT = BN / 64;   // B staging items per thread (4 complex each)
+    __shared__ __align__(16) unsigned char Bs[2][BN * kRowB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int m0 = blockIdx.x * BMC, n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    S += (long)blockIdx.z * N * lds;
+    const int lr = lane & 15, lq = lane >> 4;
+
+    x3_f4 acc[2][2][4];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[g][s][c] = x3_f4{0.f, 0.f, 0.f, 0.f};
+
+    float ra[2][8], rb[IT][8];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int m = m0 + 32 * wm + 16 * g + lr;
+            const int k = kc + 4 * lq;
+            const int avail = m < M ? kend - k : 0;
+            load4(A + (long)(m < M ? m : 0) * lda + k, avail, ra[g]);
+        }
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int e = tid + 256 * j;
+            const int n = n0 + (e >> 2), k = kc + 4 * (e & 3);
+            const int avail = n < N ? kend - k : 0;
+            load4(B + (long)(n < N ? n : 0) * ldb + k, avail, rb[j]);
+        }
+    };
+
+    if (kbeg < kend) fetch(kbeg);
+    for (int kc = kbeg; kc < kend; kc += 16) {
+        // stage B (split) in LDS, A fragments in registers
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int e = tid + 256 * j;
+            x3_u4 h, l;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint2 w = split2(rb[j][2 * q], rb[j][2 * q + 1]);
+                h[q] = w.x;
+                l[q] = w.y;
+            }
+            const int off = (e >> 2) * kRowB + (e & 3) * 16;
+            *reinterpret_cast<x3_u4*>(&Bs[0][off]) = h;
+            *reinterpret_cast<x3_u4*>(&Bs[1][off]) = l;
+        }
+        x3_u4 ah[2][2], al[2][2];   // [g][s]
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint2 w = split2(ra[g][2 * q], ra[g][2 * q + 1]);
+                ah[g][0][q] = w.x;
+                al[g][0][q] = w.y;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ah[g][1][q] = rot_neg_first(ah[g][0][q]);
+                al[g][1][q] = rot_neg_first(al[g][0][q]);
+            }
+        }
+        __syncthreads();
+        if (kc + 16 < kend) fetch(kc + 16);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int off = (64 * wn + 16 * c + lr) * kRowB + lq * 16;
+            const x3_u4 bh = *reinterpret_cast<const x3_u4*>(&Bs[0][off]);
+            const x3_u4 bl = *reinterpret_cast<const x3_u4*>(&Bs[1][off]);
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) acc[g][s][c] = mma3(ah[g][s], al[g][s], bh, bl, acc[g][s][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + 32 * wm + 16 * g + 4 * lq + i;
+                const int n = n0 + 64 * wn + 16 * c + lr;
+                if (m < M && n < N) S[(long)n * lds + m] = make_float2(acc[g][0][c][i], acc[g][1][c][i]);
+            }
+}
+
+// Y[n][k] = beta Y[n][k] + alpha sum_m S[n][m] A[m][k].
+// Workgroup tile: 128 rows n (32 per wave) x 64 complex columns k; the contraction
+// advances 16 complex m (32 real) per step.  The A tile (16 m x 64 k) is split into
+// LDS as [k][m] dwords (hi: (hi(re), hi(im)), lo likewise); each wave loads its own
+// S fragments.  Requires lds multiple of 4 complex (16-byte aligned S loads).
+__global__ __launch_bounds__(256) void k_gemm_update_x3(int M, int N, int K, const float2* __restrict__ A,
+                                                        long lda, const float2* __restrict__ S, long lds,
+                                                        float alpha, float beta, float2* __restrict__ Y, long ldy) {
+    constexpr int BK = 64, BNR = 128;
+    __shared__ __align__(16) unsigned char As[2][BK * kRowB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k0 = blockIdx.x * BK, n0 = blockIdx.y * BNR;
+    const int lr = lane & 15, lq = lane >> 4;
+
+    x3_f4 acc[2][4][2];   // [a][b][d]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) acc[a][b][d] = x3_f4{0.f, 0.f, 0.f, 0.f};
+
+    // A staging: thread -> (m row, 4 consecutive k)
+    const int sm = tid >> 4, sk = 4 * (tid & 15);
+    float rs[2][8], ra[8];
+    auto fetch = [&](int mc) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int n = n0 + 32 * wave + 16 * a + lr;
+            const int m = mc + 4 * lq;
+            const int avail = n < N ? M - m : 0;
+            load4(S + (long)(n < N ? n : 0) * lds + m, avail, rs[a]);
+        }
+        const int m = mc + sm, k = k0 + sk;
+        const int avail = m < M ? K - k : 0;
+        load4(A + (long)(m < M ? m : 0) * lda + k, avail, ra);
+    };
+
+    fetch(0);
+    for (int mc = 0; mc < M; mc += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint2 w = split2(ra[2 * q], ra[2 * q + 1]);
+            const int off = (sk + q) * kRowB + sm * 4;
+            *reinterpret_cast<uint32_t*>(&As[0][off]) = w.x;
+            *reinterpret_cast<uint32_t*>(&As[1][off]) = w.y;
+        }
+        x3_u4 sh[2], sl[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint2 w = split2(rs[a][2 * q], rs[a][2 * q + 1]);
+                sh[a][q] = w.x;
+                sl[a][q] = w.y;
+            }
+        __syncthreads();
+        if (mc + 16 < M) fetch(mc + 16);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int off = (16 * b + lr) * kRowB + lq * 16;
+            const x3_u4 wh = *reinterpret_cast<const x3_u4*>(&As[0][off]);
+            const x3_u4 wl = *reinterpret_cast<const x3_u4*>(&As[1][off]);
+            x3_u4 bh[2], bl[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bh[0][q] = neg_second(wh[q]);     // (re, -im): real output column
+                bl[0][q] = neg_second(wl[q]);
+                bh[1][q] = swap_halves(wh[q]);    // (im, re): imaginary output column
+                bl[1][q] = swap_halves(wl[q]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) acc[a][b][d] = mma3(sh[a], sl[a], bh[d], bl[d], acc[a][b][d]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
+                const int k = k0 + 16 * b + lr;
+                if (n < N && k < K) {
+                    float2* y = Y + (long)n * ldy + k;
+                    float2 o = make_float2(alpha * acc[a][b][0][i], alpha * acc[a][b][1][i]);
+                    if (beta != 0.f) {
+                        const float2 old = *y;
+                        o.x += beta * old.x;
+                        o.y += beta * old.y;
+                    }
+                    *y = o;
+                }
+            }
+}
+
+}  // namespace
+
+void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
+                        long lds, float2* work, size_t work_elems, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
+    const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
+    const int BMC = 32 * WM, BN = 64 * (4 / WM);
+    PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
+    dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
+    int splits = 1;
+    const long tiles = (long)grid.x * grid.y;
+    if (work && tiles < 512) {
+        splits = (int)std::min<long>((1024 + tiles - 1) / tiles, std::max(1, K / 256));
+        while (splits > 1 && (size_t)splits * N * lds > work_elems) --splits;
+    }
+    const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
+    if (splits > 1) splits = (K + kchunk - 1) / kchunk;
+    grid.z = splits;
+    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * sizeof(float2),
+                    8.0 * (double)M * N * K);
+    float2* out = splits > 1 ? work : S;
+    if (WM == 1) hipLaunchKernelGGL(k_gemm_ahb_x3<1>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    else if (WM == 2) hipLaunchKernelGGL(k_gemm_ahb_x3<2>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    else hipLaunchKernelGGL(k_gemm_ahb_x3<4>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    PDEP_HIP(hipGetLastError());
+    if (splits > 1) launch_splitk_reduce_f32(M, N, lds, splits, work, S, s);
+}
+
+void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,
+                           double beta, float2* Y, long ldy, hipStream_t s) {
+    if (N <= 0 || K <= 0) return;
+    PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
+                 "gemm_update_x3: leading dimensions must be multiples of 4");
+    PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "gemm_update_x3: N too large");
+    dim3 grid((K + 63) / 64, (N + 127) / 128);
+    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float2) +
+                    (double)N * K * sizeof(float2) * (beta != 0.0 ? 2.0 : 1.0), 8.0 * (double)M * N * K);
+    hipLaunchKernelGGL(k_gemm_update_x3, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha, (float)beta, Y,
+                       ldy);
+    PDEP_HIP(hipGetLastError());
+}
+
+}  // namespace pdep

@@ -436,6 +436,14 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
     }
 }
 
+void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s) {
+    const long tot = (long)N * M;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_splitk_reduce<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds, splits,
+                       P, S);
+    PDEP_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds, double alpha,
                         double beta, cplx<T>* Y, long ldy, hipStream_t s) {

@@ -176,6 +176,14 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds,
                         double alpha, double beta, cplx<T>* Y, long ldy, hipStream_t s);
+// BF16x3 variants of the two GEMMs above for FP32 operands (16 significant bits per
+// product; for the inner solve of the refinement only).  lda/ldb/lds multiples of 4.
+void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
+                        long lds, float2* work, size_t work_elems, hipStream_t s);
+void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,
+                           double beta, float2* Y, long ldy, hipStream_t s);
+// S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)
+void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s);
 // per-row dot products: out[r] = Re <a_r, b_r>, out2[r] = ||a_r||^2 (out2 may be null)
 template <typename T>
 void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>* b, long ldb,
@@ -265,7 +273,7 @@ struct Ctx {
     int gs_iterations = 0;
     double gs_residual = 0.0;
     Buf vloc64, vloc32;                   // [ng] z-major
-    Buf psi64, psi32;                     // [nv][npw] complex
+    Buf psi64, psi32;                     // [nv][npw] complex FP64; [nv][sphere_ld(npw)] FP32
     Buf u64;                              // [nv][ng] complex grids, z-major
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic

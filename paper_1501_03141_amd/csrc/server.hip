@@ -194,7 +194,7 @@ size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, c
     const size_t nb = (size_t)n_pdep + (size_t)std::max(0, eo.n_buffer);
     const size_t mp = std::max<size_t>(eo.max_subspace > 0 ? (size_t)eo.max_subspace : 4 * (size_t)n_pdep, nb + n_pdep);
     const size_t dav = 2 * mp * ld * 16 + 4 * nb * ld * 16 + mp * mp * 16 * 2 + ((size_t)64 << 20);
-    const size_t inner = o.precision == PDEP_MIXED_FP32 ? 8 : 16;
+    const size_t inner = o.precision != PDEP_FP64 ? 8 : 16;
     const size_t row = ld * 16 * 5 + ld * inner * 11 + sticks_row + nv * 16 + 256;
     const size_t per_pert = nv * row + 2 * ng * 8;
     const size_t tile = std::min<size_t>(nb, 16);

@@ -42,6 +42,8 @@ static_assert(W_LAST <= WS_SOLVER_END, "solver work-space slots overlap the othe
 template <typename T> const cplx<T>* psi_of(Ctx& c);
 template <> const double2* psi_of<double>(Ctx& c) { return c.psi64.as<double2>(); }
 template <> const float2* psi_of<float>(Ctx& c) { return c.psi32.as<float2>(); }
+// row strides of the two copies of Psi
+template <typename T> long psi_ld(Ctx& c) { return sizeof(T) == sizeof(float) ? sphere_ld(c.basis.npw) : c.basis.npw; }
 template <typename T> const T* vloc_of(Ctx& c);
 template <> const double* vloc_of<double>(Ctx& c) { return c.vloc64.as<double>(); }
 template <> const float* vloc_of<float>(Ctx& c) { return c.vloc32.as<float>(); }
@@ -59,15 +61,30 @@ size_t sticks_row_bytes(const Ctx& c) {
 
 long sphere_ld(int npw) { return ((long)npw + 63) / 64 * 64; }
 
-// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.  S: work space of nrows * nv double2.
+// Row stride of the projection coefficients S[row][band] (16-byte aligned FP32 rows)
+// and the work space for nrows rows (either precision).
+long coef_ld(int nv) { return ((long)nv + 3) / 4 * 4; }
+size_t coef_bytes(int nv, int nrows) { return (size_t)nrows * coef_ld(nv) * sizeof(double2); }
+
+// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.  S: work space of coef_bytes(nv, nrows).
+// In the BF16x3 mode the FP32 pair runs on the bf16 matrix cores (three products).
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv;
+    const long lds = coef_ld(nv);
     cplx<T>* St = reinterpret_cast<cplx<T>*>(S);
     const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
     cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
-    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), npw, Y, ld, St, nv, work, split_elems, c.stream);
-    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), npw, St, nv, -1.0, 1.0, Y, ld, c.stream);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (c.opts.precision == PDEP_MIXED_BF16X3) {
+            const long lp = sphere_ld(npw);
+            launch_gemm_ahb_x3(nv, nrows, npw, psi_of<T>(c), lp, Y, ld, St, lds, work, split_elems, c.stream);
+            launch_gemm_update_x3(nv, nrows, npw, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
+            return;
+        }
+    }
+    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), Y, ld, St, lds, work, split_elems, c.stream);
+    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream);
 }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
@@ -202,7 +219,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     cplx<T>* xout = static_cast<cplx<T>*>(c.ws(W_XOUT, vbytes));
     int* dmap = static_cast<int*>(c.ws(W_MAP, (size_t)2 * n * sizeof(int) + 64));
     void* sticks = c.ws(W_STICKS, (size_t)n * sticks_row_bytes(c));
-    double2* S = static_cast<double2*>(c.ws(W_S, (size_t)n * nv * sizeof(double2)));
+    double2* S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, n)));
     const int pre = c.opts.precond;
     const T* kin = kin_of<T>(c);
     int cur = 0, ncur = n;
@@ -305,7 +322,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     const int npw = c.basis.npw, nv = c.nv;
     hipStream_t s = c.stream;
     const double tol = c.opts.cg_tol;
-    const bool mixed = c.opts.precision == PDEP_MIXED_FP32;
+    const bool mixed = c.opts.precision != PDEP_FP64;
     const size_t vb64 = (size_t)n * ld * sizeof(double2);
     double2* r64 = static_cast<double2*>(c.ws(W_R64, vb64));
     double2* xa = static_cast<double2*>(c.ws(W_XA, vb64));
@@ -382,7 +399,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         // true FP64 residual of the rows just updated
         launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
         apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, c.ws(W_STICKS, (size_t)na * sticks_row_bytes(c)),
-                         static_cast<double2*>(c.ws(W_S, (size_t)na * nv * sizeof(double2))));
+                         static_cast<double2*>(c.ws(W_S, coef_bytes(nv, na))));
         st.op_applications++;
         launch_sub_rows(na, npw, b64, ld, d_rows, qa, ld, qa, ld, s);
         launch_scatter_rows(na, npw, qa, ld, d_rows, r64, ld, s);
@@ -413,7 +430,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
 namespace {
 
 size_t row_bytes(const Ctx& c, long ld) {
-    const size_t inner = c.opts.precision == PDEP_MIXED_FP32 ? sizeof(float2) : sizeof(double2);
+    const size_t inner = c.opts.precision != PDEP_FP64 ? sizeof(float2) : sizeof(double2);
     return (size_t)ld * sizeof(double2) * 5 + (size_t)ld * inner * 6 + sticks_row_bytes(c) +
            (size_t)c.nv * sizeof(double2) + 128;
 }
@@ -453,7 +470,7 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
         double2* sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));
         double2* b64 = static_cast<double2*>(c.ws(W_B64, (size_t)nrow * ld * sizeof(double2)));
         double2* x64 = static_cast<double2*>(c.ws(W_X64, (size_t)nrow * ld * sizeof(double2)));
-        double2* S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
+        double2* S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow)));
         // right-hand sides b = -P_c Fwd(dV_i u_v)
         launch_slab_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.u64.as<double2>(), nv, nrow, sticks,
                                         s);
@@ -464,7 +481,7 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
         project_c<double>(c, b64, ld, nrow, S);
         PDEP_HIP(hipStreamSynchronize(s));
         solve_rows(c, nrow, b64, x64, ld, st, ref2);
-        S = static_cast<double2*>(c.ws(W_S, (size_t)nrow * nv * sizeof(double2)));
+        S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow)));
         project_c<double>(c, x64, ld, nrow, S);
         // density response
         sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));

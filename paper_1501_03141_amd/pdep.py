@@ -29,6 +29,7 @@ PDEP_EBUSY = -6
 PDEP_ENOTFOUND = -7
 PDEP_FP64 = 0
 PDEP_MIXED_FP32 = 1
+PDEP_MIXED_BF16X3 = 2
 PDEP_DEVICE_PTRS = 1
 
 _NAMES = {0: "PDEP_OK", -1: "PDEP_EINVAL", -2: "PDEP_ENOMEM", -3: "PDEP_ENOTCONV", -4: "PDEP_EGAP",

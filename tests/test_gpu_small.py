@@ -82,7 +82,23 @@ def test_small_pdep_eigs(oracle_small):
     print("oracle residuals", res, "rq err", np.abs(rq - lam))
     assert res.max() <= 1e-7
     assert np.max(np.abs(rq - lam)) <= 1e-10
-    with _ctx(V, gs, precision=pdep.PDEP_MIXED_FP32, cg_tol=1e-8) as c:
-        eps_m, _, _ = c.eigs(W.n_pdep, seed=W.seed, tol=1e-7, maxit=80, n_buffer=8)
-    print("mixed vs fp64 max |d eps|", np.max(np.abs(eps_m - eps)))
-    assert np.max(np.abs(eps_m - eps)) <= 1e-6
+    for prec in (pdep.PDEP_MIXED_FP32, pdep.PDEP_MIXED_BF16X3):
+        with _ctx(V, gs, precision=prec, cg_tol=1e-8) as c:
+            eps_m, _, _ = c.eigs(W.n_pdep, seed=W.seed, tol=1e-7, maxit=80, n_buffer=8)
+        print("mixed mode", prec, "vs fp64 max |d eps|", np.max(np.abs(eps_m - eps)))
+        assert np.max(np.abs(eps_m - eps)) <= 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_small_chi0_bf16x3_parity(oracle_small):
+    """BF16x3 inner products, FP64 refinement to 1e-10: same bar as FP64 mode up to the
+    refinement tolerance (relative 1e-8 per perturbation)."""
+    V, m, gs = oracle_small
+    from paper_1501_03141_amd import pdep
+    phi = inputs.trial_block(m.miller[m.nz], 4, W.seed + 7)
+    want = R.chi0bar_apply(m, gs, phi, method="sos")
+    with _ctx(V, gs, precision=pdep.PDEP_MIXED_BF16X3) as c:
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print("stats", st, "relerr max", err.max())
+    assert err.max() <= 1e-8

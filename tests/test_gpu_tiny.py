@@ -107,12 +107,16 @@ def test_device_pointers_match_host(oracle_tiny):
     assert np.array_equal(dev.cpu().numpy(), host)
 
 
-def test_mixed_precision_parity(oracle_tiny):
+@pytest.mark.parametrize("mode", ["mixed_fp32", "bf16x3"])
+def test_mixed_precision_parity(oracle_tiny, mode):
+    """Both mixed modes refine to the same FP64 residual tolerance, so both meet the
+    same bar against the oracle (BF16x3 only changes the inner P_c products)."""
     V, m, gs, lam, Phi = oracle_tiny
     from paper_1501_03141_amd import pdep
+    prec = {"mixed_fp32": pdep.PDEP_MIXED_FP32, "bf16x3": pdep.PDEP_MIXED_BF16X3}[mode]
     phi = inputs.trial_block(m.miller[m.nz], 5, 105)
     want = R.chi0bar_apply(m, gs, phi)
-    with _ctx(V, gs, precision=pdep.PDEP_MIXED_FP32, cg_tol=1e-10) as c:
+    with _ctx(V, gs, precision=prec, cg_tol=1e-10) as c:
         got, st = c.chi0_apply(phi)
     err = _relerr(got, want)
     print("mixed stats", st, "relerr", err)
@@ -159,10 +163,12 @@ def test_pdep_eigs_seeded_block(oracle_tiny):
     assert np.max(np.abs(eps - want)) <= 1e-10 * want.max()
 
 
-def test_pdep_eigs_mixed_within_1e6(oracle_tiny):
+@pytest.mark.parametrize("mode", ["mixed_fp32", "bf16x3"])
+def test_pdep_eigs_mixed_within_1e6(oracle_tiny, mode):
     V, m, gs, lam, Phi = oracle_tiny
     from paper_1501_03141_amd import pdep
-    with _ctx(V, gs, precision=pdep.PDEP_MIXED_FP32, cg_tol=1e-8) as c:
+    prec = {"mixed_fp32": pdep.PDEP_MIXED_FP32, "bf16x3": pdep.PDEP_MIXED_BF16X3}[mode]
+    with _ctx(V, gs, precision=prec, cg_tol=1e-8) as c:
         eps, _, st = c.eigs(W.n_pdep, seed=7, tol=1e-7, maxit=100, n_buffer=4)
     want = np.sort(1.0 - lam)[::-1]
     assert np.max(np.abs(eps - want)) <= 1e-6
