@@ -133,6 +133,26 @@ void build_basis(const pdep_cell& cell, Basis& b) {
         b.stick_pos[k] = s * b.n[2] + iz;
     }
     b.stick_start.push_back(b.npw);
+    // x columns: for each mx in -mxmax..mxmax the sticks with that mx are consecutive and
+    // cover my = -ymax(mx)..ymax(mx) (the sphere is convex and symmetric)
+    b.col_start.assign(b.ax + 1, -1);
+    b.col_my0.assign(b.ax, 0);
+    const int nsticks = (int)b.stick_start.size() - 1;
+    for (int s = 0; s < nsticks; ++s) {
+        const int k = b.stick_start[s];
+        const int c = b.miller[3 * k] + b.mxmax;
+        if (b.col_start[c] < 0) {
+            b.col_start[c] = s;
+            b.col_my0[c] = b.miller[3 * k + 1];
+        }
+    }
+    b.col_start[b.ax] = nsticks;
+    for (int c = 0; c < b.ax; ++c) {
+        PDEP_REQUIRE(b.col_start[c] >= 0, PDEP_EINVAL, "internal: empty x column in the sphere");
+        const int cnt = (c + 1 < b.ax ? b.col_start[c + 1] : nsticks) - b.col_start[c];
+        PDEP_REQUIRE(b.col_my0[c] <= 0 && cnt == 1 - 2 * b.col_my0[c], PDEP_EINVAL,
+                     "internal: x column of the sphere is not a symmetric my range");
+    }
     FftDims& d = b.dims;
     d.nx = b.n[0];
     d.ny = b.n[1];
@@ -155,6 +175,9 @@ void upload_basis(Basis& b, Allocator* al, hipStream_t s) {
     up(b.d_stick_start, b.stick_start.data(), b.stick_start.size() * sizeof(int));
     up(b.d_stick_pos, b.stick_pos.data(), b.stick_pos.size() * sizeof(int));
     up(b.d_slab_pos, b.slab_pos.data(), b.slab_pos.size() * sizeof(int));
+    std::vector<int> cols(b.col_start);
+    cols.insert(cols.end(), b.col_my0.begin(), b.col_my0.end());
+    up(b.d_cols, cols.data(), cols.size() * sizeof(int));
     up(b.d_kin64, b.kin.data(), b.kin.size() * sizeof(double));
     std::vector<float> k32(b.kin.begin(), b.kin.end());
     up(b.d_kin32, k32.data(), k32.size() * sizeof(float));
@@ -171,6 +194,8 @@ void upload_basis(Basis& b, Allocator* al, hipStream_t s) {
     t.stick_start = b.d_stick_start.as<int>();
     t.stick_pos = b.d_stick_pos.as<int>();
     t.slab_pos = b.d_slab_pos.as<int>();
+    t.col_start = b.d_cols.as<int>();
+    t.col_my0 = b.d_cols.as<int>() + b.ax + 1;
     const double* t64 = b.d_tw64.as<double>();
     const float* t32 = b.d_tw32.as<float>();
     t.twx64 = t64;

@@ -22,6 +22,8 @@
 // sizes are compile-time template parameters (all index arithmetic is then by
 // constants); other sizes use the same code with run-time sizes.  Twiddles come from
 // tables exp(-2 pi i m / n) built in extended precision on the host.
+#include <type_traits>
+
 #include "pdep_internal.h"
 
 namespace pdep {
@@ -99,6 +101,143 @@ template <typename T, int SIGN> struct Dft<T, 8, SIGN> {
         v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
     }
 };
+
+// ------------------------------------------------------- register-resident DFTs ---
+// A whole line of length N held by one thread, transformed with every index and every
+// twiddle a compile-time constant (mixed radix 2/3/4/8, decimation in time).  The
+// twiddles exp(+-2 pi i e / N) are evaluated at compile time: the angle is reduced to
+// the first octant with integer arithmetic and sin / cos come from their Taylor
+// series (Horner form, 13 terms; |x| <= pi/4, error below one unit in the last place
+// of a double).
+
+template <int B, int E, typename F> __device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+struct TwCS { double c, s; };
+constexpr double sin_small(double x) {
+    const double x2 = x * x;
+    double r = 1.0;
+    for (int k = 13; k >= 1; --k) r = 1.0 - x2 / ((2.0 * k) * (2.0 * k + 1.0)) * r;
+    return x * r;
+}
+constexpr double cos_small(double x) {
+    const double x2 = x * x;
+    double r = 1.0;
+    for (int k = 13; k >= 1; --k) r = 1.0 - x2 / ((2.0 * k - 1.0) * (2.0 * k)) * r;
+    return r;
+}
+// exp(2 pi i e / N)
+constexpr TwCS unit_root(int e, int N) {
+    e = ((e % N) + N) % N;
+    const int q = (4 * e) / N, r = (4 * e) % N;   // angle = (pi/2) (q + r / N)
+    const double half_pi = 1.5707963267948966192;
+    double c = 0.0, sn = 0.0;
+    if (2 * r <= N) {
+        const double x = half_pi * r / N;
+        c = cos_small(x);
+        sn = sin_small(x);
+    } else {
+        const double x = half_pi * (N - r) / N;
+        c = sin_small(x);
+        sn = cos_small(x);
+    }
+    for (int i = 0; i < q; ++i) {
+        const double t = c;
+        c = -sn;
+        sn = t;
+    }
+    return TwCS{c, sn};
+}
+
+constexpr int reg_radix(int n) { return (n % 4 == 0 && n > 8) ? 4 : (n % 3 == 0 ? 3 : 2); }
+constexpr bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+// inverse of a modulo m (gcd(a, m) = 1)
+constexpr int inv_mod(int a, int m) {
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
+template <typename T, int SIGN, int N, int IS> __device__ __forceinline__ void dft_reg(const cplx<T>* x, cplx<T>* X);
+
+// Good-Thomas split N = N1 N2 with gcd(N1, N2) = 1: input n = (N2 n1 + N1 n2) mod N and
+// output k = (N2 a k1 + N1 b k2) mod N, a = N2^-1 mod N1, b = N1^-1 mod N2, turn the
+// length-N DFT into an N1 x N2 two-dimensional DFT with no twiddle factors.
+template <typename T, int SIGN, int N1, int N2>
+__device__ __forceinline__ void dft_pfa(const cplx<T>* x, cplx<T>* X) {
+    constexpr int N = N1 * N2;
+    constexpr int a = inv_mod(N2 % N1, N1), b = inv_mod(N1 % N2, N2);
+    cplx<T> Z[N];   // Z[k1 * N2 + n2]: length-N1 DFTs over n1
+    sfor<0, N2>([&](auto n2c) {
+        constexpr int n2 = decltype(n2c)::value;
+        cplx<T> v[N1];
+        sfor<0, N1>([&](auto n1c) {
+            constexpr int n1 = decltype(n1c)::value;
+            v[n1] = x[(N2 * n1 + N1 * n2) % N];
+        });
+        Dft<T, N1, SIGN>::run(v);
+        sfor<0, N1>([&](auto k1c) {
+            constexpr int k1 = decltype(k1c)::value;
+            Z[k1 * N2 + n2] = v[k1];
+        });
+    });
+    sfor<0, N1>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        cplx<T> Y[N2];
+        dft_reg<T, SIGN, N2, 1>(Z + k1 * N2, Y);
+        sfor<0, N2>([&](auto k2c) {
+            constexpr int k2 = decltype(k2c)::value;
+            X[(N2 * a * k1 + N1 * b * k2) % N] = Y[k2];
+        });
+    });
+}
+
+// X[k] = sum_n x[n * IS] exp(SIGN 2 pi i n k / N), k = 0..N-1.
+template <typename T, int SIGN, int N, int IS>
+__device__ __forceinline__ void dft_reg(const cplx<T>* x, cplx<T>* X) {
+    if constexpr (IS == 1 && N % 3 == 0 && N > 3 && pow2(N / 3)) {
+        dft_pfa<T, SIGN, 3, N / 3>(x, X);
+    } else if constexpr (N == 1) {
+        X[0] = x[0];
+    } else if constexpr (N == 2 || N == 3 || N == 4 || N == 8) {
+        cplx<T> v[N];
+        sfor<0, N>([&](auto n) { v[decltype(n)::value] = x[decltype(n)::value * IS]; });
+        Dft<T, N, SIGN>::run(v);
+        sfor<0, N>([&](auto k) { X[decltype(k)::value] = v[decltype(k)::value]; });
+    } else {
+        constexpr int R = reg_radix(N);
+        constexpr int M = N / R;
+        // n = n1 + R n2: length-M transforms of the R decimated sequences, then
+        // twiddles exp(SIGN 2 pi i n1 k1 / N) and radix-R butterflies.
+        cplx<T> Y[N];
+        sfor<0, R>([&](auto n1c) {
+            constexpr int n1 = decltype(n1c)::value;
+            dft_reg<T, SIGN, M, IS * R>(x + n1 * IS, Y + n1 * M);
+        });
+        sfor<0, M>([&](auto k1c) {
+            constexpr int k1 = decltype(k1c)::value;
+            cplx<T> v[R];
+            sfor<0, R>([&](auto n1c) {
+                constexpr int n1 = decltype(n1c)::value;
+                if constexpr ((n1 * k1) % N == 0) {
+                    v[n1] = Y[n1 * M + k1];
+                } else {
+                    constexpr TwCS w = unit_root(SIGN * n1 * k1, N);
+                    v[n1] = cmul(Y[n1 * M + k1], mk<T>((T)w.c, (T)w.s));
+                }
+            });
+            Dft<T, R, SIGN>::run(v);
+            sfor<0, R>([&](auto k2c) {
+                constexpr int k2 = decltype(k2c)::value;
+                X[k1 + M * k2] = v[k2];
+            });
+        });
+    }
+}
 
 // Line l of a transform starts at LDS offset ((lo + l) mod m) * ls.
 struct LineMap {
@@ -415,6 +554,113 @@ __global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cpl
     }
 }
 
+// Slab pass of H (V multiply), FP32, NX = NY = NL, with every line in registers: a
+// workgroup of 256 threads (four waves) takes ZG = 256 / NL consecutive z slabs of one
+// row.  Lines are read at clamped indices and masked afterwards, so the loads of a
+// line issue back to back.
+//   1. the ZG stick rows are copied to LDS (coalesced);
+//   2. one thread per (slab, non-empty x column), packed into the first ZG * ax
+//      threads: its y line from the stick row (zeros outside the column's my range),
+//      inverse y DFT, written to the transpose plane [slab][iy][column];
+//   3. one thread per (slab, iy): its x line (zeros at empty columns), inverse x DFT,
+//      times V(z, x, y), forward x DFT, non-empty columns written back;
+//   4. one thread per (slab, column): forward y DFT, the column's my range written to
+//      the stick row;
+//   5. stick rows copied back.
+// The stick rows and the transpose plane share LDS: every thread holds its line in
+// registers across the barrier that separates reading one from writing the other.
+template <int NL>
+__global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, float2* __restrict__ sticks,
+                                                     const float* __restrict__ Vr) {
+    constexpr int ZG = 256 / NL;
+    constexpr int HALF = (NL + 1) / 2;   // index i holds frequency i (i < HALF) or i - NL
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2* lds = reinterpret_cast<float2*>(smem);
+    const int ax = d.ax, mxmax = d.mxmax, sld = d.sld, nz = d.nz;
+    const int axp = ax | 1;
+    const int z0 = blockIdx.x * ZG, row = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int zl = tid / NL, li = tid - zl * NL;   // x passes: (slab, iy)
+    const int zc = tid / ax, lc = tid - zc * ax;   // y passes: (slab, column)
+    const int nzh = min(ZG, nz - z0);
+    const bool zact = zl < nzh && zl < ZG;
+    const bool col = zc < nzh;
+    float2* g = sticks + ((long)row * nz + z0) * sld;
+    const int ns = d.ns;
+    for (int zz = 0; zz < nzh; ++zz)
+        for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+    __syncthreads();
+
+    int s0 = 0, my0 = 0;
+    float2 v[NL], X[NL];
+    if (col) {
+        s0 = t.col_start[lc];
+        my0 = t.col_my0[lc];
+        const float2* sr = lds + zc * sld + s0 - my0;
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int my = i < HALF ? i : i - NL;
+            const float2 val = sr[min(max(my, my0), -my0)];
+            v[i] = (my >= my0 && my <= -my0) ? val : make_float2(0.f, 0.f);
+        });
+    }
+    __syncthreads();
+    float2* tp = lds + (long)zl * NL * axp;     // transpose plane of the x-pass slab: [iy][column]
+    float2* tc = lds + (long)zc * NL * axp;     // transpose plane of the y-pass slab
+    if (col) {
+        dft_reg<float, +1, NL, 1>(v, X);
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            tc[i * axp + lc] = X[i];
+        });
+    }
+    __syncthreads();
+    if (zact) {
+        const float2* tr = tp + li * axp + mxmax;
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int mx = i < HALF ? i : i - NL;
+            const float2 val = tr[min(max(mx, -mxmax), mxmax)];
+            v[i] = (mx >= -mxmax && mx <= mxmax) ? val : make_float2(0.f, 0.f);
+        });
+        dft_reg<float, +1, NL, 1>(v, X);
+        const float* vz = Vr + (long)(z0 + zl) * NL * NL + li;
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const float vv = vz[i * NL];
+            X[i].x *= vv;
+            X[i].y *= vv;
+        });
+        dft_reg<float, -1, NL, 1>(X, v);
+        float2* tw = tp + li * axp + mxmax;
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int mx = i < HALF ? i : i - NL;
+            if (mx >= -mxmax && mx <= mxmax) tw[mx] = v[i];
+        });
+    }
+    __syncthreads();
+    if (col) {
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            v[i] = tc[i * axp + lc];
+        });
+    }
+    __syncthreads();
+    if (col) {
+        dft_reg<float, -1, NL, 1>(v, X);
+        float2* sw = lds + zc * sld + s0 - my0;
+        sfor<0, NL>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int my = i < HALF ? i : i - NL;
+            if (my >= my0 && my <= -my0) sw[my] = X[i];
+        });
+    }
+    __syncthreads();
+    for (int zz = 0; zz < nzh; ++zz)
+        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+}
+
 constexpr int kMaxAcc = 24;
 
 // Density: dn_i(z, x, y) = scale * Re sum_v conj(u_v(z, x, y)) Inv(sticks[i * nv + v])(z, x, y).
@@ -594,11 +840,38 @@ void launch_slab(const FftDims& d, const BasisTables& t, int nrows, cplx<T>* sti
 
 }  // namespace
 
+// LDS of the register slab kernel for line length nl (0 if it does not apply).
+size_t slab_reg_lds(const FftDims& d, int nl) {
+    if (d.nx != d.ny || d.nx != nl) return 0;
+    const int zg = 256 / nl;
+    const size_t elems = std::max((size_t)zg * d.sld, (size_t)zg * nl * (size_t)(d.ax | 1));
+    const size_t bytes = elems * sizeof(float2);
+    return bytes <= 65536 ? bytes : 0;
+}
+
 template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s) {
     const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
-    launch_slab<T, SLAB_HV>(d, t, nrows, sticks, Vz, nullptr, 1, nullptr, nullptr, s, K_SLAB_HV,
-                            (double)nrows * 2.0 * sk + (double)d.nx * d.ny * d.nz * sizeof(T));
+    const double bytes = (double)nrows * 2.0 * sk + (double)d.nx * d.ny * d.nz * sizeof(T);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        bool done = false;
+        with_n(d.nx, [&]<int N>() {
+            if constexpr (N > 0 && N <= 48) {
+                const size_t lds = slab_reg_lds(d, N);
+                if (lds > 0 && nrows > 0) {
+                    check_rows(nrows);
+                    constexpr int ZG = 256 / N;
+                    ProfScope prof_(K_SLAB_HV, s, bytes);
+                    hipLaunchKernelGGL((k_slab_hv_reg<N>), dim3((d.nz + ZG - 1) / ZG, nrows), dim3(256), lds, s, d,
+                                       t, sticks, Vz);
+                    PDEP_HIP(hipGetLastError());
+                    done = true;
+                }
+            }
+        });
+        if (done || nrows <= 0) return;
+    }
+    launch_slab<T, SLAB_HV>(d, t, nrows, sticks, Vz, nullptr, 1, nullptr, nullptr, s, K_SLAB_HV, bytes);
 }
 
 template <typename T>

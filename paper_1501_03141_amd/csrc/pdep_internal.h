@@ -124,6 +124,8 @@ struct BasisTables {
     const int* stick_start;   // [ns + 1] first sphere index of each stick
     const int* stick_pos;     // [npw]    stick * nz + (mz mod nz)
     const int* slab_pos;      // [ns]     (mx mod nx) * ny + (my mod ny)
+    const int* col_start;     // [ax + 1] first stick of each non-empty x column c = mx + mxmax
+    const int* col_my0;       // [ax]     my of that stick (the column spans my0 .. -my0)
     const double* twx64; const double* twy64; const double* twz64;  // n complex each: exp(-2 pi i m / n)
     const float* twx32; const float* twy32; const float* twz32;
 };
@@ -237,10 +239,10 @@ struct Basis {
     int g0;                               // index of G = 0 in S
     int ax, mxmax;
     std::vector<int32_t> miller;          // 3 * npw
-    std::vector<int> stick_start, stick_pos, slab_pos;
+    std::vector<int> stick_start, stick_pos, slab_pos, col_start, col_my0;
     std::vector<double> kin, coul;        // coul[g0] = 0
     FftDims dims{};
-    Buf d_stick_start, d_stick_pos, d_slab_pos, d_kin64, d_kin32, d_coul, d_tw64, d_tw32;
+    Buf d_stick_start, d_stick_pos, d_slab_pos, d_cols, d_kin64, d_kin32, d_coul, d_tw64, d_tw32;
     BasisTables tables{};
 };
 
