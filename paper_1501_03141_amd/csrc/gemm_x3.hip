@@ -82,16 +82,16 @@ __device__ __forceinline__ void load4(const float2* p, int avail, float (&v)[8])
 constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad (conflict-free b128 reads)
 
 // S[n][m] = sum_{k in chunk z} conj(A[m][k]) B[n][k].
-// WM waves along m (32 complex rows each), 4 / WM waves along n (64 rows each).
+// WM waves along m (32 complex rows each), 4 / WM waves along n (16 CT rows each).
 // k advances 16 complex (32 real) per step; the B tile goes through LDS (shared by
 // the waves of one n range), the A fragments are loaded by each wave directly.
 // Requires lda, ldb, K-chunk starts multiple of 4 complex (16-byte aligned loads).
-template <int WM>
+template <int WM, int CT>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
                                                      const float2* __restrict__ B, long ldb, float2* __restrict__ S,
                                                      long lds, int kchunk) {
     constexpr int WN = 4 / WM;
-    constexpr int BMC = 32 * WM, BN = 64 * WN;
+    constexpr int BMC = 32 * WM, BN = 16 * CT * WN;
     constexpr int IT = BN / 64;   // B staging items per thread (4 complex each)
     __shared__ __align__(16) unsigned char Bs[2][BN * kRowB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -102,13 +102,13 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
     S += (long)blockIdx.z * N * lds;
     const int lr = lane & 15, lq = lane >> 4;
 
-    x3_f4 acc[2][2][4];
+    x3_f4 acc[2][2][CT];
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[g][s][c] = x3_f4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < CT; ++c) acc[g][s][c] = x3_f4{0.f, 0.f, 0.f, 0.f};
 
     float ra[2][8], rb[IT][8];
     auto fetch = [&](int kc) {
@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
         __syncthreads();
         if (kc + 16 < kend) fetch(kc + 16);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int off = (64 * wn + 16 * c + lr) * kRowB + lq * 16;
+        for (int c = 0; c < CT; ++c) {
+            const int off = (16 * CT * wn + 16 * c + lr) * kRowB + lq * 16;
             const x3_u4 bh = *reinterpret_cast<const x3_u4*>(&Bs[0][off]);
             const x3_u4 bl = *reinterpret_cast<const x3_u4*>(&Bs[1][off]);
 #pragma unroll
@@ -177,11 +177,11 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = m0 + 32 * wm + 16 * g + 4 * lq + i;
-                const int n = n0 + 64 * wn + 16 * c + lr;
+                const int n = n0 + 16 * CT * wn + 16 * c + lr;
                 if (m < M && n < N) S[(long)n * lds + m] = make_float2(acc[g][0][c][i], acc[g][1][c][i]);
             }
 }
@@ -292,7 +292,9 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
-    const int BMC = 32 * WM, BN = 64 * (4 / WM);
+    // eight column tiles per wave when all four waves run along m and are mostly full
+    const int CT = M > 96 ? 8 : 4;
+    const int BMC = 32 * WM, BN = 16 * CT * (4 / WM);
     PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
     dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
     int splits = 1;
@@ -307,9 +309,10 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
     ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * sizeof(float2),
                     8.0 * (double)M * N * K);
     float2* out = splits > 1 ? work : S;
-    if (WM == 1) hipLaunchKernelGGL(k_gemm_ahb_x3<1>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
-    else if (WM == 2) hipLaunchKernelGGL(k_gemm_ahb_x3<2>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
-    else hipLaunchKernelGGL(k_gemm_ahb_x3<4>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    if (WM == 1) hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    else if (WM == 2) hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    else if (CT == 8) hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    else hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
     PDEP_HIP(hipGetLastError());
     if (splits > 1) launch_splitk_reduce_f32(M, N, lds, splits, work, S, s);
 }
