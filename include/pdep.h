@@ -265,6 +265,9 @@ int pdep_server_destroy(pdep_server* s);
  * (any output pointer may be NULL); classes are named by pdep_profile_kernel_name(k)
  * ("" past the last class).  Call after the timed work finished. */
 int pdep_profile_enable(int on);
+/* Restrict timing to the kernel classes whose bit (1 << k) is set in mask (default: all);
+ * the other launches then run without events. */
+int pdep_profile_set_classes(unsigned mask);
 int pdep_profile_read(int reset, double* total_ms, long long* launches, double* bytes, double* flops,
                       int max_kernels);
 const char* pdep_profile_kernel_name(int k);

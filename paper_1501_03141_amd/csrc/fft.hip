@@ -22,6 +22,7 @@
 // sizes are compile-time template parameters (all index arithmetic is then by
 // constants); other sizes use the same code with run-time sizes.  Twiddles come from
 // tables exp(-2 pi i m / n) built in extended precision on the host.
+#include <cmath>
 #include <type_traits>
 
 #include "pdep_internal.h"
@@ -826,11 +827,11 @@ namespace {
 
 template <typename T, int MODE>
 void launch_slab(const FftDims& d, const BasisTables& t, int nrows, cplx<T>* sticks, const T* Vr, const cplx<T>* u,
-                 int nv, cplx<T>* grid_c, T* grid_r, hipStream_t s, int kid, double bytes) {
+                 int nv, cplx<T>* grid_c, T* grid_r, hipStream_t s, int kid, double bytes, double flops = 0.0) {
     if (nrows <= 0) return;
     check_slab(d);
     check_rows(nrows);
-    ProfScope prof_(kid, s, bytes);
+    ProfScope prof_(kid, s, bytes, flops);
     with_nxy(d.nx, d.ny, [&]<int N>() {
         hipLaunchKernelGGL((k_slab<T, N, N, MODE>), dim3(d.nz, nrows), dim3(kThreads), slab_lds<T>(d), s, d, t,
                            sticks, Vr, u, nv > 0 ? nv : 1, grid_c, grid_r);
@@ -853,6 +854,12 @@ template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s) {
     const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     const double bytes = (double)nrows * 2.0 * sk + (double)d.nx * d.ny * d.nz * sizeof(T);
+    // algorithmic flops: 5 n log2 n per length-n complex line (inverse and forward y on the
+    // non-empty columns, inverse and forward x on every row) plus the real multiply by V
+    const double lines_y = 2.0 * d.ax * d.nz, lines_x = 2.0 * d.ny * d.nz;
+    const double flops = (double)nrows * (lines_y * 5.0 * d.ny * std::log2((double)d.ny) +
+                                          lines_x * 5.0 * d.nx * std::log2((double)d.nx) +
+                                          2.0 * d.nx * d.ny * d.nz);
     if constexpr (sizeof(T) == sizeof(float)) {
         bool done = false;
         with_n(d.nx, [&]<int N>() {
@@ -861,7 +868,7 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
                 if (lds > 0 && nrows > 0) {
                     check_rows(nrows);
                     constexpr int ZG = 256 / N;
-                    ProfScope prof_(K_SLAB_HV, s, bytes);
+                    ProfScope prof_(K_SLAB_HV, s, bytes, flops);
                     hipLaunchKernelGGL((k_slab_hv_reg<N>), dim3((d.nz + ZG - 1) / ZG, nrows), dim3(256), lds, s, d,
                                        t, sticks, Vz);
                     PDEP_HIP(hipGetLastError());
@@ -871,7 +878,8 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
         });
         if (done || nrows <= 0) return;
     }
-    launch_slab<T, SLAB_HV>(d, t, nrows, sticks, Vz, nullptr, 1, nullptr, nullptr, s, K_SLAB_HV, bytes);
+    launch_slab<T, SLAB_HV>(d, t, nrows, sticks, Vz, nullptr, 1, nullptr, nullptr, s,
+                            sizeof(T) == sizeof(double) ? K_SLAB_HV64 : K_SLAB_HV, bytes, flops);
 }
 
 template <typename T>

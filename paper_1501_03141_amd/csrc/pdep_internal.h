@@ -80,7 +80,7 @@ bool verbose();
 // Kernel classes timed by the opt-in profiler (prof.hip; see pdep_profile_enable).
 enum KernelId : int {
     K_SPHERE_TO_STICKS = 0, K_SLAB_HV, K_STICKS_TO_SPHERE, K_SLAB_INV_STORE, K_SLAB_FWD_PRODUCT,
-    K_SLAB_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_COUNT
+    K_SLAB_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_SLAB_HV64, K_COUNT
 };
 // Records HIP events around the launch made during its lifetime (when profiling is on),
 // with the launch's algorithmic HBM bytes and flops.

@@ -21,6 +21,7 @@ struct Pending {
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    unsigned mask = ~0u;   // kernel classes that are timed while on
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     double total_ms[K_COUNT] = {0};
@@ -63,14 +64,14 @@ Profiler& prof() {
 
 const char* kNames[K_COUNT] = {"sphere_to_sticks", "slab_hv",    "sticks_to_sphere", "slab_inv_store",
                                "slab_fwd_product", "slab_density", "gemm_ahb",      "gemm_update",
-                               "row_dots",         "cg_update",    "misc"};
+                               "row_dots",         "cg_update",    "misc",          "slab_hv_fp64"};
 
 }  // namespace
 
 ProfScope::ProfScope(int kid, hipStream_t s, double bytes, double flops)
     : kid_(kid), s_(s), bytes_(bytes), flops_(flops) {
     Profiler& p = prof();
-    if (!p.on) return;
+    if (!p.on || !((p.mask >> kid) & 1u)) return;
     std::lock_guard<std::mutex> g(p.mu);
     a_ = p.ev();
     b_ = p.ev();
@@ -108,6 +109,13 @@ int pdep_profile_enable(int on) {
     } catch (...) {
     }
     p.on = on != 0;
+    return PDEP_OK;
+}
+
+int pdep_profile_set_classes(unsigned mask) {
+    pdep::Profiler& p = pdep::prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.mask = mask;
     return PDEP_OK;
 }
 

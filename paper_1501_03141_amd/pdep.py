@@ -156,6 +156,8 @@ def load(path: str = LIB_PATH):
     lib.pdep_profile_read.restype = C.c_int
     lib.pdep_profile_kernel_name.argtypes = [C.c_int]
     lib.pdep_profile_kernel_name.restype = C.c_char_p
+    lib.pdep_profile_set_classes.argtypes = [C.c_uint]
+    lib.pdep_profile_set_classes.restype = C.c_int
     lib.pdep_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]
     lib.pdep_submit.argtypes = [P, C.POINTER(Job), C.POINTER(C.c_uint64)]
     lib.pdep_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(JobResult), D, C.c_int]
@@ -190,6 +192,21 @@ def _check(code: int, allow=()):
 
 def profile_enable(on: bool = True):
     _check(load().pdep_profile_enable(1 if on else 0))
+
+
+def profile_classes(names=None):
+    """Time only the named kernel classes (None: all of them)."""
+    lib = load()
+    if names is None:
+        mask = 0xFFFFFFFF
+    else:
+        idx = {lib.pdep_profile_kernel_name(k).decode(): k for k in range(32)}
+        mask = 0
+        for n in names:
+            if n not in idx:
+                raise ValueError(f"unknown kernel class {n!r}")
+            mask |= 1 << idx[n]
+    _check(lib.pdep_profile_set_classes(C.c_uint(mask)))
 
 
 def profile_read(reset: bool = True):
