@@ -4,6 +4,7 @@
 // plane-wave expansion of Sec. 2.1), enumerated lexicographically in (mx, my, mz).
 // Because mz is the fastest index, every (mx, my) z-stick of the sphere is a
 // contiguous run, which is what the stick passes of the transforms read and write.
+#include <algorithm>
 #include <cmath>
 
 #include "pdep_internal.h"
@@ -162,6 +163,17 @@ void build_basis(const pdep_cell& cell, Basis& b) {
     d.npw = b.npw;
     d.ns = (int)b.slab_pos.size();
     d.sld = (d.ns + 31) / 32 * 32;
+    d.sg_max = 0;
+    for (int s0 = 0; s0 < d.ns; s0 += kRegStickGroup) {
+        const int s1 = std::min(d.ns, s0 + kRegStickGroup);
+        d.sg_max = std::max(d.sg_max, b.stick_start[s1] - b.stick_start[s0]);
+    }
+    // every stick covers a symmetric mz range (convex, inversion-symmetric sphere)
+    for (int s = 0; s < d.ns; ++s) {
+        const int k0 = b.stick_start[s], cnt = b.stick_start[s + 1] - k0;
+        PDEP_REQUIRE(cnt % 2 == 1 && b.miller[3 * k0 + 2] == -(cnt - 1) / 2, PDEP_EINVAL,
+                     "internal: z stick of the sphere is not a symmetric mz range");
+    }
     d.px = make_axis_plan(d.nx);
     d.py = make_axis_plan(d.ny);
     d.pz = make_axis_plan(d.nz);

@@ -456,6 +456,68 @@ __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere(
     }
 }
 
+// Register-resident sticks -> sphere pass (FP32): one thread per z stick of a group
+// of kRegStickGroup sticks, the whole length-NZ line in registers.  A stick's sphere
+// entries are contiguous and cover mz = -kz..kz, so line index iz holds mz = iz or
+// iz - NZ and the stick needs no position table.  The group's sphere entries pass
+// through LDS so that the sphere side (with the epilogue) is written coalesced; the
+// sticks side ([row][iz][stick]) is read coalesced across the threads of a group.
+// (The same structure for the sphere -> sticks direction measured slower than the
+// LDS-staged kernel, which is kept for it.)
+template <int NZ>
+__global__ __launch_bounds__(kRegStickGroup) void k_sticks_to_sphere_reg(
+    FftDims d, BasisTables t, const float2* __restrict__ sticks, float2* __restrict__ out, long ld_out, int epi,
+    double alpha, const float2* __restrict__ x, long ld_x, const float* __restrict__ kin,
+    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale) {
+    constexpr int HALF = (NZ + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2* buf = reinterpret_cast<float2*>(smem);
+    const int s0 = blockIdx.x * kRegStickGroup, row = blockIdx.y;
+    const int nsh = min(kRegStickGroup, d.ns - s0);
+    const int kb = t.stick_start[s0], ke = t.stick_start[s0 + nsh];
+    const int sl = threadIdx.x;
+    if (sl < nsh) {
+        const float2* srcs = sticks + (long)row * NZ * d.sld + s0 + sl;
+        float2 v[NZ], X[NZ];
+        sfor<0, NZ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            v[i] = srcs[(long)i * d.sld];
+        });
+        dft_reg<float, -1, NZ, 1>(v, X);
+        const int ks = t.stick_start[s0 + sl] - kb, kz = (t.stick_start[s0 + sl + 1] - kb - ks - 1) / 2;
+        float2* line = buf + ks + kz;
+        sfor<0, NZ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int mz = i < HALF ? i : i - NZ;
+            if (mz >= -kz && mz <= kz) line[mz] = X[i];
+        });
+    }
+    __syncthreads();
+    const float inv_ng = 1.0f / (float)((double)d.nx * d.ny * d.nz);
+    float2* o = out + (long)row * ld_out;
+    if (epi == EPI_SHIFTED_H) {
+        const float sh = (float)shift[row % nshift];
+        const float2* xr = x + (long)row * ld_x;
+        for (int k = kb + threadIdx.x; k < ke; k += kRegStickGroup) {
+            const float2 f = buf[k - kb], xv = xr[k];
+            const float dk = kin[k] - sh;
+            o[k] = make_float2(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
+        }
+    } else if (epi == EPI_GSCALE) {
+        for (int k = kb + threadIdx.x; k < ke; k += kRegStickGroup) {
+            const float2 f = buf[k - kb];
+            const float g = (float)gscale[k] * inv_ng;
+            o[k] = make_float2(f.x * g, f.y * g);
+        }
+    } else {
+        const float sc = (float)alpha * inv_ng;
+        for (int k = kb + threadIdx.x; k < ke; k += kRegStickGroup) {
+            const float2 f = buf[k - kb];
+            o[k] = make_float2(f.x * sc, f.y * sc);
+        }
+    }
+}
+
 // ------------------------------------------------------------------- slab passes ---
 // A workgroup owns one z slab of one row: an nx x ny tile in LDS, element (ix, iy) at
 // ix * ny + iy.  The non-empty x columns are ix = mx mod nx for |mx| <= mxmax.
@@ -758,6 +820,12 @@ template <typename T> size_t stick_lds(const FftDims& d) {
 template <typename T> size_t slab_lds(const FftDims& d) {
     return sizeof(cplx<T>) * ((size_t)d.nx * d.ny + d.nx + d.ny);
 }
+// The register stick passes apply to FP32 lines of a compiled length up to 48 whose
+// group staging fits the 64 KB of LDS one workgroup may use.
+bool stick_reg_ok(const FftDims& d) {
+    const bool len = d.nz == 16 || d.nz == 24 || d.nz == 32 || d.nz == 48;
+    return len && d.sg_max > 0 && (size_t)d.sg_max * sizeof(float2) <= 65536;
+}
 dim3 stick_grid(const FftDims& d, int nrows) {
     return dim3((d.ns + sticks_per_group(d.nz) - 1) / sticks_per_group(d.nz), nrows);
 }
@@ -816,6 +884,20 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
     check_rows(nrows);
     const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     ProfScope prof_(K_STICKS_TO_SPHERE, s, (double)nrows * (sk + sp + (epi == EPI_SHIFTED_H ? sp : 0.0)));
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (stick_reg_ok(d)) {
+            const dim3 grid((d.ns + kRegStickGroup - 1) / kRegStickGroup, nrows);
+            const size_t lds = (size_t)d.sg_max * sizeof(float2);
+            with_n(d.nz, [&]<int NZ>() {
+                if constexpr (NZ > 0 && NZ <= 48)
+                    hipLaunchKernelGGL((k_sticks_to_sphere_reg<NZ>), grid, dim3(kRegStickGroup), lds, s, d, t,
+                                       sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1,
+                                       gscale);
+            });
+            PDEP_HIP(hipGetLastError());
+            return;
+        }
+    }
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sticks_to_sphere<T, NZ>), stick_grid(d, nrows), dim3(kThreads), stick_lds<T>(d), s, d,
                            t, sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, gscale);

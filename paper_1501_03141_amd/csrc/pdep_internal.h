@@ -116,8 +116,12 @@ struct FftDims {
     int npw;
     int ns;                   // number of sticks
     int sld;                  // stick leading dimension of the sticks buffer (>= ns)
+    int sg_max;               // most sphere entries in one group of kRegStickGroup sticks
     AxisPlan px, py, pz;
 };
+
+// Sticks per workgroup of the register stick passes.
+constexpr int kRegStickGroup = 128;
 
 // Device tables of the sphere / grid (one set per context).
 struct BasisTables {
