@@ -285,11 +285,18 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
         double* rz = sc.s_rz[cur];
         double* sh = sc.s_shift[cur];
         for (int k = 0; k < nstep; ++k) {
-            apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
+            // With the preconditioner z = P_c K r is projected every iteration, so p stays in
+            // range(P_c) and q = (H - shift) p needs no projection: <p, q> and the update of
+            // x are unchanged by it.  What q adds to r outside range(P_c) is rounding (the
+            // orbitals are eigenvectors of H); it is removed from r once per group of
+            // iterations, before the residual test, so it never reaches the inner
+            // tolerance.  Without the preconditioner z = r, and q is projected every time.
+            apply_op<T>(c, p, q, ld, ncur, sh, ncur, !pre, sticks, S);
             st.op_applications++;
             launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
             launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, sc.active, kin, sh, ncur, pre, s);
             if (pre) project_c<T>(c, z, ld, ncur, S);
+            if (pre && k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
             launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
