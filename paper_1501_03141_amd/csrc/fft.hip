@@ -405,13 +405,26 @@ __global__ __launch_bounds__(kThreads) void k_sphere_to_sticks(FftDims d, BasisT
     }
 }
 
+// Sum of v over the NT threads of a workgroup (fixed order), result in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
 // sticks -> sphere rows (forward z transforms, 1/N_g) with an epilogue.
 template <typename T, int NZ_>
 __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere(
     FftDims d, BasisTables t, const cplx<T>* __restrict__ sticks, cplx<T>* __restrict__ out, long ld_out, int epi,
     double alpha, const cplx<T>* __restrict__ x, long ld_x, const T* __restrict__ kin,
-    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale) {
+    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale, double* __restrict__ dot_part) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kThreads];
     using C = cplx<T>;
     const int NZ = NZ_ ? NZ_ : d.nz;
     const int SG = sticks_per_group(NZ);
@@ -435,11 +448,18 @@ __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere(
     if (epi == EPI_SHIFTED_H) {
         const T sh = (T)shift[row % nshift];
         const C* xr = x + (long)row * ld_x;
+        double acc = 0.0;
         for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
             const C f = buf[t.stick_pos[k] - off];
             const C xv = xr[k];
             const T dk = kin[k] - sh;
-            o[k] = mk<T>(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
+            const C ov = mk<T>(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
+            o[k] = ov;
+            acc += (double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y;
+        }
+        if (dot_part) {
+            const double tot = block_sum<kThreads>(acc, red);
+            if (threadIdx.x == 0) dot_part[(long)row * gridDim.x + blockIdx.x] = tot;
         }
     } else if (epi == EPI_GSCALE) {
         for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
@@ -468,9 +488,10 @@ template <int NZ>
 __global__ __launch_bounds__(kRegStickGroup) void k_sticks_to_sphere_reg(
     FftDims d, BasisTables t, const float2* __restrict__ sticks, float2* __restrict__ out, long ld_out, int epi,
     double alpha, const float2* __restrict__ x, long ld_x, const float* __restrict__ kin,
-    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale) {
+    const double* __restrict__ shift, int nshift, const double* __restrict__ gscale, double* __restrict__ dot_part) {
     constexpr int HALF = (NZ + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kRegStickGroup];
     float2* buf = reinterpret_cast<float2*>(smem);
     const int s0 = blockIdx.x * kRegStickGroup, row = blockIdx.y;
     const int nsh = min(kRegStickGroup, d.ns - s0);
@@ -498,10 +519,17 @@ __global__ __launch_bounds__(kRegStickGroup) void k_sticks_to_sphere_reg(
     if (epi == EPI_SHIFTED_H) {
         const float sh = (float)shift[row % nshift];
         const float2* xr = x + (long)row * ld_x;
+        double acc = 0.0;
         for (int k = kb + threadIdx.x; k < ke; k += kRegStickGroup) {
             const float2 f = buf[k - kb], xv = xr[k];
             const float dk = kin[k] - sh;
-            o[k] = make_float2(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
+            const float2 ov = make_float2(f.x * inv_ng + dk * xv.x, f.y * inv_ng + dk * xv.y);
+            o[k] = ov;
+            acc += (double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y;
+        }
+        if (dot_part) {
+            const double tot = block_sum<kRegStickGroup>(acc, red);
+            if (threadIdx.x == 0) dot_part[(long)row * gridDim.x + blockIdx.x] = tot;
         }
     } else if (epi == EPI_GSCALE) {
         for (int k = kb + threadIdx.x; k < ke; k += kRegStickGroup) {
@@ -878,8 +906,10 @@ void launch_sphere_to_sticks(const FftDims& d, const BasisTables& t, const cplx<
 template <typename T>
 void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows, cplx<T>* out,
                              long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x, const T* kin,
-                             const double* shift, int nshift, const double* gscale, hipStream_t s) {
+                             const double* shift, int nshift, const double* gscale, hipStream_t s,
+                             double* dot_part) {
     if (nrows <= 0) return;
+    PDEP_REQUIRE(!dot_part || epi == EPI_SHIFTED_H, PDEP_EINVAL, "sticks_to_sphere: dot products need EPI_SHIFTED_H");
     check_sticks(d);
     check_rows(nrows);
     const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
@@ -892,7 +922,7 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
                 if constexpr (NZ > 0 && NZ <= 48)
                     hipLaunchKernelGGL((k_sticks_to_sphere_reg<NZ>), grid, dim3(kRegStickGroup), lds, s, d, t,
                                        sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1,
-                                       gscale);
+                                       gscale, dot_part);
             });
             PDEP_HIP(hipGetLastError());
             return;
@@ -900,7 +930,8 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
     }
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sticks_to_sphere<T, NZ>), stick_grid(d, nrows), dim3(kThreads), stick_lds<T>(d), s, d,
-                           t, sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, gscale);
+                           t, sticks, out, ld_out, epi, alpha, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, gscale,
+                           dot_part);
     });
     PDEP_HIP(hipGetLastError());
 }
@@ -1017,12 +1048,18 @@ void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, 
     PDEP_HIP(hipGetLastError());
 }
 
+template <typename T> int sticks_to_sphere_groups(const FftDims& d) {
+    if (sizeof(T) == sizeof(float) && stick_reg_ok(d)) return (d.ns + kRegStickGroup - 1) / kRegStickGroup;
+    return (int)stick_grid(d, 1).x;
+}
+
 #define PDEP_INST_FFT(T)                                                                                          \
     template void launch_sphere_to_sticks<T>(const FftDims&, const BasisTables&, const cplx<T>*, long, int,       \
                                              const double*, cplx<T>*, hipStream_t);                               \
     template void launch_sticks_to_sphere<T>(const FftDims&, const BasisTables&, const cplx<T>*, int, cplx<T>*,   \
                                              long, int, double, const cplx<T>*, long, const T*, const double*,     \
-                                             int, const double*, hipStream_t);                                    \
+                                             int, const double*, hipStream_t, double*);                           \
+    template int sticks_to_sphere_groups<T>(const FftDims&);                                                      \
     template void launch_slab_hv<T>(const FftDims&, const BasisTables&, cplx<T>*, int, const T*, hipStream_t);    \
     template void launch_slab_inv_store<T>(const FftDims&, const BasisTables&, cplx<T>*, int, cplx<T>*, T*,       \
                                            hipStream_t);                                                          \

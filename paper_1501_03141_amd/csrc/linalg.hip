@@ -274,13 +274,14 @@ __global__ void k_cg_init(int K, const cplx<T>* __restrict__ b, long ld, cplx<T>
 template <typename T>
 __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__ r, cplx<T>* __restrict__ z,
                            const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q, long ld,
-                           const double* __restrict__ rz, const double* __restrict__ pq,
+                           const double* __restrict__ rz, const double* __restrict__ pq, int npq,
                            const int* __restrict__ active, const T* __restrict__ kin,
                            const double* __restrict__ shift, int nshift, int precond) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
     if (k >= K || !active[row]) return;
-    const double den = pq[row];
+    double den = 0.0;
+    for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
     const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
     const long o = (long)row * ld + k;
     const cplx<T> pv = p[o], qv = q[o];
@@ -477,12 +478,12 @@ void launch_cg_init(int nrows, int K, const cplx<T>* b, long ld, cplx<T>* x, cpl
 
 template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p, const cplx<T>* q,
-                     long ld, const double* rz, const double* pq, const int* active, const T* kin,
+                     long ld, const double* rz, const double* pq, int npq, const int* active, const T* kin,
                      const double* shift, int nshift, int precond, hipStream_t s) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s, 7.0 * nrows * (double)K * sizeof(cplx<T>));
-    hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq, active,
-                       kin, shift, nshift > 0 ? nshift : 1, precond);
+    hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
+                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -583,8 +584,8 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
     template void launch_cg_init<T>(int, int, const cplx<T>*, long, cplx<T>*, cplx<T>*, cplx<T>*, const T*,    \
                                     const double*, int, int, hipStream_t);                                    \
     template void launch_cg_step1<T>(int, int, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,   \
-                                     long, const double*, const double*, const int*, const T*, const double*,  \
-                                     int, int, hipStream_t);                                                  \
+                                     long, const double*, const double*, int, const int*, const T*,            \
+                                     const double*, int, int, hipStream_t);                                   \
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \

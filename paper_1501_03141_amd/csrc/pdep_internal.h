@@ -147,11 +147,16 @@ enum SphereEpilogue : int {
     EPI_SHIFTED_H = 1,        // out = F + (kin - shift[row % nshift]) * x
     EPI_GSCALE = 2,           // out = F * gscale
 };
-// sticks -> sphere rows (forward z transforms, 1/N_g) with an epilogue.
+// sticks -> sphere rows (forward z transforms, 1/N_g) with an epilogue.  With
+// EPI_SHIFTED_H and dot_part non-null, each workgroup also writes Re<x, out> over its
+// part of the row (FP64 sum) to dot_part[row * G + group], G = sticks_to_sphere_groups.
 template <typename T>
 void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows, cplx<T>* out,
                              long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x, const T* kin,
-                             const double* shift, int nshift, const double* gscale, hipStream_t s);
+                             const double* shift, int nshift, const double* gscale, hipStream_t s,
+                             double* dot_part = nullptr);
+// number of partial dot products per row that launch_sticks_to_sphere<T> writes
+template <typename T> int sticks_to_sphere_groups(const FftDims& d);
 // sticks -> inverse (y, x) -> * V(z, x, y) (z-major real grid) -> forward -> sticks, in place.
 template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s);
@@ -198,9 +203,10 @@ void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>
 template <typename T>
 void launch_cg_init(int nrows, int K, const cplx<T>* b, long ld, cplx<T>* x, cplx<T>* r, cplx<T>* z,
                     const T* kin, const double* shift, int nshift, int precond, hipStream_t s);
+// pq: npq partial sums of <p, q> per row (row-major), added in order
 template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p,
-                     const cplx<T>* q, long ld, const double* rz, const double* pq, const int* active,
+                     const cplx<T>* q, long ld, const double* rz, const double* pq, int npq, const int* active,
                      const T* kin, const double* shift, int nshift, int precond, hipStream_t s);
 template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new,

@@ -35,7 +35,7 @@ namespace {
 
 enum Slot {
     W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_STICKS, W_S, W_SCAL,
-    W_ROWS, W_VR, W_DN, W_REF2, W_CX2, W_CR2, W_CZ2, W_CP2, W_XOUT, W_MAP, W_SPLIT, W_LAST
+    W_ROWS, W_VR, W_DN, W_REF2, W_CX2, W_CR2, W_CZ2, W_CP2, W_XOUT, W_MAP, W_SPLIT, W_PQP, W_LAST
 };
 static_assert(W_LAST <= WS_SOLVER_END, "solver work-space slots overlap the others");
 
@@ -88,16 +88,19 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
 }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
-// kinetic/shift epilogue, then (optionally) the P_c GEMM pair.
+// kinetic/shift epilogue, then (optionally) the P_c GEMM pair.  pq_part (may be null,
+// only without the projection): per-row partial sums of Re<p, q> from the epilogue,
+// sticks_to_sphere_groups<T> of them per row.
 template <typename T>
 void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const double* shift, int nshift,
-              bool project, void* sticks_buf, double2* S) {
+              bool project, void* sticks_buf, double2* S, double* pq_part = nullptr) {
     const Basis& b = c.basis;
+    PDEP_REQUIRE(!(project && pq_part), PDEP_EINVAL, "apply_op: partial dots are of the unprojected q");
     cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
     launch_sphere_to_sticks<T>(b.dims, b.tables, p, ld, nrows, nullptr, sk, c.stream);
     launch_slab_hv<T>(b.dims, b.tables, sk, nrows, vloc_of<T>(c), c.stream);
     launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nrows, q, ld, EPI_SHIFTED_H, 0.0, p, ld, kin_of<T>(c), shift,
-                               nshift, nullptr, c.stream);
+                               nshift, nullptr, c.stream, pq_part);
     if (project) project_c<T>(c, q, ld, nrows, S);
 }
 
@@ -221,6 +224,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     void* sticks = c.ws(W_STICKS, (size_t)n * sticks_row_bytes(c));
     double2* S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, n)));
     const int pre = c.opts.precond;
+    const int npq = sticks_to_sphere_groups<T>(c.basis.dims);
+    double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * npq * sizeof(double) + 64));
     const T* kin = kin_of<T>(c);
     int cur = 0, ncur = n;
 
@@ -291,10 +296,18 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             // orbitals are eigenvectors of H); it is removed from r once per group of
             // iterations, before the residual test, so it never reaches the inner
             // tolerance.  Without the preconditioner z = r, and q is projected every time.
-            apply_op<T>(c, p, q, ld, ncur, sh, ncur, !pre, sticks, S);
-            st.op_applications++;
-            launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
-            launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, sc.active, kin, sh, ncur, pre, s);
+            // <p, q> comes from the epilogue that produces q (partial sums per stick
+            // group), unless q is projected afterwards
+            if (pre) {
+                apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, sticks, S, pq_part);
+                st.op_applications++;
+                launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s);
+            } else {
+                apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
+                st.op_applications++;
+                launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
+                launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, 1, sc.active, kin, sh, ncur, pre, s);
+            }
             if (pre) project_c<T>(c, z, ld, ncur, S);
             if (pre && k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
