@@ -276,22 +276,61 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
                            const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q, long ld,
                            const double* __restrict__ rz, const double* __restrict__ pq, int npq,
                            const int* __restrict__ active, const T* __restrict__ kin,
-                           const double* __restrict__ shift, int nshift, int precond) {
+                           const double* __restrict__ shift, int nshift, int precond,
+                           double* __restrict__ rz_part, double* __restrict__ rr_part) {
+    __shared__ double red[2][256];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
-    if (k >= K || !active[row]) return;
-    double den = 0.0;
-    for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
-    const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
-    const long o = (long)row * ld + k;
-    const cplx<T> pv = p[o], qv = q[o];
-    cplx<T> xv = x[o], rv = r[o];
-    xv.x += alpha * pv.x; xv.y += alpha * pv.y;
-    rv.x -= alpha * qv.x; rv.y -= alpha * qv.y;
-    x[o] = xv;
-    r[o] = rv;
-    const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
-    z[o] = mk<T>(f * rv.x, f * rv.y);
+    if (!active[row]) return;                         // whole block: one row
+    double srz = 0.0, srr = 0.0;
+    if (k < K) {
+        double den = 0.0;
+        for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
+        const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
+        const long o = (long)row * ld + k;
+        const cplx<T> pv = p[o], qv = q[o];
+        cplx<T> xv = x[o], rv = r[o];
+        xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+        rv.x -= alpha * qv.x; rv.y -= alpha * qv.y;
+        x[o] = xv;
+        r[o] = rv;
+        const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
+        z[o] = mk<T>(f * rv.x, f * rv.y);
+        const double n2 = (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+        srr = n2;
+        srz = (double)f * n2;
+    }
+    if (rz_part) {   // <r, K r> and ||r||^2 over this block (fixed-order tree)
+        red[0][threadIdx.x] = srz;
+        red[1][threadIdx.x] = srr;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            rz_part[(long)row * gridDim.x + blockIdx.x] = red[0][0];
+            rr_part[(long)row * gridDim.x + blockIdx.x] = red[1][0];
+        }
+    }
+}
+
+// rz[row] = sum_g rz_part[row][g], rr[row] likewise (g in order); inactive rows skipped.
+__global__ void k_sum_parts(int nrows, int nparts, const double* __restrict__ rz_part,
+                            const double* __restrict__ rr_part, const int* __restrict__ active,
+                            double* __restrict__ rz, double* __restrict__ rr) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nrows || !active[row]) return;
+    double a = 0.0, b = 0.0;
+    for (int g = 0; g < nparts; ++g) {
+        a += rz_part[(long)row * nparts + g];
+        b += rr_part[(long)row * nparts + g];
+    }
+    rz[row] = a;
+    rr[row] = b;
 }
 
 template <typename T>
@@ -479,12 +518,18 @@ void launch_cg_init(int nrows, int K, const cplx<T>* b, long ld, cplx<T>* x, cpl
 template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p, const cplx<T>* q,
                      long ld, const double* rz, const double* pq, int npq, const int* active, const T* kin,
-                     const double* shift, int nshift, int precond, hipStream_t s) {
+                     const double* shift, int nshift, int precond, hipStream_t s, double* rz_part,
+                     double* rr_part, double* rz_new, double* rr) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s, 7.0 * nrows * (double)K * sizeof(cplx<T>));
     hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
-                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond);
+                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part);
     PDEP_HIP(hipGetLastError());
+    if (rz_part) {
+        hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)rows_grid(K, nrows).x,
+                           rz_part, rr_part, active, rz_new, rr);
+        PDEP_HIP(hipGetLastError());
+    }
 }
 
 template <typename T>
@@ -585,7 +630,8 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
                                     const double*, int, int, hipStream_t);                                    \
     template void launch_cg_step1<T>(int, int, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,   \
                                      long, const double*, const double*, int, const int*, const T*,            \
-                                     const double*, int, int, hipStream_t);                                   \
+                                     const double*, int, int, hipStream_t, double*, double*, double*,          \
+                                     double*);                                                                \
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \

@@ -203,11 +203,16 @@ void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>
 template <typename T>
 void launch_cg_init(int nrows, int K, const cplx<T>* b, long ld, cplx<T>* x, cplx<T>* r, cplx<T>* z,
                     const T* kin, const double* shift, int nshift, int precond, hipStream_t s);
-// pq: npq partial sums of <p, q> per row (row-major), added in order
+// pq: npq partial sums of <p, q> per row (row-major), added in order.  With rz_part
+// non-null (work space of nrows * ceil(K / 256) doubles each, as rr_part), the step also
+// forms <r, K r> and ||r||^2 of the updated r and writes their row sums to rz_new, rr
+// (active rows only): for r in range(P_c), <r, P_c K r> = <r, K r>.
 template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p,
                      const cplx<T>* q, long ld, const double* rz, const double* pq, int npq, const int* active,
-                     const T* kin, const double* shift, int nshift, int precond, hipStream_t s);
+                     const T* kin, const double* shift, int nshift, int precond, hipStream_t s,
+                     double* rz_part = nullptr, double* rr_part = nullptr, double* rz_new = nullptr,
+                     double* rr = nullptr);
 template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new,
                      double* rz, const int* active, hipStream_t s);

@@ -224,8 +224,12 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     void* sticks = c.ws(W_STICKS, (size_t)n * sticks_row_bytes(c));
     double2* S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, n)));
     const int pre = c.opts.precond;
-    const int npq = sticks_to_sphere_groups<T>(c.basis.dims);
-    double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * npq * sizeof(double) + 64));
+    // per-row partial sums: <p, q> (stick groups of the H epilogue), <r, K r> and ||r||^2
+    // (blocks of the CG step)
+    const int npq = sticks_to_sphere_groups<T>(c.basis.dims), nblk = (npw + 255) / 256;
+    double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * (npq + 2 * nblk) * sizeof(double) + 64));
+    double* rz_part = pq_part + (size_t)n * npq;
+    double* rr_part = rz_part + (size_t)n * nblk;
     const T* kin = kin_of<T>(c);
     int cur = 0, ncur = n;
 
@@ -294,23 +298,25 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             // range(P_c) and q = (H - shift) p needs no projection: <p, q> and the update of
             // x are unchanged by it.  What q adds to r outside range(P_c) is rounding (the
             // orbitals are eigenvectors of H); it is removed from r once per group of
-            // iterations, before the residual test, so it never reaches the inner
-            // tolerance.  Without the preconditioner z = r, and q is projected every time.
-            // <p, q> comes from the epilogue that produces q (partial sums per stick
-            // group), unless q is projected afterwards
+            // iterations, so it stays far below the inner tolerance.  The inner products
+            // come from the kernels that produce their operands: <p, q> from the epilogue
+            // of H (partial sums per stick group), <r, z> = <r, K r> (r in range(P_c)) and
+            // ||r||^2 from the step that updates r.  Without the preconditioner z = r, q
+            // is projected every time and the products are separate passes.
             if (pre) {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, sticks, S, pq_part);
                 st.op_applications++;
-                launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s);
+                launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s,
+                                   rz_part, rr_part, sc.rz_new, sc.rr);
+                project_c<T>(c, z, ld, ncur, S);
+                if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             } else {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
                 st.op_applications++;
                 launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, 1, sc.active, kin, sh, ncur, pre, s);
+                launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
             }
-            if (pre) project_c<T>(c, z, ld, ncur, S);
-            if (pre && k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
-            launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
             launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
             launch_cg_check(ncur, sc.rr, sc.s_thr2[cur], sc.active, sc.s_iters[cur], rz, sc.rz_new, sc.n_active, 1,
