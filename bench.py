@@ -198,6 +198,7 @@ def main():
     ap.add_argument("--precision", choices=["bf16x3", "mixed_fp32"], default="bf16x3",
                     help="mixed mode of the timed steps (the other one is timed once beside it)")
     ap.add_argument("--no-other-mode", action="store_true")
+    ap.add_argument("--no-eigs", action="store_true", help="skip the end-to-end PDEP Davidson")
     ap.add_argument("--serving-jobs", type=int, default=24, help="0 disables the serving phase")
     ap.add_argument("--serving-max-running", type=int, default=4)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -325,6 +326,21 @@ def main():
             if ctx_o is not ctx:
                 ctx_o.close()
 
+    # ---- end-to-end PDEP: block Davidson for the N_pdep most screened eigenpairs from the
+    # library's own random start (main mixed mode)
+    eigs = None
+    if not args.no_eigs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eps_pdep, _, est = ctx_main.eigs(w.n_pdep, seed=w.seed, tol=1e-6, maxit=60, n_buffer=8, allow_notconv=True)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter() - t0
+        eigs = {"seconds": round(t_e, 2), "n_pdep": w.n_pdep, "tol": 1e-6, "n_buffer": 8,
+                "iterations": est["iterations"], "chi0_columns": est["chi0_columns"],
+                "max_residual": est["max_residual"], "eps_max": float(eps_pdep[0]),
+                "eps_min": float(eps_pdep[-1])}
+        log("pdep_eigs", eigs)
+
     serving = None
     if args.serving_jobs > 0:
         serving = serving_bench(args.serving_jobs, args.serving_max_running, log)
@@ -367,6 +383,7 @@ def main():
         "roofline": roof,
         "kernels_one_step": {k: {"ms": round(v["ms"], 2), "launches": v["launches"]} for k, v in prof.items()
                              if v["launches"]},
+        "pdep_eigs": eigs,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -264,7 +264,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     int it = 0;
     const int poll = 4;
     while (h_active > 0 && it < maxit) {
-        if (h_active < ncur && (4 * h_active < 3 * ncur)) {
+        if (h_active < ncur && (10 * h_active < 9 * ncur)) {
             // compact: retire converged slots, gather live state into the other set
             flags.resize(ncur);
             PDEP_HIP(hipMemcpyAsync(flags.data(), sc.active, ncur * sizeof(int), hipMemcpyDeviceToHost, s));
