@@ -304,12 +304,13 @@ def main():
     if not args.no_fp64:
         ctx64 = make_context(w, V, pdep.PDEP_FP64, psi=psi, eps=eps_occ)
         out64 = torch.empty_like(phi)
-        ms64, sts64, _ = run_steps(ctx64, out64, 1, 0, False)
+        ms64, sts64, _ = run_steps(ctx64, out64, 1, 1, False)
         st64 = sts64[-1]
         chi64 = out64.cpu().numpy()
         e_fp64 = ritz_eps(phi_host, chi64)
         eps_err = float(np.max(np.abs(ritz_eps(phi_host, chi_mixed) - e_fp64)))
         fp64 = {"ms_per_step": round(ms64, 2), "value": round(w.n_pdep / (ms64 / 1e3), 3),
+                "fft_chunk_rows": st64["fft_chunk"],
                 "cg_iter_max": st64["cg_iter_max"], "speedup_mixed_over_fp64": round(ms64 / ms_step, 3)}
         log("fp64", st64, f"{ms64:.1f} ms; ritz eps err {main_mode} vs fp64 {eps_err:.2e}")
         ctx64.close()
@@ -378,6 +379,7 @@ def main():
         "cg_iter_max": stats[-1]["cg_iter_max"],
         "cg_iter_mean": round(stats[-1]["cg_iter_total"] / max(stats[-1]["n_rhs"], 1), 2),
         "refine_steps": stats[-1]["refine_steps"],
+        "fft_chunk_rows": stats[-1]["fft_chunk"],
         "setup_s": round(setup_s, 2),
         "dominant_kernel": kname,
         "roofline": roof,

@@ -131,6 +131,8 @@ typedef struct {
     int n_notconv;                /* systems that missed cg_tol */
     double max_rel_residual;      /* max over systems of the final FP64 relative residual */
     double ms;                    /* wall time of the call on the device stream */
+    int fft_chunk;                /* rows per launch of the transform chain of the inner solves
+                                     (chosen by timing on the first large application) */
 } pdep_apply_stats;
 
 typedef struct {

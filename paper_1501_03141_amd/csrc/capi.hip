@@ -274,6 +274,7 @@ int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_a
         st->n_notconv = as.n_notconv;
         st->max_rel_residual = as.max_rel_residual;
         st->ms = ms;
+        st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
     }
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
@@ -323,6 +324,7 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
         st->n_notconv = as.n_notconv;
         st->max_rel_residual = as.max_rel_residual;
         st->ms = ms;
+        st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
     }
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");

@@ -299,6 +299,8 @@ struct Ctx {
     bool own_blas = false;
     Buf w[WS_COUNT];
     void* ws(int i, size_t bytes) { w[i].ensure(&al, bytes); return w[i].get(); }
+    // rows per launch of the transform chain for FP32 / FP64 rows (0: not tuned yet)
+    int fft_chunk32 = 0, fft_chunk64 = 0;
 };
 
 // solver.hip

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 
+#include <vector>
 #include "pdep_internal.h"
 
 namespace pdep {
@@ -87,6 +88,24 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream);
 }
 
+// Rows per launch of the transform chain (sticks pass, slab pass, sticks pass).  With
+// blocks of rows whose sticks fit in the on-die cache, each pass reads what the previous
+// one wrote from that cache instead of HBM.  The block size is chosen by timing: on the
+// first application with at least kTuneRows rows, the chain runs for candidate sizes
+// around the cache rule (and for all rows at once) on the actual data and the fastest
+// is kept for the context (per precision).  Every row is independent, so the results do
+// not depend on the choice.
+constexpr double kChunkCacheBytes = 150e6;   // about half of the 256 MB last-level cache
+constexpr int kTuneRows = 1024;
+
+template <typename T> int& fft_chunk_of(Ctx& c) { return sizeof(T) == sizeof(float) ? c.fft_chunk32 : c.fft_chunk64; }
+
+template <typename T> int fft_chunk_rule(const Ctx& c) {
+    const FftDims& d = c.basis.dims;
+    const double row = (double)d.nz * d.sld * sizeof(cplx<T>);
+    return std::max(32, (int)(kChunkCacheBytes / row));
+}
+
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
 // kinetic/shift epilogue, then (optionally) the P_c GEMM pair.  pq_part (may be null,
 // only without the projection): per-row partial sums of Re<p, q> from the epilogue,
@@ -97,10 +116,51 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
     const Basis& b = c.basis;
     PDEP_REQUIRE(!(project && pq_part), PDEP_EINVAL, "apply_op: partial dots are of the unprojected q");
     cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
-    launch_sphere_to_sticks<T>(b.dims, b.tables, p, ld, nrows, nullptr, sk, c.stream);
-    launch_slab_hv<T>(b.dims, b.tables, sk, nrows, vloc_of<T>(c), c.stream);
-    launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nrows, q, ld, EPI_SHIFTED_H, 0.0, p, ld, kin_of<T>(c), shift,
-                               nshift, nullptr, c.stream, pq_part);
+    const int npq = sticks_to_sphere_groups<T>(b.dims);
+    auto chain = [&](int chunk) {
+        for (int r0 = 0; r0 < nrows; r0 += chunk) {
+            const int nr = std::min(chunk, nrows - r0);
+            const cplx<T>* pc = p + (long)r0 * ld;
+            const bool per_row = nshift == nrows;
+            launch_sphere_to_sticks<T>(b.dims, b.tables, pc, ld, nr, nullptr, sk, c.stream);
+            launch_slab_hv<T>(b.dims, b.tables, sk, nr, vloc_of<T>(c), c.stream);
+            launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, EPI_SHIFTED_H, 0.0, pc, ld,
+                                       kin_of<T>(c), per_row ? shift + r0 : shift, per_row ? nr : nshift, nullptr,
+                                       c.stream, pq_part ? pq_part + (long)r0 * npq : nullptr);
+        }
+    };
+    int& tuned = fft_chunk_of<T>(c);
+    if (tuned == 0 && nrows >= kTuneRows) {
+        const int rule = fft_chunk_rule<T>(c);
+        std::vector<int> cand;
+        for (int v : {rule / 2, (3 * rule) / 4, rule, (3 * rule) / 2, 2 * rule, nrows}) {
+            v = std::min(std::max(v, 32), nrows);
+            if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+        }
+        hipEvent_t e0, e1;
+        PDEP_HIP(hipEventCreate(&e0));
+        PDEP_HIP(hipEventCreate(&e1));
+        float best = 0.f;
+        for (int v : cand) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {   // the second run is timed
+                PDEP_HIP(hipEventRecord(e0, c.stream));
+                chain(v);
+                PDEP_HIP(hipEventRecord(e1, c.stream));
+                PDEP_HIP(hipEventSynchronize(e1));
+                PDEP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            }
+            if (verbose()) fprintf(stderr, "[pdep] transform chain, %d rows in blocks of %d: %.3f ms\n", nrows, v, ms);
+            if (tuned == 0 || ms < best) {
+                best = ms;
+                tuned = v;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (verbose()) fprintf(stderr, "[pdep] transform chain block size %d rows\n", tuned), fflush(stderr);
+    }
+    chain(tuned > 0 ? tuned : nrows);
     if (project) project_c<T>(c, q, ld, nrows, S);
 }
 

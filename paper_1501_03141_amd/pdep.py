@@ -70,7 +70,7 @@ class Info(C.Structure):
 class ApplyStats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("cg_iter_max", C.c_int), ("cg_iter_total", C.c_longlong),
                 ("op_applications", C.c_longlong), ("refine_steps", C.c_int), ("n_notconv", C.c_int),
-                ("max_rel_residual", C.c_double), ("ms", C.c_double)]
+                ("max_rel_residual", C.c_double), ("ms", C.c_double), ("fft_chunk", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
