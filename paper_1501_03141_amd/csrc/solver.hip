@@ -26,7 +26,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-
+#include <cstdlib>
+#include <cstring>
+#include <utility>
 #include <vector>
 #include "pdep_internal.h"
 
@@ -94,9 +96,23 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
 // first application with at least kTuneRows rows, the chain runs for candidate sizes
 // around the cache rule (and for all rows at once) on the actual data and the fastest
 // is kept for the context (per precision).  Every row is independent, so the results do
-// not depend on the choice.
+// not depend on the choice.  PDEP_FFT_CHUNK=<fp32 rows>[:<fp64 rows>] in the environment
+// fixes the sizes instead (for profiling runs that must launch the shapes of a tuned run).
 constexpr double kChunkCacheBytes = 150e6;   // about half of the 256 MB last-level cache
 constexpr int kTuneRows = 1024;
+
+int fft_chunk_env(bool fp64) {
+    static const std::pair<int, int> v = [] {
+        int a = 0, b = 0;
+        if (const char* e = std::getenv("PDEP_FFT_CHUNK")) {
+            a = std::atoi(e);
+            const char* colon = std::strchr(e, ':');
+            b = colon ? std::atoi(colon + 1) : 0;
+        }
+        return std::make_pair(std::max(a, 0), std::max(b, 0));
+    }();
+    return fp64 ? v.second : v.first;
+}
 
 template <typename T> int& fft_chunk_of(Ctx& c) { return sizeof(T) == sizeof(float) ? c.fft_chunk32 : c.fft_chunk64; }
 
@@ -130,6 +146,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
         }
     };
     int& tuned = fft_chunk_of<T>(c);
+    if (tuned == 0) tuned = fft_chunk_env(sizeof(T) == sizeof(double));
     if (tuned == 0 && nrows >= kTuneRows) {
         const int rule = fft_chunk_rule<T>(c);
         std::vector<int> cand;
