@@ -174,6 +174,18 @@ void build_basis(const pdep_cell& cell, Basis& b) {
         PDEP_REQUIRE(cnt % 2 == 1 && b.miller[3 * k0 + 2] == -(cnt - 1) / 2, PDEP_EINVAL,
                      "internal: z stick of the sphere is not a symmetric mz range");
     }
+    // inversion: the lexicographic order of an inversion-symmetric set is reversed by
+    // G -> -G, so -G_k is entry npw - 1 - k, G = 0 the centre (npw - 1) / 2, and stick
+    // ns - 1 - s the mirror of stick s (vectors real in r are stored as half spheres)
+    PDEP_REQUIRE(b.npw % 2 == 1 && b.g0 == (b.npw - 1) / 2 && d.ns % 2 == 1, PDEP_EINVAL,
+                 "internal: the sphere is not inversion symmetric");
+    for (int k = 0; k < b.npw; ++k)
+        for (int a = 0; a < 3; ++a)
+            PDEP_REQUIRE(b.miller[3 * (b.npw - 1 - k) + a] == -b.miller[3 * k + a], PDEP_EINVAL,
+                         "internal: the sphere order does not pair G with -G");
+    for (int s = 0; s < d.ns; ++s)
+        PDEP_REQUIRE(b.stick_start[d.ns - 1 - s] == b.npw - b.stick_start[s + 1], PDEP_EINVAL,
+                     "internal: the stick order does not pair mirror sticks");
     d.px = make_axis_plan(d.nx);
     d.py = make_axis_plan(d.ny);
     d.pz = make_axis_plan(d.nz);

@@ -183,6 +183,7 @@ int pdep::setup_context(const pdep_cell* cell, const double* vloc, const pdep_op
             return fail(PDEP_EGAP, m);
         }
     }
+    pdep::realify_orbitals(c);
     finish_setup(c);
     *out = ctx;
     ctx = nullptr;

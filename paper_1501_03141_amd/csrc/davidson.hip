@@ -437,6 +437,92 @@ void ground_state(Ctx& c) {
     PDEP_HIP(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------ orbitals real in r ---
+namespace {
+
+// Row j of psi -> rows j (A) and nv + j (B) of v: A = (psi + conj psi(-G)) / 2 and
+// B = (psi - conj psi(-G)) / 2i, the coefficients of Re psi(r) and Im psi(r).  The
+// sphere order puts -G_k at npw - 1 - k.
+__global__ void k_sym_split(int npw, int nv, const double2* __restrict__ psi, long ldp, double2* __restrict__ v,
+                            long ldv) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (k >= npw) return;
+    const double2 p = psi[(long)j * ldp + k], q = psi[(long)j * ldp + npw - 1 - k];
+    // q* = (q.x, -q.y)
+    v[(long)j * ldv + k] = make_double2(0.5 * (p.x + q.x), 0.5 * (p.y - q.y));
+    v[(long)(nv + j) * ldv + k] = make_double2(0.5 * (p.y + q.y), -0.5 * (p.x - q.x));
+}
+
+}  // namespace
+
+// The orbitals are replaced by an orthonormal basis of the same occupied subspace made
+// of functions that are real in r (Hermitian-symmetric coefficients), each a Ritz
+// vector of H in that subspace.  H is real in r, so conjugation in r maps eigenvectors
+// to eigenvectors of the same energy: the occupied subspace of a gapped system is
+// closed under it and the real and imaginary parts (in r) of the orbitals span it.  The
+// 2 N_v parts have a Gram matrix with N_v eigenvalues 1 and N_v eigenvalues 0; the
+// eigenvectors of the first N_v give an orthonormal real basis, and Rayleigh-Ritz with
+// H (real symmetric) rotates it into Ritz vectors.
+void realify_orbitals(Ctx& c) {
+    const Basis& b = c.basis;
+    const int npw = b.npw, nv = c.nv, m = 2 * nv;
+    const long ld = sphere_ld(npw);
+    hipStream_t s = c.stream;
+    Solver sv(c);
+    Workspace ws(c);
+    double2* V = static_cast<double2*>(ws.get(D_V, (size_t)m * ld * sizeof(double2)));
+    double2* X = static_cast<double2*>(ws.get(D_X, (size_t)nv * ld * sizeof(double2)));
+    double2* AX = static_cast<double2*>(ws.get(D_AX, (size_t)nv * ld * sizeof(double2)));
+    double2* sticks = static_cast<double2*>(c.ws(WS_SETUP_STICKS, (size_t)nv * b.dims.nz * b.dims.sld * sizeof(double2)));
+    double* dtheta = static_cast<double*>(c.ws(WS_DAV_THETA, (size_t)m * sizeof(double) * 2 + 64));
+    double2* Cdev = static_cast<double2*>(c.ws(WS_DAV_C, (size_t)m * m * sizeof(double2)));
+    launch_fill_zero(V, (size_t)m * ld * sizeof(double2), s);
+    hipLaunchKernelGGL(k_sym_split, dim3((npw + 255) / 256, nv), dim3(256), 0, s, npw, nv, c.psi64.as<double2>(),
+                       (long)npw, V, ld);
+    PDEP_HIP(hipGetLastError());
+    launch_gemm_ahb<double>(m, m, npw, V, ld, V, ld, Cdev, m, ws.split(), Workspace::kSplitElems, s);
+    std::vector<double2> G = d2h(Cdev, (size_t)m * m, s);
+    std::vector<double> w;
+    std::vector<double2> Q;
+    dense_eig(ws, sv, G, m, true, w, Q);
+    const double wmax = std::max(w[m - 1], 1e-300);
+    PDEP_REQUIRE(w[nv - 1] <= 1e-6 * wmax && w[nv] >= 0.5 * wmax, PDEP_EINVAL,
+                 "the orbitals do not span a subspace closed under complex conjugation in r (Gram eigenvalues " +
+                     std::to_string(w[nv - 1]) + " and " + std::to_string(w[nv]) +
+                     "): they are not the complete occupied eigenspace of H");
+    std::vector<double2> C((size_t)nv * m);
+    for (int j = 0; j < nv; ++j) {
+        const int col = m - 1 - j;
+        const double f = 1.0 / std::sqrt(w[col]);
+        for (int i = 0; i < m; ++i) C[(size_t)j * m + i] = make_double2(Q[(size_t)col * m + i].x * f, 0.0);
+    }
+    combine(c, V, m, nv, ld, C, X, Cdev);
+    launch_sym_fix(nv, npw, X, ld, s);
+    // Rayleigh-Ritz with H in the real basis
+    double* dzero = dtheta + m;
+    launch_fill_zero(dzero, sizeof(double), s);
+    apply_h64(c, X, ld, nv, dzero, 1, AX, ld, sticks);
+    launch_gemm_ahb<double>(nv, nv, npw, X, ld, AX, ld, Cdev, nv, ws.split(), Workspace::kSplitElems, s);
+    std::vector<double2> Hm = d2h(Cdev, (size_t)nv * nv, s);
+    std::vector<double> theta;
+    std::vector<double2> Y;
+    dense_eig(ws, sv, Hm, nv, true, theta, Y);
+    std::vector<double2> C2(Y.begin(), Y.begin() + (size_t)nv * nv);
+    for (auto& x : C2) x.y = 0.0;
+    combine(c, X, nv, nv, ld, C2, V, Cdev);
+    launch_sym_fix(nv, npw, V, ld, s);
+    PDEP_HIP(hipMemcpy2DAsync(c.psi64.get(), npw * sizeof(double2), V, ld * sizeof(double2), npw * sizeof(double2),
+                              nv, hipMemcpyDeviceToDevice, s));
+    PDEP_HIP(hipStreamSynchronize(s));
+    double dmax = 0.0;
+    for (int j = 0; j < nv; ++j) dmax = std::max(dmax, std::abs(theta[j] - c.eps[j]));
+    if (verbose())
+        fprintf(stderr, "[pdep] orbitals made real in r: Gram split %.2e / %.2e, max |d eps| %.2e\n", w[nv - 1],
+                w[nv], dmax), fflush(stderr);
+    c.eps.assign(theta.begin(), theta.begin() + nv);
+}
+
 // --------------------------------------------------------------------------- PDEP --
 EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_dev, const pdep_eig_opts& eo,
                         double* lam_out, double2* basis_out_dev) {

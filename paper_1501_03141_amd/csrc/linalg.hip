@@ -440,6 +440,21 @@ __global__ void k_compact_s1(int npw, int g0, const double2* __restrict__ in, lo
     out[(long)row * ldo + k] = in[(long)row * ldi + (k < g0 ? k : k + 1)];
 }
 
+// Make rows exactly Hermitian-symmetric: c_k and c_{npw-1-k} (the coefficients of G and
+// -G in the sphere order) <- the symmetric part; the centre (G = 0) becomes real.  One
+// thread per pair k <= npw - 1 - k.
+__global__ void k_sym_fix(int npw, double2* __restrict__ x, long ld) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int m = npw - 1 - k;
+    if (k > m) return;
+    double2* r = x + (long)j * ld;
+    const double2 a = r[k], b = r[m];
+    const double2 v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    r[k] = v;
+    r[m] = make_double2(v.x, -v.y);
+}
+
 inline dim3 rows_grid(int K, int nrows) {
     PDEP_REQUIRE(nrows <= 65535, PDEP_EINVAL, "too many rows for one launch (max 65535)");
     return dim3((K + 255) / 256, nrows);
@@ -582,6 +597,13 @@ void launch_scatter_rows(int nrows, int K, const double2* src, long lds, const i
     if (nrows <= 0) return;
     ProfScope prof_(K_MISC, s);
     hipLaunchKernelGGL(k_scatter_rows, rows_grid(K, nrows), dim3(256), 0, s, K, src, lds, rows, dst, ldd);
+    PDEP_HIP(hipGetLastError());
+}
+
+void launch_sym_fix(int nrows, int npw, double2* x, long ld, hipStream_t s) {
+    if (nrows <= 0) return;
+    ProfScope prof_(K_MISC, s, 32.0 * nrows * npw);
+    hipLaunchKernelGGL(k_sym_fix, rows_grid(npw / 2 + 1, nrows), dim3(256), 0, s, npw, x, ld);
     PDEP_HIP(hipGetLastError());
 }
 

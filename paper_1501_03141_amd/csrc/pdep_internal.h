@@ -234,6 +234,8 @@ void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* ro
 // dst[rows[r]] = src[r]
 void launch_scatter_rows(int nrows, int K, const double2* src, long lds, const int* rows, double2* dst,
                          long ldd, hipStream_t s);
+// rows <- their Hermitian-symmetric part (c_{-G} = conj c_G; -G_k sits at npw - 1 - k)
+void launch_sym_fix(int nrows, int npw, double2* x, long ld, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_fill_i32(int* p, int n, int value, hipStream_t s);
 // S' <-> S: expand inserts a zero at G = 0 (index g0); compact drops it.  Rows of length
@@ -331,6 +333,8 @@ size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, c
 
 // davidson.hip
 void ground_state(Ctx& c);
+// orbitals -> Hermitian-symmetric (real in r) Ritz vectors of the same subspace
+void realify_orbitals(Ctx& c);
 struct EigResult {
     int iterations = 0, columns = 0;
     double max_residual = 0.0;

@@ -579,6 +579,8 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
                                         s);
         launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, nrow, b64, ld, EPI_SCALE, -1.0, nullptr, 0, nullptr,
                                         nullptr, 0, nullptr, s);
+        // dV and u_v are real in r, so b is Hermitian-symmetric up to rounding: make it exact
+        launch_sym_fix(nrow, npw, b64, ld, s);
         double* ref2 = static_cast<double*>(c.ws(W_REF2, (size_t)nrow * sizeof(double)));
         launch_row_dots<double>(nrow, npw, b64, ld, b64, ld, ref2, nullptr, s);
         project_c<double>(c, b64, ld, nrow, S);
