@@ -546,6 +546,147 @@ __global__ __launch_bounds__(kRegStickGroup) void k_sticks_to_sphere_reg(
     }
 }
 
+// ------------------------------------------------------- paired half-sphere rows ---
+// Rows that are real in r (Hermitian-symmetric coefficients, c_{-G} = conj c_G) are kept
+// as half spheres: entries k <= c = (npw - 1) / 2 of the sphere order, where -G_k is
+// entry npw - 1 - k and the centre c is G = 0.  Two such rows a, b travel through one
+// complex transform: Inv(a + i b) = a(r) + i b(r) with both parts real, so a real
+// potential acts on each part separately, and after the forward transform W of the
+// product a_G = (W_G + conj W_-G) / 2, b_G = (W_G - conj W_-G) / 2i.
+
+// Half-sphere rows 2j, 2j + 1 -> sticks of packed row j (inverse z transforms).  The
+// entries k > c come from the mirrors npw - 1 - k (conjugated); the centre is taken
+// real.  Row 2j + 1 is zero when it does not exist (odd nrows).
+template <typename T, int NZ_>
+__global__ __launch_bounds__(kThreads) void k_sphere_to_sticks_pair(FftDims d, BasisTables t,
+                                                                    const cplx<T>* __restrict__ in, long ld_in,
+                                                                    int nrows, cplx<T>* __restrict__ sticks) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    using C = cplx<T>;
+    const int NZ = NZ_ ? NZ_ : d.nz;
+    const int SG = sticks_per_group(NZ);
+    C* buf = reinterpret_cast<C*>(smem);
+    C* twz = buf + SG * NZ;
+    const int s0 = blockIdx.x * SG;
+    const int ns_here = min(SG, d.ns - s0);
+    const int pr = blockIdx.y;
+    const bool has_b = 2 * pr + 1 < nrows;
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) buf[e] = mk<T>(0, 0);
+    load_tw<T>(twz, t, 2, NZ);
+    __syncthreads();
+    const int k0 = t.stick_start[s0], k1 = t.stick_start[s0 + ns_here];
+    const int npw = d.npw, c = (npw - 1) / 2;
+    const C* a = in + (long)(2 * pr) * ld_in;
+    const C* b = a + ld_in;
+    const int off = s0 * NZ;
+    for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
+        const int src = k <= c ? k : npw - 1 - k;
+        C va = a[src];
+        C vb = has_b ? b[src] : mk<T>(0, 0);
+        if (k == c) {
+            va.y = 0;
+            vb.y = 0;
+        } else if (k > c) {
+            va.y = -va.y;
+            vb.y = -vb.y;
+        }
+        buf[t.stick_pos[k] - off] = mk<T>(va.x - vb.y, va.y + vb.x);
+    }
+    __syncthreads();
+    fft_lines<T, +1, NZ_, 0, false>(buf, d.pz, ns_here, LineMap{0, SG, NZ}, 1, twz);
+    C* dst = sticks + (long)pr * NZ * d.sld + s0;
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) {
+        const int sl = e % SG, z = e / SG;
+        if (sl < ns_here) dst[(long)z * d.sld + sl] = buf[sl * NZ + z];
+    }
+}
+
+// Sticks of packed row j -> half-sphere rows 2j, 2j + 1 with the shifted-H epilogue
+// out = F + (kin - shift[row % nshift]) x and, when dot_part is non-null, the partial
+// sums of Re<x, out> over the full sphere (weight 2 off the centre) per workgroup.  A
+// workgroup transforms SG / 2 sticks of the front half (s <= (ns - 1) / 2, which hold
+// every entry k <= c) and their mirrors ns - 1 - s.
+template <typename T, int NZ_>
+__global__ __launch_bounds__(kThreads) void k_sticks_to_sphere_pair(
+    FftDims d, BasisTables t, const cplx<T>* __restrict__ sticks, int nrows, cplx<T>* __restrict__ out, long ld_out,
+    const cplx<T>* __restrict__ x, long ld_x, const T* __restrict__ kin, const double* __restrict__ shift,
+    int nshift, double* __restrict__ dot_part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][kThreads];
+    using C = cplx<T>;
+    const int NZ = NZ_ ? NZ_ : d.nz;
+    const int SG = sticks_per_group(NZ), SGH = SG / 2;
+    C* buf = reinterpret_cast<C*>(smem);
+    C* twz = buf + SG * NZ;
+    const int nfront = (d.ns + 1) / 2;
+    const int s0 = blockIdx.x * SGH;
+    const int nf = min(SGH, nfront - s0);
+    const int pr = blockIdx.y;
+    const C* src = sticks + (long)pr * NZ * d.sld;
+    // line j < SGH: front stick s0 + j; line SGH + j: its mirror
+    for (int e = threadIdx.x; e < SG * NZ; e += kThreads) {
+        const int sl = e % SG, z = e / SG;
+        const int j = sl < SGH ? sl : sl - SGH;
+        C v = mk<T>(0, 0);
+        if (j < nf) v = src[(long)z * d.sld + (sl < SGH ? s0 + j : d.ns - 1 - s0 - j)];
+        buf[sl * NZ + z] = v;
+    }
+    load_tw<T>(twz, t, 2, NZ);
+    __syncthreads();
+    fft_lines<T, -1, NZ_, 0, false>(buf, d.pz, SG, LineMap{0, SG, NZ}, 1, twz);
+    const int c = (d.npw - 1) / 2;
+    const int k0 = t.stick_start[s0], k1 = min(t.stick_start[s0 + nf], c + 1);
+    const T inv_ng = T(1.0 / ((double)d.nx * d.ny * d.nz));
+    const T half = T(0.5) * inv_ng;
+    const int ra = 2 * pr, rb = ra + 1;
+    const bool has_b = rb < nrows;
+    const T sha = (T)shift[ra % nshift], shb = has_b ? (T)shift[rb % nshift] : T(0);
+    C* oa = out + (long)ra * ld_out;
+    C* ob = oa + ld_out;
+    const C* xa = x + (long)ra * ld_x;
+    const C* xb = xa + ld_x;
+    double acca = 0.0, accb = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
+        const int pos = t.stick_pos[k];
+        const int st = pos / NZ, iz = pos - st * NZ;
+        const int j = st - s0;
+        const C W = buf[j * NZ + iz];
+        const C Wm = buf[(SGH + j) * NZ + (iz == 0 ? 0 : NZ - iz)];
+        const double w = k == c ? 1.0 : 2.0;
+        const T kk = kin[k];
+        {
+            const C xv = xa[k];
+            const T dk = kk - sha;
+            const C ov = mk<T>(half * (W.x + Wm.x) + dk * xv.x, half * (W.y - Wm.y) + dk * xv.y);
+            oa[k] = ov;
+            acca += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+        }
+        if (has_b) {
+            const C xv = xb[k];
+            const T dk = kk - shb;
+            const C ov = mk<T>(half * (W.y + Wm.y) + dk * xv.x, half * (Wm.x - W.x) + dk * xv.y);
+            ob[k] = ov;
+            accb += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+        }
+    }
+    if (dot_part) {
+        red[0][threadIdx.x] = acca;
+        red[1][threadIdx.x] = accb;
+        __syncthreads();
+        for (int s = kThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + s];
+                red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            dot_part[(long)ra * gridDim.x + blockIdx.x] = red[0][0];
+            if (has_b) dot_part[(long)rb * gridDim.x + blockIdx.x] = red[1][0];
+        }
+    }
+}
+
 // ------------------------------------------------------------------- slab passes ---
 // A workgroup owns one z slab of one row: an nx x ny tile in LDS, element (ix, iy) at
 // ix * ny + iy.  The non-empty x columns are ix = mx mod nx for |mx| <= mxmax.
@@ -936,6 +1077,45 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
     PDEP_HIP(hipGetLastError());
 }
 
+int sticks_to_sphere_pair_groups(const FftDims& d) {
+    const int sgh = sticks_per_group(d.nz) / 2;
+    return ((d.ns + 1) / 2 + sgh - 1) / sgh;
+}
+
+template <typename T>
+void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
+                                  cplx<T>* sticks, hipStream_t s) {
+    if (nrows <= 0) return;
+    check_sticks(d);
+    const int npair = (nrows + 1) / 2;
+    check_rows(npair);
+    const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    ProfScope prof_(K_SPHERE_TO_STICKS, s, (double)nrows * hp + (double)npair * sk);
+    with_n(d.nz, [&]<int NZ>() {
+        hipLaunchKernelGGL((k_sphere_to_sticks_pair<T, NZ>), stick_grid(d, npair), dim3(kThreads), stick_lds<T>(d), s,
+                           d, t, in, ld_in, nrows, sticks);
+    });
+    PDEP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows,
+                                  cplx<T>* out, long ld_out, const cplx<T>* x, long ld_x, const T* kin,
+                                  const double* shift, int nshift, hipStream_t s, double* dot_part) {
+    if (nrows <= 0) return;
+    check_sticks(d);
+    const int npair = (nrows + 1) / 2;
+    check_rows(npair);
+    const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
+    ProfScope prof_(K_STICKS_TO_SPHERE, s, (double)npair * sk + 2.0 * nrows * hp);
+    const dim3 grid(sticks_to_sphere_pair_groups(d), npair);
+    with_n(d.nz, [&]<int NZ>() {
+        hipLaunchKernelGGL((k_sticks_to_sphere_pair<T, NZ>), grid, dim3(kThreads), stick_lds<T>(d), s, d, t, sticks,
+                           nrows, out, ld_out, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, dot_part);
+    });
+    PDEP_HIP(hipGetLastError());
+}
+
 namespace {
 
 template <typename T, int MODE>
@@ -1060,6 +1240,11 @@ template <typename T> int sticks_to_sphere_groups(const FftDims& d) {
                                              long, int, double, const cplx<T>*, long, const T*, const double*,     \
                                              int, const double*, hipStream_t, double*);                           \
     template int sticks_to_sphere_groups<T>(const FftDims&);                                                      \
+    template void launch_sphere_to_sticks_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, long, int,  \
+                                                  cplx<T>*, hipStream_t);                                         \
+    template void launch_sticks_to_sphere_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, int,        \
+                                                  cplx<T>*, long, const cplx<T>*, long, const T*, const double*,  \
+                                                  int, hipStream_t, double*);                                     \
     template void launch_slab_hv<T>(const FftDims&, const BasisTables&, cplx<T>*, int, const T*, hipStream_t);    \
     template void launch_slab_inv_store<T>(const FftDims&, const BasisTables&, cplx<T>*, int, cplx<T>*, T*,       \
                                            hipStream_t);                                                          \

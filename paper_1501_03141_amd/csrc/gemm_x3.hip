@@ -89,7 +89,7 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 template <int WM, int CT>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
                                                      const float2* __restrict__ B, long ldb, float2* __restrict__ S,
-                                                     long lds, int kchunk) {
+                                                     long lds, int kchunk, int real_out) {
     constexpr int WN = 4 / WM;
     constexpr int BMC = 32 * WM, BN = 16 * CT * WN;
     constexpr int IT = BN / 64;   // B staging items per thread (4 complex each)
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
             for (int i = 0; i < 4; ++i) {
                 const int m = m0 + 32 * wm + 16 * g + 4 * lq + i;
                 const int n = n0 + 16 * CT * wn + 16 * c + lr;
-                if (m < M && n < N) S[(long)n * lds + m] = make_float2(acc[g][0][c][i], acc[g][1][c][i]);
+                if (m < M && n < N) S[(long)n * lds + m] = make_float2(acc[g][0][c][i], real_out ? 0.f : acc[g][1][c][i]);
             }
 }
 
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3(int M, int N, int K, con
 }  // namespace
 
 void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
-                        long lds, float2* work, size_t work_elems, hipStream_t s) {
+                        long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out) {
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
@@ -309,12 +309,17 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
     ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * sizeof(float2),
                     8.0 * (double)M * N * K);
     float2* out = splits > 1 ? work : S;
-    if (WM == 1) hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
-    else if (WM == 2) hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
-    else if (CT == 8) hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
-    else hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk);
+    const int ro = (real_out && splits == 1) ? 1 : 0;
+    if (WM == 1) hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
+                                          ro);
+    else if (WM == 2) hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
+                                          ro);
+    else if (CT == 8) hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
+                                          ro);
+    else hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
+                                          ro);
     PDEP_HIP(hipGetLastError());
-    if (splits > 1) launch_splitk_reduce_f32(M, N, lds, splits, work, S, s);
+    if (splits > 1) launch_splitk_reduce_f32(M, N, lds, splits, work, S, s, real_out);
 }
 
 void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,

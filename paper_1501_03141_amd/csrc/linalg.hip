@@ -53,7 +53,7 @@ constexpr int kPad = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cplx<T>* __restrict__ A, long lda,
                                                   const cplx<T>* __restrict__ B, long ldb, cplx<T>* __restrict__ S,
-                                                  long lds, int kchunk) {
+                                                  long lds, int kchunk, int real_out) {
     constexpr int BMC = 32, BN = 64, BKC = 16;
     constexpr int BMR = 2 * BMC, BKR = 2 * BKC;
     __shared__ T As[BKR][BMR + kPad];
@@ -116,14 +116,14 @@ __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cpl
                 const int mr = wm + 16 * a + Op::row(lane, i);       // real row in the tile
                 const int m = m0 + (mr >> 1), part = mr & 1;
                 const int n = n0 + wn + 16 * b + (lane & 15);
-                if (m < M && n < N) So[((long)n * lds + m) * 2 + part] = acc[a][b][i];
+                if (m < M && n < N) So[((long)n * lds + m) * 2 + part] = (real_out && part) ? T(0) : acc[a][b][i];
             }
 }
 
 // S[n][m] = sum_z P[z][n][m] in the order z = 0, 1, ... (deterministic split-K sum).
 template <typename T>
 __global__ void k_splitk_reduce(int M, int N, long lds, int splits, const cplx<T>* __restrict__ P,
-                                cplx<T>* __restrict__ S) {
+                                cplx<T>* __restrict__ S, int real_out) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)N * M) return;
     const long n = e / M, m = e - (e / M) * M;
@@ -136,7 +136,7 @@ __global__ void k_splitk_reduce(int M, int N, long lds, int splits, const cplx<T
     }
     cplx<T> o;
     o.x = re;
-    o.y = im;
+    o.y = real_out ? T(0) : im;
     S[n * lds + m] = o;
 }
 
@@ -219,10 +219,15 @@ __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const 
 }
 
 // ------------------------------------------------------------------- reductions ---
+// Half-sphere rows (half != 0) hold the entries k <= c of a Hermitian-symmetric vector,
+// the centre G = 0 last (k = K - 1); every other entry stands for itself and its mirror
+// -G, so it counts twice in an inner product.
+__device__ __forceinline__ double half_weight(int half, int k, int K) { return (half && k != K - 1) ? 2.0 : 1.0; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_dots(int K, const cplx<T>* __restrict__ a, long lda,
                                                   const cplx<T>* __restrict__ b, long ldb, double* __restrict__ out,
-                                                  double* __restrict__ out2) {
+                                                  double* __restrict__ out2, int half) {
     __shared__ double red[2][256];
     const int row = blockIdx.x;
     const cplx<T>* ar = a + (long)row * lda;
@@ -230,8 +235,9 @@ __global__ __launch_bounds__(256) void k_row_dots(int K, const cplx<T>* __restri
     double s = 0.0, s2 = 0.0;
     for (int k = threadIdx.x; k < K; k += 256) {
         const cplx<T> x = ar[k], y = br[k];
-        s += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
-        s2 += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+        const double w = half_weight(half, k, K);
+        s += w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+        s2 += w * ((double)x.x * (double)x.x + (double)x.y * (double)x.y);
     }
     red[0][threadIdx.x] = s;
     red[1][threadIdx.x] = s2;
@@ -277,7 +283,7 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
                            const double* __restrict__ rz, const double* __restrict__ pq, int npq,
                            const int* __restrict__ active, const T* __restrict__ kin,
                            const double* __restrict__ shift, int nshift, int precond,
-                           double* __restrict__ rz_part, double* __restrict__ rr_part) {
+                           double* __restrict__ rz_part, double* __restrict__ rr_part, int half) {
     __shared__ double red[2][256];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
@@ -296,7 +302,7 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
         r[o] = rv;
         const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
         z[o] = mk<T>(f * rv.x, f * rv.y);
-        const double n2 = (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+        const double n2 = half_weight(half, k, K) * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
         srr = n2;
         srz = (double)f * n2;
     }
@@ -440,6 +446,41 @@ __global__ void k_compact_s1(int npw, int g0, const double2* __restrict__ in, lo
     out[(long)row * ldo + k] = in[(long)row * ldi + (k < g0 ? k : k + 1)];
 }
 
+// x[rows[r]] += rowscale[r] * (d[r] extended from the half sphere): entries k < c and
+// their mirrors npw - 1 - k (conjugate), the centre c = (npw - 1) / 2 real.
+__global__ void k_axpy_rows_half(int npw, const float2* __restrict__ d, long ldd, const int* __restrict__ rows,
+                                 const double* __restrict__ rowscale, double2* __restrict__ x, long ldx) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    const int c = (npw - 1) / 2;
+    if (k > c) return;
+    const double s = rowscale[row];
+    const float2 v = d[(long)row * ldd + k];
+    double2* xr = x + (long)(rows ? rows[row] : row) * ldx;
+    const double vx = s * (double)v.x, vy = k == c ? 0.0 : s * (double)v.y;
+    double2 a = xr[k];
+    a.x += vx;
+    a.y += vy;
+    xr[k] = a;
+    if (k < c) {
+        double2 b = xr[npw - 1 - k];
+        b.x += vx;
+        b.y -= vy;
+        xr[npw - 1 - k] = b;
+    }
+}
+
+// out[r][k] = w_k in[r][k] for k < K: weight 2 except for the last entry (the centre of a
+// half-sphere row), so that Re sum_k conj(out) y over the half sphere is the full inner product.
+__global__ void k_half_weights(int K, const float2* __restrict__ in, long ldi, float2* __restrict__ out, long ldo) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (k >= K) return;
+    const float w = k == K - 1 ? 1.f : 2.f;
+    const float2 v = in[(long)row * ldi + k];
+    out[(long)row * ldo + k] = make_float2(w * v.x, w * v.y);
+}
+
 // Make rows exactly Hermitian-symmetric: c_k and c_{npw-1-k} (the coefficients of G and
 // -G in the sphere order) <- the symmetric part; the centre (G = 0) becomes real.  One
 // thread per pair k <= npw - 1 - k.
@@ -464,7 +505,7 @@ inline dim3 rows_grid(int K, int nrows) {
 
 template <typename T>
 void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, cplx<T>* S,
-                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s) {
+                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s, bool real_out) {
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_ahb: N too large");
     dim3 grid((M + 31) / 32, (N + 63) / 64);
@@ -481,21 +522,22 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
     ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * sizeof(cplx<T>),
                     8.0 * (double)M * N * K);
     hipLaunchKernelGGL(k_gemm_ahb<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, splits > 1 ? work : S, lds,
-                       kchunk);
+                       kchunk, real_out ? 1 : 0);
     PDEP_HIP(hipGetLastError());
     if (splits > 1) {
         const long tot = (long)N * M;
         hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds, splits,
-                           work, S);
+                           work, S, real_out ? 1 : 0);
         PDEP_HIP(hipGetLastError());
     }
 }
 
-void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s) {
+void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s,
+                              bool real_out) {
     const long tot = (long)N * M;
     if (tot <= 0) return;
     hipLaunchKernelGGL(k_splitk_reduce<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds, splits,
-                       P, S);
+                       P, S, real_out ? 1 : 0);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -513,10 +555,10 @@ void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const c
 
 template <typename T>
 void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>* b, long ldb, double* out,
-                     double* out2, hipStream_t s) {
+                     double* out2, hipStream_t s, bool half) {
     if (nrows <= 0) return;
     ProfScope prof_(K_ROW_DOTS, s, 2.0 * nrows * (double)K * sizeof(cplx<T>));
-    hipLaunchKernelGGL(k_row_dots<T>, dim3(nrows), dim3(256), 0, s, K, a, lda, b, ldb, out, out2);
+    hipLaunchKernelGGL(k_row_dots<T>, dim3(nrows), dim3(256), 0, s, K, a, lda, b, ldb, out, out2, half ? 1 : 0);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -534,11 +576,12 @@ template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p, const cplx<T>* q,
                      long ld, const double* rz, const double* pq, int npq, const int* active, const T* kin,
                      const double* shift, int nshift, int precond, hipStream_t s, double* rz_part,
-                     double* rr_part, double* rz_new, double* rr) {
+                     double* rr_part, double* rz_new, double* rr, bool half) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s, 7.0 * nrows * (double)K * sizeof(cplx<T>));
     hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
-                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part);
+                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part,
+                       half ? 1 : 0);
     PDEP_HIP(hipGetLastError());
     if (rz_part) {
         hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)rows_grid(K, nrows).x,
@@ -581,6 +624,21 @@ void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* r
     if (nrows <= 0) return;
     ProfScope prof_(K_MISC, s);
     hipLaunchKernelGGL(k_axpy_rows<T>, rows_grid(K, nrows), dim3(256), 0, s, K, d, ldd, rows, rowscale, x, ldx);
+    PDEP_HIP(hipGetLastError());
+}
+
+void launch_axpy_rows_half(int nrows, int npw, const float2* d, long ldd, const int* rows, const double* rowscale,
+                           double2* x, long ldx, hipStream_t s) {
+    if (nrows <= 0) return;
+    ProfScope prof_(K_MISC, s);
+    hipLaunchKernelGGL(k_axpy_rows_half, rows_grid((npw + 1) / 2, nrows), dim3(256), 0, s, npw, d, ldd, rows, rowscale,
+                       x, ldx);
+    PDEP_HIP(hipGetLastError());
+}
+
+void launch_half_weights(int nrows, int K, const float2* in, long ldi, float2* out, long ldo, hipStream_t s) {
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(k_half_weights, rows_grid(K, nrows), dim3(256), 0, s, K, in, ldi, out, ldo);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -643,17 +701,17 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
 
 #define PDEP_INST_LA(T)                                                                                         \
     template void launch_gemm_ahb<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, cplx<T>*,      \
-                                     long, cplx<T>*, size_t, hipStream_t);                                    \
+                                     long, cplx<T>*, size_t, hipStream_t, bool);                              \
     template void launch_gemm_update<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, double,     \
                                         double, cplx<T>*, long, hipStream_t);                                 \
     template void launch_row_dots<T>(int, int, const cplx<T>*, long, const cplx<T>*, long, double*, double*,   \
-                                     hipStream_t);                                                            \
+                                     hipStream_t, bool);                                                      \
     template void launch_cg_init<T>(int, int, const cplx<T>*, long, cplx<T>*, cplx<T>*, cplx<T>*, const T*,    \
                                     const double*, int, int, hipStream_t);                                    \
     template void launch_cg_step1<T>(int, int, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,   \
                                      long, const double*, const double*, int, const int*, const T*,            \
                                      const double*, int, int, hipStream_t, double*, double*, double*,          \
-                                     double*);                                                                \
+                                     double*, bool);                                                          \
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \

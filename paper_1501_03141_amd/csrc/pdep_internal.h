@@ -157,6 +157,19 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
                              double* dot_part = nullptr);
 // number of partial dot products per row that launch_sticks_to_sphere<T> writes
 template <typename T> int sticks_to_sphere_groups(const FftDims& d);
+// Paired half-sphere rows (rows real in r, entries k <= c = (npw - 1) / 2 of the sphere
+// order, the rest implied by c_{npw-1-k} = conj c_k): rows 2j and 2j + 1 share packed
+// sticks row j (the transform of a + i b); nrows may be odd.
+template <typename T>
+void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
+                                  cplx<T>* sticks, hipStream_t s);
+// packed sticks -> half-sphere rows with the EPI_SHIFTED_H epilogue; dot_part (may be
+// null): Re<x, out> of the full vectors, sticks_to_sphere_pair_groups partials per row
+template <typename T>
+void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows,
+                                  cplx<T>* out, long ld_out, const cplx<T>* x, long ld_x, const T* kin,
+                                  const double* shift, int nshift, hipStream_t s, double* dot_part);
+int sticks_to_sphere_pair_groups(const FftDims& d);
 // sticks -> inverse (y, x) -> * V(z, x, y) (z-major real grid) -> forward -> sticks, in place.
 template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s);
@@ -180,9 +193,10 @@ void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, 
 // S: N x M, leading dimensions in complex elements).  work (work_elems complex, may be
 // null) holds split-K partial products when the output alone is too small to fill the
 // GPU; the partials are summed in a fixed order.
+// real_out: S gets only the real parts (imaginary parts stored as zero).
 template <typename T>
 void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, cplx<T>* S,
-                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s);
+                     long lds, cplx<T>* work, size_t work_elems, hipStream_t s, bool real_out = false);
 // Y[n][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S: N x M; Y must not alias A or S)
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds,
@@ -190,15 +204,18 @@ void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const c
 // BF16x3 variants of the two GEMMs above for FP32 operands (16 significant bits per
 // product; for the inner solve of the refinement only).  lda/ldb/lds multiples of 4.
 void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
-                        long lds, float2* work, size_t work_elems, hipStream_t s);
+                        long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out = false);
 void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,
                            double beta, float2* Y, long ldy, hipStream_t s);
 // S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)
-void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s);
-// per-row dot products: out[r] = Re <a_r, b_r>, out2[r] = ||a_r||^2 (out2 may be null)
+void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s,
+                              bool real_out = false);
+// per-row dot products: out[r] = Re <a_r, b_r>, out2[r] = ||a_r||^2 (out2 may be null).
+// half: the rows are half spheres of Hermitian-symmetric vectors (entries k <= c of the
+// sphere order, the centre G = 0 last) and the products are those of the full vectors.
 template <typename T>
 void launch_row_dots(int nrows, int K, const cplx<T>* a, long lda, const cplx<T>* b, long ldb,
-                     double* out, double* out2, hipStream_t s);
+                     double* out, double* out2, hipStream_t s, bool half = false);
 // Batched preconditioned CG, element-wise parts (the algorithm is in solver.hip).
 template <typename T>
 void launch_cg_init(int nrows, int K, const cplx<T>* b, long ld, cplx<T>* x, cplx<T>* r, cplx<T>* z,
@@ -212,7 +229,7 @@ void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const
                      const cplx<T>* q, long ld, const double* rz, const double* pq, int npq, const int* active,
                      const T* kin, const double* shift, int nshift, int precond, hipStream_t s,
                      double* rz_part = nullptr, double* rr_part = nullptr, double* rz_new = nullptr,
-                     double* rr = nullptr);
+                     double* rr = nullptr, bool half = false);
 template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new,
                      double* rz, const int* active, hipStream_t s);
@@ -228,6 +245,12 @@ void launch_convert_rows(int nrows, int K, const cplx<Tin>* in, long ldi, const 
 template <typename T>
 void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* rows,
                       const double* rowscale, double2* x, long ldx, hipStream_t s);
+// x[rows[r]] += rowscale[r] * d[r] for half-sphere rows d (FP32, entries k <= c): entry k
+// and its mirror npw - 1 - k (conjugate) of the full rows x; the centre takes the real part.
+void launch_axpy_rows_half(int nrows, int npw, const float2* d, long ldd, const int* rows, const double* rowscale,
+                           double2* x, long ldx, hipStream_t s);
+// out[r][k] = 2 in[r][k] for k < K - 1, in[r][K - 1] at k = K - 1 (half-sphere weights)
+void launch_half_weights(int nrows, int K, const float2* in, long ldi, float2* out, long ldo, hipStream_t s);
 // out[r] = a[rows[r]] - b[r]
 void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b,
                      long ldb, double2* out, long ldo, hipStream_t s);
@@ -293,6 +316,7 @@ struct Ctx {
     double gs_residual = 0.0;
     Buf vloc64, vloc32;                   // [ng] z-major
     Buf psi64, psi32;                     // [nv][npw] complex FP64; [nv][sphere_ld(npw)] FP32
+    Buf psi32w;                           // psi32 with the half-sphere weights (2 off the centre)
     Buf u64;                              // [nv][ng] complex grids, z-major
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic
@@ -308,6 +332,8 @@ struct Ctx {
 // solver.hip
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
+// entries of a half-sphere row (k <= (npw - 1) / 2, the centre G = 0 last)
+int half_len(int npw);
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
 struct ApplyStats {
     int n_rhs = 0, cg_iter_max = 0, refine_steps = 0, n_notconv = 0;

@@ -63,6 +63,7 @@ size_t sticks_row_bytes(const Ctx& c) {
 }  // namespace
 
 long sphere_ld(int npw) { return ((long)npw + 63) / 64 * 64; }
+int half_len(int npw) { return (npw + 1) / 2; }
 
 // Row stride of the projection coefficients S[row][band] (16-byte aligned FP32 rows)
 // and the work space for nrows rows (either precision).
@@ -70,7 +71,11 @@ long coef_ld(int nv) { return ((long)nv + 3) / 4 * 4; }
 size_t coef_bytes(int nv, int nrows) { return (size_t)nrows * coef_ld(nv) * sizeof(double2); }
 
 // Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.  S: work space of coef_bytes(nv, nrows).
-// In the BF16x3 mode the FP32 pair runs on the bf16 matrix cores (three products).
+// FP64 rows are full spheres.  FP32 rows are half spheres of vectors real in r (entries
+// k <= c, the centre last): with Psi real in r as well, Psi^H Y is real and equals
+// Re sum_{k <= c} w_k conj(Psi_k) Y_k with w = 2 off the centre (the weights sit in the
+// copy psi32w), and the update touches the half sphere only.  In the BF16x3 mode the
+// FP32 pair runs on the bf16 matrix cores (three products).
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv;
@@ -79,12 +84,17 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
     cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
     if constexpr (sizeof(T) == sizeof(float)) {
+        const int nh = half_len(npw);
+        const long lp = sphere_ld(npw);
+        const float2* pw = c.psi32w.as<float2>();
         if (c.opts.precision == PDEP_MIXED_BF16X3) {
-            const long lp = sphere_ld(npw);
-            launch_gemm_ahb_x3(nv, nrows, npw, psi_of<T>(c), lp, Y, ld, St, lds, work, split_elems, c.stream);
-            launch_gemm_update_x3(nv, nrows, npw, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
-            return;
+            launch_gemm_ahb_x3(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
+            launch_gemm_update_x3(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
+        } else {
+            launch_gemm_ahb<T>(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
+            launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
         }
+        return;
     }
     launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), Y, ld, St, lds, work, split_elems, c.stream);
     launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream);
@@ -118,31 +128,49 @@ template <typename T> int& fft_chunk_of(Ctx& c) { return sizeof(T) == sizeof(flo
 
 template <typename T> int fft_chunk_rule(const Ctx& c) {
     const FftDims& d = c.basis.dims;
-    const double row = (double)d.nz * d.sld * sizeof(cplx<T>);
+    // FP32 rows are paired: two rows per sticks row
+    const double row = (double)d.nz * d.sld * sizeof(cplx<T>) / (sizeof(T) == sizeof(float) ? 2.0 : 1.0);
     return std::max(32, (int)(kChunkCacheBytes / row));
+}
+
+// Partial dot products per row written by the epilogue of apply_op<T>.
+template <typename T> int op_dot_groups(const FftDims& d) {
+    return sizeof(T) == sizeof(float) ? sticks_to_sphere_pair_groups(d) : sticks_to_sphere_groups<T>(d);
 }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
 // kinetic/shift epilogue, then (optionally) the P_c GEMM pair.  pq_part (may be null,
 // only without the projection): per-row partial sums of Re<p, q> from the epilogue,
-// sticks_to_sphere_groups<T> of them per row.
+// op_dot_groups<T> of them per row.  FP64 rows are full spheres; FP32 rows are half
+// spheres of vectors real in r, transformed two rows per complex transform.
 template <typename T>
 void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const double* shift, int nshift,
               bool project, void* sticks_buf, double2* S, double* pq_part = nullptr) {
     const Basis& b = c.basis;
     PDEP_REQUIRE(!(project && pq_part), PDEP_EINVAL, "apply_op: partial dots are of the unprojected q");
     cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
-    const int npq = sticks_to_sphere_groups<T>(b.dims);
+    constexpr bool paired = sizeof(T) == sizeof(float);
+    const int npq = op_dot_groups<T>(b.dims);
     auto chain = [&](int chunk) {
+        if (paired) chunk += chunk & 1;   // pairs never straddle two blocks
         for (int r0 = 0; r0 < nrows; r0 += chunk) {
             const int nr = std::min(chunk, nrows - r0);
             const cplx<T>* pc = p + (long)r0 * ld;
             const bool per_row = nshift == nrows;
-            launch_sphere_to_sticks<T>(b.dims, b.tables, pc, ld, nr, nullptr, sk, c.stream);
-            launch_slab_hv<T>(b.dims, b.tables, sk, nr, vloc_of<T>(c), c.stream);
-            launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, EPI_SHIFTED_H, 0.0, pc, ld,
-                                       kin_of<T>(c), per_row ? shift + r0 : shift, per_row ? nr : nshift, nullptr,
-                                       c.stream, pq_part ? pq_part + (long)r0 * npq : nullptr);
+            const double* shc = per_row ? shift + r0 : shift;
+            const int nsh = per_row ? nr : nshift;
+            double* pqc = pq_part ? pq_part + (long)r0 * npq : nullptr;
+            if constexpr (paired) {
+                launch_sphere_to_sticks_pair<T>(b.dims, b.tables, pc, ld, nr, sk, c.stream);
+                launch_slab_hv<T>(b.dims, b.tables, sk, (nr + 1) / 2, vloc_of<T>(c), c.stream);
+                launch_sticks_to_sphere_pair<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, pc, ld, kin_of<T>(c),
+                                                shc, nsh, c.stream, pqc);
+            } else {
+                launch_sphere_to_sticks<T>(b.dims, b.tables, pc, ld, nr, nullptr, sk, c.stream);
+                launch_slab_hv<T>(b.dims, b.tables, sk, nr, vloc_of<T>(c), c.stream);
+                launch_sticks_to_sphere<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, EPI_SHIFTED_H, 0.0, pc, ld,
+                                           kin_of<T>(c), shc, nsh, nullptr, c.stream, pqc);
+            }
         }
     };
     int& tuned = fft_chunk_of<T>(c);
@@ -288,7 +316,9 @@ __global__ void k_iota_copy(int n, const double* __restrict__ sh, const double* 
 // into a compact set of slots, so every kernel runs on active rows only.
 template <typename T>
 int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit, ApplyStats& st) {
-    const int npw = c.basis.npw, nv = c.nv;
+    // FP32: half-sphere rows (entries k <= c of vectors real in r); FP64: full spheres
+    constexpr bool half = sizeof(T) == sizeof(float);
+    const int npw = half ? half_len(c.basis.npw) : c.basis.npw, nv = c.nv;
     hipStream_t s = c.stream;
     const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
     cplx<T>* X[2] = {static_cast<cplx<T>*>(c.ws(W_CX, vbytes)), static_cast<cplx<T>*>(c.ws(W_CX2, vbytes))};
@@ -303,7 +333,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const int pre = c.opts.precond;
     // per-row partial sums: <p, q> (stick groups of the H epilogue), <r, K r> and ||r||^2
     // (blocks of the CG step)
-    const int npq = sticks_to_sphere_groups<T>(c.basis.dims), nblk = (npw + 255) / 256;
+    const int npq = op_dot_groups<T>(c.basis.dims), nblk = (npw + 255) / 256;
     double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * (npq + 2 * nblk) * sizeof(double) + 64));
     double* rz_part = pq_part + (size_t)n * npq;
     double* rr_part = rz_part + (size_t)n * nblk;
@@ -316,7 +346,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     launch_cg_init<T>(n, npw, b, ld, X[0], R[0], Z[0], kin, sc.s_shift[0], n, pre, s);
     if (pre) project_c<T>(c, Z[0], ld, n, S);
     PDEP_HIP(hipMemcpyAsync(P[0], Z[0], vbytes, hipMemcpyDeviceToDevice, s));
-    launch_row_dots<T>(n, npw, R[0], ld, Z[0], ld, sc.s_rz[0], sc.rr, s);
+    launch_row_dots<T>(n, npw, R[0], ld, Z[0], ld, sc.s_rz[0], sc.rr, s, half);
     launch_fill_i32(sc.active, n, 1, s);
     launch_fill_zero(sc.n_active, sizeof(int), s);
     launch_cg_check(n, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], sc.s_rz[0], nullptr, sc.n_active, 0, s);
@@ -384,15 +414,15 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, sticks, S, pq_part);
                 st.op_applications++;
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s,
-                                   rz_part, rr_part, sc.rz_new, sc.rr);
+                                   rz_part, rr_part, sc.rz_new, sc.rr, half);
                 project_c<T>(c, z, ld, ncur, S);
                 if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             } else {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
                 st.op_applications++;
-                launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s);
+                launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s, half);
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, 1, sc.active, kin, sh, ncur, pre, s);
-                launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s);
+                launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s, half);
             }
             launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
@@ -487,10 +517,13 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         PDEP_HIP(hipMemcpyAsync(sc.shift, shift.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
         PDEP_HIP(hipMemcpyAsync(sc.thr2, thr2.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
         if (mixed) {
-            float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ld * sizeof(float2)));
-            launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ld, s);
-            cg_inner<float>(c, na, rhs, ld, sc, c.opts.cg_maxit, st);
-            launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ld, d_rows, d_invscale, x64, ld, s);
+            // the inner solve works on half spheres (the residual is real in r)
+            const int nh = half_len(npw);
+            const long ldh = sphere_ld(nh);
+            float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(float2)));
+            launch_convert_rows<double, float>(na, nh, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            cg_inner<float>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
+            launch_axpy_rows_half(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s);
         } else {
             double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ld * sizeof(double2)));
             launch_convert_rows<double, double>(na, npw, r64, ld, d_rows, d_scale, rhs, ld, s);
