@@ -92,6 +92,8 @@ def dominant_roofline(prof: dict, mfma_dtype: str):
                       "avg_launch_ms": round(rec["ms"] / max(rec["launches"], 1), 4),
                       "launches": rec["launches"]}
     if rec["flops"] > 0:
+        if name.endswith("_fp64"):
+            mfma_dtype = "f64"
         ach = rec["flops"] / t / 1e12
         peak = MFMA_PEAK_TFLOPS[mfma_dtype]
         r = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",

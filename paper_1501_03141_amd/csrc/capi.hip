@@ -73,7 +73,12 @@ void finish_setup(Ctx& c) {
     // weighted half-sphere copy for the projection coefficients of half-sphere rows
     c.psi32w.ensure(&c.al, (size_t)nv * ld32 * sizeof(float2));
     pdep::launch_fill_zero(c.psi32w.get(), (size_t)nv * ld32 * sizeof(float2), s);
-    pdep::launch_half_weights(nv, pdep::half_len(npw), c.psi32.as<float2>(), ld32, c.psi32w.as<float2>(), ld32, s);
+    pdep::launch_half_weights<float>(nv, pdep::half_len(npw), c.psi32.as<float2>(), ld32, c.psi32w.as<float2>(), ld32,
+                                     s);
+    c.psi64w.ensure(&c.al, (size_t)nv * npw * sizeof(double2));
+    pdep::launch_fill_zero(c.psi64w.get(), (size_t)nv * npw * sizeof(double2), s);
+    pdep::launch_half_weights<double>(nv, pdep::half_len(npw), c.psi64.as<double2>(), npw, c.psi64w.as<double2>(),
+                                      npw, s);
     c.eps_dev.ensure(&c.al, (size_t)nv * sizeof(double));
     PDEP_HIP(hipMemcpyAsync(c.eps_dev.get(), c.eps.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
     // residual of the orbitals in use

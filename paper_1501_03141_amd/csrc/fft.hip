@@ -1036,7 +1036,7 @@ void launch_sphere_to_sticks(const FftDims& d, const BasisTables& t, const cplx<
     check_sticks(d);
     check_rows(nrows);
     const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
-    ProfScope prof_(K_SPHERE_TO_STICKS, s, (double)nrows * (sp + sk));
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_SPHERE_TO_STICKS64 : K_SPHERE_TO_STICKS, s, (double)nrows * (sp + sk));
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sphere_to_sticks<T, NZ>), stick_grid(d, nrows), dim3(kThreads), stick_lds<T>(d), s, d, t,
                            in, ld_in, gscale, sticks);
@@ -1054,7 +1054,8 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
     check_sticks(d);
     check_rows(nrows);
     const double sp = (double)d.npw * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
-    ProfScope prof_(K_STICKS_TO_SPHERE, s, (double)nrows * (sk + sp + (epi == EPI_SHIFTED_H ? sp : 0.0)));
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_STICKS_TO_SPHERE64 : K_STICKS_TO_SPHERE, s,
+                    (double)nrows * (sk + sp + (epi == EPI_SHIFTED_H ? sp : 0.0)));
     if constexpr (sizeof(T) == sizeof(float)) {
         if (stick_reg_ok(d)) {
             const dim3 grid((d.ns + kRegStickGroup - 1) / kRegStickGroup, nrows);
@@ -1090,7 +1091,8 @@ void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const 
     const int npair = (nrows + 1) / 2;
     check_rows(npair);
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
-    ProfScope prof_(K_SPHERE_TO_STICKS, s, (double)nrows * hp + (double)npair * sk);
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_SPHERE_TO_STICKS64 : K_SPHERE_TO_STICKS, s,
+                    (double)nrows * hp + (double)npair * sk);
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sphere_to_sticks_pair<T, NZ>), stick_grid(d, npair), dim3(kThreads), stick_lds<T>(d), s,
                            d, t, in, ld_in, nrows, sticks);
@@ -1107,7 +1109,8 @@ void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const 
     const int npair = (nrows + 1) / 2;
     check_rows(npair);
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
-    ProfScope prof_(K_STICKS_TO_SPHERE, s, (double)npair * sk + 2.0 * nrows * hp);
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_STICKS_TO_SPHERE64 : K_STICKS_TO_SPHERE, s,
+                    (double)npair * sk + 2.0 * nrows * hp);
     const dim3 grid(sticks_to_sphere_pair_groups(d), npair);
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sticks_to_sphere_pair<T, NZ>), grid, dim3(kThreads), stick_lds<T>(d), s, d, t, sticks,

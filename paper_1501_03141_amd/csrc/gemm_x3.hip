@@ -17,6 +17,11 @@
 //   gemm_update Y[n][k] += sum_m S[n][m] A[m][k]: the interleaved S row is the left
 //               operand; the right operand has the column tile of Re (pairs
 //               (a_re, -a_im) down the contraction) and of Im (pairs (a_im, a_re)).
+// Real coefficients (rows real in r, kept as half spheres) need half the products:
+//   gemm_ahb_real     S[n][m] = Re sum_k conj(A[m][k]) B[n][k] = the real dot product
+//                     of the interleaved rows (only the real row tile of A);
+//   gemm_update_real  Y[n][k] += sum_m S[n][m] A[m][k] with S real: a real GEMM over the
+//                     interleaved columns k' = 2k + c of Y and A.
 #include <cstdint>
 
 #include "pdep_internal.h"
@@ -86,10 +91,13 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 // k advances 16 complex (32 real) per step; the B tile goes through LDS (shared by
 // the waves of one n range), the A fragments are loaded by each wave directly.
 // Requires lda, ldb, K-chunk starts multiple of 4 complex (16-byte aligned loads).
-template <int WM, int CT>
+// REAL: only the real parts, written as floats (Sv: float [N][lds]); otherwise complex
+// (Sv: float2 [N][lds], imaginary parts stored as zero when real_out is set).
+template <int WM, int CT, bool REAL>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
-                                                     const float2* __restrict__ B, long ldb, float2* __restrict__ S,
+                                                     const float2* __restrict__ B, long ldb, void* __restrict__ Sv,
                                                      long lds, int kchunk, int real_out) {
+    constexpr int NSUB = REAL ? 1 : 2;   // row tiles of A: real part, imaginary part
     constexpr int WN = 4 / WM;
     constexpr int BMC = 32 * WM, BN = 16 * CT * WN;
     constexpr int IT = BN / 64;   // B staging items per thread (4 complex each)
@@ -99,14 +107,14 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
     const int m0 = blockIdx.x * BMC, n0 = blockIdx.y * BN;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
-    S += (long)blockIdx.z * N * lds;
+    const long zoff = (long)blockIdx.z * N * lds;
     const int lr = lane & 15, lq = lane >> 4;
 
-    x3_f4 acc[2][2][CT];
+    x3_f4 acc[2][NSUB][CT];
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < NSUB; ++s)
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[g][s][c] = x3_f4{0.f, 0.f, 0.f, 0.f};
 
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
             *reinterpret_cast<x3_u4*>(&Bs[0][off]) = h;
             *reinterpret_cast<x3_u4*>(&Bs[1][off]) = l;
         }
-        x3_u4 ah[2][2], al[2][2];   // [g][s]
+        x3_u4 ah[2][NSUB], al[2][NSUB];   // [g][s]
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
 #pragma unroll
@@ -154,10 +162,12 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
                 ah[g][0][q] = w.x;
                 al[g][0][q] = w.y;
             }
+            if constexpr (!REAL) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ah[g][1][q] = rot_neg_first(ah[g][0][q]);
-                al[g][1][q] = rot_neg_first(al[g][0][q]);
+                for (int q = 0; q < 4; ++q) {
+                    ah[g][NSUB - 1][q] = rot_neg_first(ah[g][0][q]);
+                    al[g][NSUB - 1][q] = rot_neg_first(al[g][0][q]);
+                }
             }
         }
         __syncthreads();
@@ -170,7 +180,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll
-                for (int s = 0; s < 2; ++s) acc[g][s][c] = mma3(ah[g][s], al[g][s], bh, bl, acc[g][s][c]);
+                for (int s = 0; s < NSUB; ++s) acc[g][s][c] = mma3(ah[g][s], al[g][s], bh, bl, acc[g][s][c]);
         }
         __syncthreads();
     }
@@ -182,7 +192,135 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
             for (int i = 0; i < 4; ++i) {
                 const int m = m0 + 32 * wm + 16 * g + 4 * lq + i;
                 const int n = n0 + 16 * CT * wn + 16 * c + lr;
-                if (m < M && n < N) S[(long)n * lds + m] = make_float2(acc[g][0][c][i], real_out ? 0.f : acc[g][1][c][i]);
+                if (m < M && n < N) {
+                    if constexpr (REAL) {
+                        static_cast<float*>(Sv)[zoff + (long)n * lds + m] = acc[g][0][c][i];
+                    } else {
+                        static_cast<float2*>(Sv)[zoff + (long)n * lds + m] =
+                            make_float2(acc[g][0][c][i], real_out ? 0.f : acc[g][NSUB - 1][c][i]);
+                    }
+                }
+            }
+}
+
+// S[n][m] = sum_z P[z][n][m] over real partial products (z in order).
+__global__ void k_splitk_reduce_real(int M, int N, long lds, int splits, const float* __restrict__ P,
+                                     float* __restrict__ S) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)N * M) return;
+    const long n = e / M, m = e - n * M;
+    const long stride = (long)N * lds;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += P[z * stride + n * lds + m];
+    S[n * lds + m] = v;
+}
+
+// Eight consecutive floats p[0..7] (16-byte aligned); entries at or beyond `avail` read as zero.
+__device__ __forceinline__ void load8f(const float* p, int avail, float (&v)[8]) {
+    if (avail >= 8) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        const float4 b = *reinterpret_cast<const float4*>(p + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = q < avail ? p[q] : 0.f;
+    }
+}
+
+// Y[n][k] = beta Y[n][k] + alpha sum_m S[n][m] A[m][k], S real (float [N][lds]).
+// Real GEMM over the real and imaginary parts of Y and A.  Workgroup tile: 128 rows n
+// (32 per wave) x 64 complex columns k; the contraction advances 32 m per step.  The A
+// tile (32 m x 64 k) is split into LDS as [column][m] (bf16 pairs of adjacent m per
+// dword, hi and lo planes), column 32 t + 16 c + j holding part c of k = 16 t + j, so
+// that output tiles 2t and 2t + 1 give a lane the real and imaginary part of the same
+// k (stored as one float2).  Each wave loads its own S fragments (8 consecutive m).
+// Requires lda and lds multiples of 4 (16-byte aligned loads).
+__global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, const float2* __restrict__ A,
+                                                         long lda, const float* __restrict__ S, long lds,
+                                                         float alpha, float beta, float2* __restrict__ Y, long ldy) {
+    constexpr int BK = 64, BNR = 128;
+    __shared__ __align__(16) unsigned char As[2][2 * BK * kRowB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k0 = blockIdx.x * BK, n0 = blockIdx.y * BNR;
+    const int lr = lane & 15, lq = lane >> 4;
+
+    x3_f4 acc[2][8];   // [a: 16-row half of the wave's rows][b: 16 real columns]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = x3_f4{0.f, 0.f, 0.f, 0.f};
+
+    // A staging: thread -> (rows 2 mp and 2 mp + 1, 4 consecutive k from kg)
+    const int mp = tid & 15, kg = 4 * (tid >> 4);
+    float rs[2][8], ra[2][8];
+    auto fetch = [&](int mc) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int n = n0 + 32 * wave + 16 * a + lr;
+            const int m = mc + 8 * lq;
+            const int avail = n < N ? M - m : 0;
+            load8f(S + (long)(n < N ? n : 0) * lds + m, avail, rs[a]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = mc + 2 * mp + h, k = k0 + kg;
+            const int avail = m < M ? K - k : 0;
+            load4(A + (long)(m < M ? m : 0) * lda + k, avail, ra[h]);
+        }
+    };
+
+    fetch(0);
+    for (int mc = 0; mc < M; mc += 32) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint2 w = split2(ra[0][2 * q + c], ra[1][2 * q + c]);
+                const int kl = kg + q;
+                const int off = (32 * (kl >> 4) + 16 * c + (kl & 15)) * kRowB + mp * 4;
+                *reinterpret_cast<uint32_t*>(&As[0][off]) = w.x;
+                *reinterpret_cast<uint32_t*>(&As[1][off]) = w.y;
+            }
+        x3_u4 sh[2], sl[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint2 w = split2(rs[a][2 * q], rs[a][2 * q + 1]);
+                sh[a][q] = w.x;
+                sl[a][q] = w.y;
+            }
+        __syncthreads();
+        if (mc + 32 < M) fetch(mc + 32);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int off = (16 * b + lr) * kRowB + lq * 16;
+            const x3_u4 bh = *reinterpret_cast<const x3_u4*>(&As[0][off]);
+            const x3_u4 bl = *reinterpret_cast<const x3_u4*>(&As[1][off]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) acc[a][b] = mma3(sh[a], sl[a], bh, bl, acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
+                const int k = k0 + 16 * t + lr;
+                if (n < N && k < K) {
+                    float2* y = Y + (long)n * ldy + k;
+                    float2 o = make_float2(alpha * acc[a][2 * t][i], alpha * acc[a][2 * t + 1][i]);
+                    if (beta != 0.f) {
+                        const float2 old = *y;
+                        o.x += beta * old.x;
+                        o.y += beta * old.y;
+                    }
+                    *y = o;
+                }
             }
 }
 
@@ -287,8 +425,12 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3(int M, int N, int K, con
 
 }  // namespace
 
-void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
-                        long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out) {
+namespace {
+
+// REAL: S and work are float arrays (real parts only).
+template <bool REAL>
+void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, void* S, long lds,
+                 void* work, size_t work_elems, hipStream_t s, bool real_out) {
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
@@ -306,20 +448,63 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
     const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
     if (splits > 1) splits = (K + kchunk - 1) / kchunk;
     grid.z = splits;
-    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * sizeof(float2),
-                    8.0 * (double)M * N * K);
-    float2* out = splits > 1 ? work : S;
+    // algorithmic: complex products (8 real flops) or their real parts (4)
+    const double esz = REAL ? sizeof(float) : sizeof(float2);
+    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * esz,
+                    (REAL ? 4.0 : 8.0) * (double)M * N * K);
+    void* out = splits > 1 ? work : S;
     const int ro = (real_out && splits == 1) ? 1 : 0;
-    if (WM == 1) hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
-                                          ro);
-    else if (WM == 2) hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
-                                          ro);
-    else if (CT == 8) hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
-                                          ro);
-    else hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds, kchunk,
-                                          ro);
+    if (WM == 1)
+        hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
+                           kchunk, ro);
+    else if (WM == 2)
+        hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
+                           kchunk, ro);
+    else if (CT == 8)
+        hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
+                           kchunk, ro);
+    else
+        hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
+                           kchunk, ro);
     PDEP_HIP(hipGetLastError());
-    if (splits > 1) launch_splitk_reduce_f32(M, N, lds, splits, work, S, s, real_out);
+    if (splits > 1) {
+        if constexpr (REAL) {
+            const long tot = (long)N * M;
+            hipLaunchKernelGGL(k_splitk_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds,
+                               splits, static_cast<const float*>(work), static_cast<float*>(S));
+            PDEP_HIP(hipGetLastError());
+        } else {
+            launch_splitk_reduce_f32(M, N, lds, splits, static_cast<const float2*>(work), static_cast<float2*>(S), s,
+                                     real_out);
+        }
+    }
+}
+
+}  // namespace
+
+void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,
+                        long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out) {
+    gemm_ahb_x3<false>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, real_out);
+}
+
+void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
+                             long lds, float* work, size_t work_elems, hipStream_t s) {
+    PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_real: lds must be a multiple of 4");
+    gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true);
+}
+
+void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
+                                double alpha, double beta, float2* Y, long ldy, hipStream_t s) {
+    if (N <= 0 || K <= 0) return;
+    PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
+                 "gemm_update_x3_real: leading dimensions must be multiples of 4");
+    PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "gemm_update_x3_real: N too large");
+    dim3 grid((K + 63) / 64, (N + 127) / 128);
+    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
+                    (double)N * K * sizeof(float2) * (beta != 0.0 ? 2.0 : 1.0), 4.0 * (double)M * N * K);
+    hipLaunchKernelGGL(k_gemm_update_x3r, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha, (float)beta, Y,
+                       ldy);
+    PDEP_HIP(hipGetLastError());
 }
 
 void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,

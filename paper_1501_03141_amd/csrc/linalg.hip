@@ -446,39 +446,29 @@ __global__ void k_compact_s1(int npw, int g0, const double2* __restrict__ in, lo
     out[(long)row * ldo + k] = in[(long)row * ldi + (k < g0 ? k : k + 1)];
 }
 
-// x[rows[r]] += rowscale[r] * (d[r] extended from the half sphere): entries k < c and
-// their mirrors npw - 1 - k (conjugate), the centre c = (npw - 1) / 2 real.
-__global__ void k_axpy_rows_half(int npw, const float2* __restrict__ d, long ldd, const int* __restrict__ rows,
-                                 const double* __restrict__ rowscale, double2* __restrict__ x, long ldx) {
+// out[r][k] = w_k in[r][k] for k < K: weight 2 except for the last entry (the centre of a
+// half-sphere row), so that Re sum_k conj(out) y over the half sphere is the full inner product.
+template <typename T>
+__global__ void k_half_weights(int K, const cplx<T>* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (k >= K) return;
+    const T w = k == K - 1 ? T(1) : T(2);
+    const cplx<T> v = in[(long)row * ldi + k];
+    out[(long)row * ldo + k] = mk<T>(w * v.x, w * v.y);
+}
+
+// Half-sphere rows -> full rows in place: x[npw - 1 - k] = conj x[k] for k < c, and the
+// centre c = (npw - 1) / 2 made real.
+__global__ void k_sym_expand(int npw, double2* __restrict__ x, long ld) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
     const int c = (npw - 1) / 2;
     if (k > c) return;
-    const double s = rowscale[row];
-    const float2 v = d[(long)row * ldd + k];
-    double2* xr = x + (long)(rows ? rows[row] : row) * ldx;
-    const double vx = s * (double)v.x, vy = k == c ? 0.0 : s * (double)v.y;
-    double2 a = xr[k];
-    a.x += vx;
-    a.y += vy;
-    xr[k] = a;
-    if (k < c) {
-        double2 b = xr[npw - 1 - k];
-        b.x += vx;
-        b.y -= vy;
-        xr[npw - 1 - k] = b;
-    }
-}
-
-// out[r][k] = w_k in[r][k] for k < K: weight 2 except for the last entry (the centre of a
-// half-sphere row), so that Re sum_k conj(out) y over the half sphere is the full inner product.
-__global__ void k_half_weights(int K, const float2* __restrict__ in, long ldi, float2* __restrict__ out, long ldo) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int row = blockIdx.y;
-    if (k >= K) return;
-    const float w = k == K - 1 ? 1.f : 2.f;
-    const float2 v = in[(long)row * ldi + k];
-    out[(long)row * ldo + k] = make_float2(w * v.x, w * v.y);
+    double2* r = x + (long)row * ld;
+    const double2 v = r[k];
+    if (k == c) r[k].y = 0.0;
+    else r[npw - 1 - k] = make_double2(v.x, -v.y);
 }
 
 // Make rows exactly Hermitian-symmetric: c_k and c_{npw-1-k} (the coefficients of G and
@@ -519,7 +509,8 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
     const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
     if (splits > 1) splits = (K + kchunk - 1) / kchunk;
     grid.z = splits;
-    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * sizeof(cplx<T>),
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_GEMM_AHB64 : K_GEMM_AHB, s,
+                    ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * sizeof(cplx<T>),
                     8.0 * (double)M * N * K);
     hipLaunchKernelGGL(k_gemm_ahb<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, splits > 1 ? work : S, lds,
                        kchunk, real_out ? 1 : 0);
@@ -547,7 +538,8 @@ void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const c
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_update: N too large");
     dim3 grid((K + 63) / 64, (N + 63) / 64);
-    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(cplx<T>) + (double)N * M * sizeof(cplx<T>) +
+    ProfScope prof_(sizeof(T) == sizeof(double) ? K_GEMM_UPDATE64 : K_GEMM_UPDATE, s,
+                    (double)M * K * sizeof(cplx<T>) + (double)N * M * sizeof(cplx<T>) +
                     (double)N * K * sizeof(cplx<T>) * (beta != 0.0 ? 2.0 : 1.0), 8.0 * (double)M * N * K);
     hipLaunchKernelGGL(k_gemm_update<T>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y, ldy);
     PDEP_HIP(hipGetLastError());
@@ -627,18 +619,19 @@ void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* r
     PDEP_HIP(hipGetLastError());
 }
 
-void launch_axpy_rows_half(int nrows, int npw, const float2* d, long ldd, const int* rows, const double* rowscale,
-                           double2* x, long ldx, hipStream_t s) {
+template <typename T>
+void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>* out, long ldo, hipStream_t s) {
     if (nrows <= 0) return;
-    ProfScope prof_(K_MISC, s);
-    hipLaunchKernelGGL(k_axpy_rows_half, rows_grid((npw + 1) / 2, nrows), dim3(256), 0, s, npw, d, ldd, rows, rowscale,
-                       x, ldx);
+    hipLaunchKernelGGL(k_half_weights<T>, rows_grid(K, nrows), dim3(256), 0, s, K, in, ldi, out, ldo);
     PDEP_HIP(hipGetLastError());
 }
+template void launch_half_weights<float>(int, int, const float2*, long, float2*, long, hipStream_t);
+template void launch_half_weights<double>(int, int, const double2*, long, double2*, long, hipStream_t);
 
-void launch_half_weights(int nrows, int K, const float2* in, long ldi, float2* out, long ldo, hipStream_t s) {
+void launch_sym_expand(int nrows, int npw, double2* x, long ld, hipStream_t s) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_half_weights, rows_grid(K, nrows), dim3(256), 0, s, K, in, ldi, out, ldo);
+    ProfScope prof_(K_MISC, s, 32.0 * nrows * (double)half_len(npw));
+    hipLaunchKernelGGL(k_sym_expand, rows_grid(half_len(npw), nrows), dim3(256), 0, s, npw, x, ld);
     PDEP_HIP(hipGetLastError());
 }
 

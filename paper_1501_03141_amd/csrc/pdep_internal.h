@@ -80,7 +80,8 @@ bool verbose();
 // Kernel classes timed by the opt-in profiler (prof.hip; see pdep_profile_enable).
 enum KernelId : int {
     K_SPHERE_TO_STICKS = 0, K_SLAB_HV, K_STICKS_TO_SPHERE, K_SLAB_INV_STORE, K_SLAB_FWD_PRODUCT,
-    K_SLAB_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_SLAB_HV64, K_COUNT
+    K_SLAB_DENSITY, K_GEMM_AHB, K_GEMM_UPDATE, K_ROW_DOTS, K_CG_UPDATE, K_MISC, K_SLAB_HV64,
+    K_SPHERE_TO_STICKS64, K_STICKS_TO_SPHERE64, K_GEMM_AHB64, K_GEMM_UPDATE64, K_COUNT
 };
 // Records HIP events around the launch made during its lifetime (when profiling is on),
 // with the launch's algorithmic HBM bytes and flops.
@@ -207,6 +208,12 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
                         long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out = false);
 void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,
                            double beta, float2* Y, long ldy, hipStream_t s);
+// Real-coefficient BF16x3 pair (S real, float [N][lds], lds multiple of 4):
+//   S[n][m] = Re sum_k conj(A[m][k]) B[n][k];   Y[n][k] = beta Y + alpha sum_m S[n][m] A[m][k]
+void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
+                             long lds, float* work, size_t work_elems, hipStream_t s);
+void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
+                                double alpha, double beta, float2* Y, long ldy, hipStream_t s);
 // S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)
 void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s,
                               bool real_out = false);
@@ -245,12 +252,11 @@ void launch_convert_rows(int nrows, int K, const cplx<Tin>* in, long ldi, const 
 template <typename T>
 void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* rows,
                       const double* rowscale, double2* x, long ldx, hipStream_t s);
-// x[rows[r]] += rowscale[r] * d[r] for half-sphere rows d (FP32, entries k <= c): entry k
-// and its mirror npw - 1 - k (conjugate) of the full rows x; the centre takes the real part.
-void launch_axpy_rows_half(int nrows, int npw, const float2* d, long ldd, const int* rows, const double* rowscale,
-                           double2* x, long ldx, hipStream_t s);
 // out[r][k] = 2 in[r][k] for k < K - 1, in[r][K - 1] at k = K - 1 (half-sphere weights)
-void launch_half_weights(int nrows, int K, const float2* in, long ldi, float2* out, long ldo, hipStream_t s);
+template <typename T>
+void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>* out, long ldo, hipStream_t s);
+// half-sphere rows -> full rows in place (mirror entries npw - 1 - k = conjugates, centre real)
+void launch_sym_expand(int nrows, int npw, double2* x, long ld, hipStream_t s);
 // out[r] = a[rows[r]] - b[r]
 void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b,
                      long ldb, double2* out, long ldo, hipStream_t s);
@@ -316,7 +322,7 @@ struct Ctx {
     double gs_residual = 0.0;
     Buf vloc64, vloc32;                   // [ng] z-major
     Buf psi64, psi32;                     // [nv][npw] complex FP64; [nv][sphere_ld(npw)] FP32
-    Buf psi32w;                           // psi32 with the half-sphere weights (2 off the centre)
+    Buf psi32w, psi64w;                   // psi32 / psi64 with the half-sphere weights (2 off the centre)
     Buf u64;                              // [nv][ng] complex grids, z-major
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic

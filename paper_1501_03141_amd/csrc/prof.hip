@@ -64,7 +64,9 @@ Profiler& prof() {
 
 const char* kNames[K_COUNT] = {"sphere_to_sticks", "slab_hv",    "sticks_to_sphere", "slab_inv_store",
                                "slab_fwd_product", "slab_density", "gemm_ahb",      "gemm_update",
-                               "row_dots",         "cg_update",    "misc",          "slab_hv_fp64"};
+                               "row_dots",         "cg_update",    "misc",          "slab_hv_fp64",
+                               "sphere_to_sticks_fp64", "sticks_to_sphere_fp64", "gemm_ahb_fp64",
+                               "gemm_update_fp64"};
 
 }  // namespace
 

@@ -70,34 +70,36 @@ int half_len(int npw) { return (npw + 1) / 2; }
 long coef_ld(int nv) { return ((long)nv + 3) / 4 * 4; }
 size_t coef_bytes(int nv, int nrows) { return (size_t)nrows * coef_ld(nv) * sizeof(double2); }
 
-// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows rows.  S: work space of coef_bytes(nv, nrows).
-// FP64 rows are full spheres.  FP32 rows are half spheres of vectors real in r (entries
-// k <= c, the centre last): with Psi real in r as well, Psi^H Y is real and equals
+// Y <- P_c Y = Y - Psi (Psi^H Y) for nrows half-sphere rows (entries k <= c of vectors
+// real in r, the centre last).  With Psi real in r as well, Psi^H Y is real and equals
 // Re sum_{k <= c} w_k conj(Psi_k) Y_k with w = 2 off the centre (the weights sit in the
-// copy psi32w), and the update touches the half sphere only.  In the BF16x3 mode the
-// FP32 pair runs on the bf16 matrix cores (three products).
+// copies psi32w / psi64w), and the update touches the half sphere only.  S: work space
+// of coef_bytes(nv, nrows).  In the BF16x3 mode the FP32 pair runs on the bf16 matrix
+// cores (three products, real coefficients).
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
-    const int npw = c.basis.npw, nv = c.nv;
+    const int npw = c.basis.npw, nv = c.nv, nh = half_len(npw);
     const long lds = coef_ld(nv);
     cplx<T>* St = reinterpret_cast<cplx<T>*>(S);
     const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
     cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
-    if constexpr (sizeof(T) == sizeof(float)) {
-        const int nh = half_len(npw);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
+                           true);
+        launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), npw, St, lds, -1.0, 1.0, Y, ld, c.stream);
+    } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
         if (c.opts.precision == PDEP_MIXED_BF16X3) {
-            launch_gemm_ahb_x3(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
-            launch_gemm_update_x3(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
+            float* Sr = reinterpret_cast<float*>(S);
+            float* wr = reinterpret_cast<float*>(work);
+            launch_gemm_ahb_x3_real(nv, nrows, nh, pw, lp, Y, ld, Sr, lds, wr, 2 * split_elems, c.stream);
+            launch_gemm_update_x3_real(nv, nrows, nh, psi_of<T>(c), lp, Sr, lds, -1.0, 1.0, Y, ld, c.stream);
         } else {
             launch_gemm_ahb<T>(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
             launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
         }
-        return;
     }
-    launch_gemm_ahb<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), Y, ld, St, lds, work, split_elems, c.stream);
-    launch_gemm_update<T>(nv, nrows, npw, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream);
 }
 
 // Rows per launch of the transform chain (sticks pass, slab pass, sticks pass).  With
@@ -128,29 +130,29 @@ template <typename T> int& fft_chunk_of(Ctx& c) { return sizeof(T) == sizeof(flo
 
 template <typename T> int fft_chunk_rule(const Ctx& c) {
     const FftDims& d = c.basis.dims;
-    // FP32 rows are paired: two rows per sticks row
-    const double row = (double)d.nz * d.sld * sizeof(cplx<T>) / (sizeof(T) == sizeof(float) ? 2.0 : 1.0);
+    // rows are paired: two rows per sticks row
+    const double row = (double)d.nz * d.sld * sizeof(cplx<T>) / 2.0;
     return std::max(32, (int)(kChunkCacheBytes / row));
 }
 
-// Partial dot products per row written by the epilogue of apply_op<T>.
-template <typename T> int op_dot_groups(const FftDims& d) {
-    return sizeof(T) == sizeof(float) ? sticks_to_sphere_pair_groups(d) : sticks_to_sphere_groups<T>(d);
-}
+// Partial dot products per row written by the epilogue of apply_op<T> on half-sphere rows.
+int op_dot_groups(const FftDims& d) { return sticks_to_sphere_pair_groups(d); }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
 // kinetic/shift epilogue, then (optionally) the P_c GEMM pair.  pq_part (may be null,
 // only without the projection): per-row partial sums of Re<p, q> from the epilogue,
-// op_dot_groups<T> of them per row.  FP64 rows are full spheres; FP32 rows are half
-// spheres of vectors real in r, transformed two rows per complex transform.
+// op_dot_groups of them per row.  half: the rows are half spheres of vectors real in r,
+// transformed two rows per complex transform (the block size of the chain is tuned);
+// otherwise full spheres, one transform per row, all rows in one block.
 template <typename T>
 void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const double* shift, int nshift,
-              bool project, void* sticks_buf, double2* S, double* pq_part = nullptr) {
+              bool project, bool half, void* sticks_buf, double2* S, double* pq_part = nullptr) {
     const Basis& b = c.basis;
     PDEP_REQUIRE(!(project && pq_part), PDEP_EINVAL, "apply_op: partial dots are of the unprojected q");
+    PDEP_REQUIRE(half || !(project || pq_part), PDEP_EINVAL, "apply_op: projection and dots need half-sphere rows");
     cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
-    constexpr bool paired = sizeof(T) == sizeof(float);
-    const int npq = op_dot_groups<T>(b.dims);
+    const bool paired = half;
+    const int npq = op_dot_groups(b.dims);
     auto chain = [&](int chunk) {
         if (paired) chunk += chunk & 1;   // pairs never straddle two blocks
         for (int r0 = 0; r0 < nrows; r0 += chunk) {
@@ -160,7 +162,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
             const double* shc = per_row ? shift + r0 : shift;
             const int nsh = per_row ? nr : nshift;
             double* pqc = pq_part ? pq_part + (long)r0 * npq : nullptr;
-            if constexpr (paired) {
+            if (paired) {
                 launch_sphere_to_sticks_pair<T>(b.dims, b.tables, pc, ld, nr, sk, c.stream);
                 launch_slab_hv<T>(b.dims, b.tables, sk, (nr + 1) / 2, vloc_of<T>(c), c.stream);
                 launch_sticks_to_sphere_pair<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, pc, ld, kin_of<T>(c),
@@ -173,6 +175,10 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
             }
         }
     };
+    if (!half) {
+        chain(nrows);
+        return;
+    }
     int& tuned = fft_chunk_of<T>(c);
     if (tuned == 0) tuned = fft_chunk_env(sizeof(T) == sizeof(double));
     if (tuned == 0 && nrows >= kTuneRows) {
@@ -212,7 +218,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
 void apply_h64(Ctx& c, const double2* x, long ldx, int nrows, const double* shift, int nshift, double2* out,
                long ldo, double2* sticks_buf) {
     PDEP_REQUIRE(ldx == ldo, PDEP_EINVAL, "apply_h64: ld mismatch");
-    apply_op<double>(c, x, out, ldx, nrows, shift, nshift, false, sticks_buf, nullptr);
+    apply_op<double>(c, x, out, ldx, nrows, shift, nshift, false, false, sticks_buf, nullptr);
 }
 
 namespace {
@@ -316,9 +322,9 @@ __global__ void k_iota_copy(int n, const double* __restrict__ sh, const double* 
 // into a compact set of slots, so every kernel runs on active rows only.
 template <typename T>
 int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit, ApplyStats& st) {
-    // FP32: half-sphere rows (entries k <= c of vectors real in r); FP64: full spheres
-    constexpr bool half = sizeof(T) == sizeof(float);
-    const int npw = half ? half_len(c.basis.npw) : c.basis.npw, nv = c.nv;
+    // half-sphere rows (entries k <= c of vectors real in r)
+    constexpr bool half = true;
+    const int npw = half_len(c.basis.npw), nv = c.nv;
     hipStream_t s = c.stream;
     const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
     cplx<T>* X[2] = {static_cast<cplx<T>*>(c.ws(W_CX, vbytes)), static_cast<cplx<T>*>(c.ws(W_CX2, vbytes))};
@@ -333,7 +339,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const int pre = c.opts.precond;
     // per-row partial sums: <p, q> (stick groups of the H epilogue), <r, K r> and ||r||^2
     // (blocks of the CG step)
-    const int npq = op_dot_groups<T>(c.basis.dims), nblk = (npw + 255) / 256;
+    const int npq = op_dot_groups(c.basis.dims), nblk = (npw + 255) / 256;
     double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * (npq + 2 * nblk) * sizeof(double) + 64));
     double* rz_part = pq_part + (size_t)n * npq;
     double* rr_part = rz_part + (size_t)n * nblk;
@@ -411,14 +417,14 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             // ||r||^2 from the step that updates r.  Without the preconditioner z = r, q
             // is projected every time and the products are separate passes.
             if (pre) {
-                apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, sticks, S, pq_part);
+                apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
                 st.op_applications++;
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s,
                                    rz_part, rr_part, sc.rz_new, sc.rr, half);
                 project_c<T>(c, z, ld, ncur, S);
                 if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             } else {
-                apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, sticks, S);
+                apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, true, sticks, S);
                 st.op_applications++;
                 launch_row_dots<T>(ncur, npw, p, ld, q, ld, sc.pq, nullptr, s, half);
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, 1, sc.active, kin, sh, ncur, pre, s);
@@ -445,14 +451,15 @@ template <typename T> cplx<T>* cg_solution(Ctx& c) { return c.w[W_XOUT].as<cplx<
 
 }  // namespace
 
-// Solve all n rows of b64 to opts.cg_tol; x64 receives dc (not yet re-projected).
+// Solve all n rows of b64 to opts.cg_tol; x64 receives dc (not yet re-projected).  The
+// rows are half spheres (entries k <= c of vectors real in r, row stride ld).
 // ref2 (may be null): per-row squared norm of the right-hand side before P_c.  A row
 // whose projected norm is below 1e-13 of it carries only rounding noise (the
 // perturbation acts inside the occupied space, e.g. a constant dV) and is solved as
 // b = 0, x = 0.
 void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyStats& st,
                 const double* ref2) {
-    const int npw = c.basis.npw, nv = c.nv;
+    const int npw = half_len(c.basis.npw), nv = c.nv;
     hipStream_t s = c.stream;
     const double tol = c.opts.cg_tol;
     const bool mixed = c.opts.precision != PDEP_FP64;
@@ -468,7 +475,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     CgScalars sc = cg_scalars(c, n);
 
     std::vector<double> bb(n), rr(n), dots(n);
-    launch_row_dots<double>(n, npw, b64, ld, b64, ld, sc.rr, nullptr, s);
+    launch_row_dots<double>(n, npw, b64, ld, b64, ld, sc.rr, nullptr, s, true);
     PDEP_HIP(hipMemcpyAsync(bb.data(), sc.rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
     launch_fill_zero(x64, vb64, s);
     PDEP_HIP(hipMemcpyAsync(r64, b64, vb64, hipMemcpyDeviceToDevice, s));
@@ -516,30 +523,29 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         PDEP_HIP(hipMemcpyAsync(d_rows, rows.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
         PDEP_HIP(hipMemcpyAsync(sc.shift, shift.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
         PDEP_HIP(hipMemcpyAsync(sc.thr2, thr2.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+        const long ldh = sphere_ld(npw);
         if (mixed) {
-            // the inner solve works on half spheres (the residual is real in r)
-            const int nh = half_len(npw);
-            const long ldh = sphere_ld(nh);
             float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(float2)));
-            launch_convert_rows<double, float>(na, nh, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
             cg_inner<float>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
-            launch_axpy_rows_half(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s);
+            launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s);
         } else {
-            double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ld * sizeof(double2)));
-            launch_convert_rows<double, double>(na, npw, r64, ld, d_rows, d_scale, rhs, ld, s);
-            cg_inner<double>(c, na, rhs, ld, sc, c.opts.cg_maxit, st);
-            launch_axpy_rows<double>(na, npw, cg_solution<double>(c), ld, d_rows, d_invscale, x64, ld, s);
+            double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(double2)));
+            launch_convert_rows<double, double>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            cg_inner<double>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
+            launch_axpy_rows<double>(na, npw, cg_solution<double>(c), ldh, d_rows, d_invscale, x64, ld, s);
         }
         std::vector<int> its(na);
         PDEP_HIP(hipMemcpyAsync(its.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
         // true FP64 residual of the rows just updated
         launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
-        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, c.ws(W_STICKS, (size_t)na * sticks_row_bytes(c)),
+        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, true,
+                         c.ws(W_STICKS, (size_t)na * sticks_row_bytes(c)),
                          static_cast<double2*>(c.ws(W_S, coef_bytes(nv, na))));
         st.op_applications++;
         launch_sub_rows(na, npw, b64, ld, d_rows, qa, ld, qa, ld, s);
         launch_scatter_rows(na, npw, qa, ld, d_rows, r64, ld, s);
-        launch_row_dots<double>(na, npw, qa, ld, qa, ld, sc.rr, nullptr, s);
+        launch_row_dots<double>(na, npw, qa, ld, qa, ld, sc.rr, nullptr, s, true);
         PDEP_HIP(hipMemcpyAsync(dots.data(), sc.rr, na * sizeof(double), hipMemcpyDeviceToHost, s));
         PDEP_HIP(hipStreamSynchronize(s));
         int itmax = 0;
@@ -614,13 +620,15 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
                                         nullptr, 0, nullptr, s);
         // dV and u_v are real in r, so b is Hermitian-symmetric up to rounding: make it exact
         launch_sym_fix(nrow, npw, b64, ld, s);
+        // from here the rows are half spheres (the first half_len(npw) entries of each row)
         double* ref2 = static_cast<double*>(c.ws(W_REF2, (size_t)nrow * sizeof(double)));
-        launch_row_dots<double>(nrow, npw, b64, ld, b64, ld, ref2, nullptr, s);
+        launch_row_dots<double>(nrow, half_len(npw), b64, ld, b64, ld, ref2, nullptr, s, true);
         project_c<double>(c, b64, ld, nrow, S);
         PDEP_HIP(hipStreamSynchronize(s));
         solve_rows(c, nrow, b64, x64, ld, st, ref2);
         S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow)));
         project_c<double>(c, x64, ld, nrow, S);
+        launch_sym_expand(nrow, npw, x64, ld, s);   // full rows for the density
         // density response
         sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));
         launch_sphere_to_sticks<double>(b.dims, b.tables, x64, ld, nrow, nullptr, sticks, s);
