@@ -8,7 +8,7 @@ replaced by preconditioned conjugate gradient, which is what the paper proposes 
 Sternheimer equation (Sec. 2.3, after Eq. stern).  It is used to time a CPU baseline
 and for sampled checks on cells where the dense matrices do not fit.
 
-Preconditioner: K_G = 1/max(1, 1/2|G|^2 - e_v) followed by P_c (the paper names a
+Preconditioner: K_G = 1/max(1/2|G|^2 - e_v, 0.1) followed by P_c (the paper names a
 preconditioned CG without fixing K; K changes iteration counts only).
 Stopping rule per band: ||P_c(b - A x)|| <= tol ||b||, x0 = 0; b = 0 gives x = 0.
 """
@@ -39,7 +39,7 @@ def cg_bands(model: Model, eps: np.ndarray, C: np.ndarray, B: np.ndarray, tol: f
     bnorm = np.linalg.norm(B, axis=1)
     active = bnorm > 0
     if precondition:
-        K = 1.0 / np.maximum(1.0, model.kin[None, :] - eps[:, None])
+        K = 1.0 / np.maximum(0.1, model.kin[None, :] - eps[:, None])
         Z = project_c(C, K * R)
     else:
         K = None

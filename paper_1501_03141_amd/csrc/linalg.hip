@@ -256,10 +256,13 @@ __global__ __launch_bounds__(256) void k_row_dots(int K, const cplx<T>* __restri
 }
 
 // ------------------------------------------------------------------- CG pieces ---
+// K_G = 1 / max(1/2|G|^2 - shift, kPrecondFloor): the kinetic diagonal of H - e_v,
+// floored (in Hartree) where it is small or negative.
+constexpr double kPrecondFloor = 0.1;
 template <typename T>
 __device__ __forceinline__ T precond_factor(const T* kin, int k, double shift) {
     const double d = (double)kin[k] - shift;
-    return (T)(1.0 / (d > 1.0 ? d : 1.0));
+    return (T)(1.0 / (d > kPrecondFloor ? d : kPrecondFloor));
 }
 
 template <typename T>
