@@ -92,11 +92,13 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 // the waves of one n range), the A fragments are loaded by each wave directly.
 // Requires lda, ldb, K-chunk starts multiple of 4 complex (16-byte aligned loads).
 // REAL: only the real parts, written as floats (Sv: float [N][lds]); otherwise complex
-// (Sv: float2 [N][lds], imaginary parts stored as zero when real_out is set).
+// (Sv: float2 [N][lds], imaginary parts stored as zero when real_out is set).  With kin
+// non-null, B[n][k] is taken times the CG preconditioner 1 / max(kin[k] - shift[n], floor).
 template <int WM, int CT, bool REAL>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
                                                      const float2* __restrict__ B, long ldb, void* __restrict__ Sv,
-                                                     long lds, int kchunk, int real_out) {
+                                                     long lds, int kchunk, int real_out, const float* __restrict__ kin,
+                                                     const double* __restrict__ shift, float kfloor) {
     constexpr int NSUB = REAL ? 1 : 2;   // row tiles of A: real part, imaginary part
     constexpr int WN = 4 / WM;
     constexpr int BMC = 32 * WM, BN = 16 * CT * WN;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[g][s][c] = x3_f4{0.f, 0.f, 0.f, 0.f};
 
-    float ra[2][8], rb[IT][8];
+    float ra[2][8], rb[IT][8], kb[IT][4];
     auto fetch = [&](int kc) {
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
@@ -133,6 +135,10 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
             const int n = n0 + (e >> 2), k = kc + 4 * (e & 3);
             const int avail = n < N ? kend - k : 0;
             load4(B + (long)(n < N ? n : 0) * ldb + k, avail, rb[j]);
+            if (kin) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) kb[j][q] = q < avail ? kin[k + q] : 0.f;
+            }
         }
     };
 
@@ -142,6 +148,17 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             const int e = tid + 256 * j;
+            if (kin) {
+                const int n = n0 + (e >> 2);
+                const float sh = n < N ? (float)shift[n] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float d = kb[j][q] - sh;
+                    const float f = 1.f / (d > kfloor ? d : kfloor);
+                    rb[j][2 * q] *= f;
+                    rb[j][2 * q + 1] *= f;
+                }
+            }
             x3_u4 h, l;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -236,9 +253,24 @@ __device__ __forceinline__ void load8f(const float* p, int avail, float (&v)[8])
 // that output tiles 2t and 2t + 1 give a lane the real and imaginary part of the same
 // k (stored as one float2).  Each wave loads its own S fragments (8 consecutive m).
 // Requires lda and lds multiples of 4 (16-byte aligned loads).
+// FUSED (the CG direction update): Y = p and, for active rows n only,
+//   p <- K r - sum_m S[n][m] A[m][k] + beta_n p,  K = 1 / max(kin[k] - shift[n], floor),
+//   beta_n = rz_new[n] / rz[n] (0 when rz[n] = 0); alpha and beta are unused.
+struct DirUpdate {
+    const float2* r;
+    long ldr;
+    const float* kin;
+    const double* shift;
+    const double* rz_new;
+    const double* rz;
+    const int* active;
+    float kfloor;
+};
+template <bool FUSED>
 __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, const float2* __restrict__ A,
                                                          long lda, const float* __restrict__ S, long lds,
-                                                         float alpha, float beta, float2* __restrict__ Y, long ldy) {
+                                                         float alpha, float beta, float2* __restrict__ Y, long ldy,
+                                                         DirUpdate du) {
     constexpr int BK = 64, BNR = 128;
     __shared__ __align__(16) unsigned char As[2][2 * BK * kRowB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -303,25 +335,51 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
         }
         __syncthreads();
     }
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
-                const int k = k0 + 16 * t + lr;
-                if (n < N && k < K) {
-                    float2* y = Y + (long)n * ldy + k;
-                    float2 o = make_float2(alpha * acc[a][2 * t][i], alpha * acc[a][2 * t + 1][i]);
-                    if (beta != 0.f) {
-                        const float2 old = *y;
-                        o.x += beta * old.x;
-                        o.y += beta * old.y;
+                if (n >= N || !du.active[n]) continue;
+                const double den = du.rz[n];
+                const float bn = (float)(den != 0.0 ? du.rz_new[n] / den : 0.0);
+                const float sh = (float)du.shift[n];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = k0 + 16 * t + lr;
+                    if (k < K) {
+                        const float d = du.kin[k] - sh;
+                        const float f = 1.f / (d > du.kfloor ? d : du.kfloor);
+                        const float2 rv = du.r[(long)n * du.ldr + k];
+                        float2* y = Y + (long)n * ldy + k;
+                        const float2 pv = *y;
+                        *y = make_float2(f * rv.x - acc[a][2 * t][i] + bn * pv.x,
+                                         f * rv.y - acc[a][2 * t + 1][i] + bn * pv.y);
                     }
-                    *y = o;
                 }
             }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
+                    const int k = k0 + 16 * t + lr;
+                    if (n < N && k < K) {
+                        float2* y = Y + (long)n * ldy + k;
+                        float2 o = make_float2(alpha * acc[a][2 * t][i], alpha * acc[a][2 * t + 1][i]);
+                        if (beta != 0.f) {
+                            const float2 old = *y;
+                            o.x += beta * old.x;
+                            o.y += beta * old.y;
+                        }
+                        *y = o;
+                    }
+                }
+    }
 }
 
 // Y[n][k] = beta Y[n][k] + alpha sum_m S[n][m] A[m][k].
@@ -430,7 +488,8 @@ namespace {
 // REAL: S and work are float arrays (real parts only).
 template <bool REAL>
 void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, void* S, long lds,
-                 void* work, size_t work_elems, hipStream_t s, bool real_out) {
+                 void* work, size_t work_elems, hipStream_t s, bool real_out, const float* kin = nullptr,
+                 const double* shift = nullptr, float kfloor = 0.f) {
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
@@ -456,16 +515,16 @@ void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B
     const int ro = (real_out && splits == 1) ? 1 : 0;
     if (WM == 1)
         hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro);
+                           kchunk, ro, kin, shift, kfloor);
     else if (WM == 2)
         hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro);
+                           kchunk, ro, kin, shift, kfloor);
     else if (CT == 8)
         hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro);
+                           kchunk, ro, kin, shift, kfloor);
     else
         hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro);
+                           kchunk, ro, kin, shift, kfloor);
     PDEP_HIP(hipGetLastError());
     if (splits > 1) {
         if constexpr (REAL) {
@@ -488,9 +547,11 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
 }
 
 void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
-                             long lds, float* work, size_t work_elems, hipStream_t s) {
+                             long lds, float* work, size_t work_elems, hipStream_t s, const float* kin,
+                             const double* shift, double kfloor) {
     PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_real: lds must be a multiple of 4");
-    gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true);
+    PDEP_REQUIRE(!kin || (shift && kfloor > 0), PDEP_EINVAL, "gemm_ahb_x3_real: preconditioner needs shifts");
+    gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor);
 }
 
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
@@ -502,8 +563,24 @@ void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, 
     dim3 grid((K + 63) / 64, (N + 127) / 128);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
                     (double)N * K * sizeof(float2) * (beta != 0.0 ? 2.0 : 1.0), 4.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_update_x3r, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha, (float)beta, Y,
-                       ldy);
+    hipLaunchKernelGGL(k_gemm_update_x3r<false>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha,
+                       (float)beta, Y, ldy, DirUpdate{});
+    PDEP_HIP(hipGetLastError());
+}
+
+void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
+                            long ldr, const float* kin, const double* shift, double kfloor, const double* rz_new,
+                            const double* rz, const int* active, float2* p, long ldp, hipStream_t s) {
+    if (N <= 0 || K <= 0) return;
+    PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
+                 "cg_direction_x3: leading dimensions must be multiples of 4");
+    PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "cg_direction_x3: N too large");
+    dim3 grid((K + 63) / 64, (N + 127) / 128);
+    ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
+                    (double)N * K * sizeof(float2) * 3.0, 4.0 * (double)M * N * K);
+    const DirUpdate du{r, ldr, kin, shift, rz_new, rz, active, (float)kfloor};
+    hipLaunchKernelGGL(k_gemm_update_x3r<true>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p, ldp,
+                       du);
     PDEP_HIP(hipGetLastError());
 }
 

@@ -258,7 +258,6 @@ __global__ __launch_bounds__(256) void k_row_dots(int K, const cplx<T>* __restri
 // ------------------------------------------------------------------- CG pieces ---
 // K_G = 1 / max(1/2|G|^2 - shift, kPrecondFloor): the kinetic diagonal of H - e_v,
 // floored (in Hartree) where it is small or negative.
-constexpr double kPrecondFloor = 0.1;
 template <typename T>
 __device__ __forceinline__ T precond_factor(const T* kin, int k, double shift) {
     const double d = (double)kin[k] - shift;
@@ -304,7 +303,7 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
         x[o] = xv;
         r[o] = rv;
         const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
-        z[o] = mk<T>(f * rv.x, f * rv.y);
+        if (z) z[o] = mk<T>(f * rv.x, f * rv.y);
         const double n2 = half_weight(half, k, K) * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
         srr = n2;
         srz = (double)f * n2;

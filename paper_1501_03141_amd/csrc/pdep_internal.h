@@ -210,10 +210,20 @@ void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const
                            double beta, float2* Y, long ldy, hipStream_t s);
 // Real-coefficient BF16x3 pair (S real, float [N][lds], lds multiple of 4):
 //   S[n][m] = Re sum_k conj(A[m][k]) B[n][k];   Y[n][k] = beta Y + alpha sum_m S[n][m] A[m][k]
+// kin non-null: B[n][k] is taken times the CG preconditioner 1 / max(kin[k] - shift[n], kfloor)
 void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
-                             long lds, float* work, size_t work_elems, hipStream_t s);
+                             long lds, float* work, size_t work_elems, hipStream_t s, const float* kin = nullptr,
+                             const double* shift = nullptr, double kfloor = 0.0);
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
                                 double alpha, double beta, float2* Y, long ldy, hipStream_t s);
+// CG direction update with the projected preconditioned residual formed in the GEMM:
+// for active rows n, p[n] <- K r[n] - sum_m S[n][m] A[m] + (rz_new[n] / rz[n]) p[n], where
+// S = Re(A^H K r) comes from launch_gemm_ahb_x3_real with the same kin / shift / kfloor.
+void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
+                            long ldr, const float* kin, const double* shift, double kfloor, const double* rz_new,
+                            const double* rz, const int* active, float2* p, long ldp, hipStream_t s);
+// floor of the CG preconditioner 1 / max(1/2|G|^2 - e_v, floor) (Hartree)
+constexpr double kPrecondFloor = 0.1;
 // S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)
 void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* P, float2* S, hipStream_t s,
                               bool real_out = false);

@@ -264,7 +264,7 @@ __global__ void k_gather_state(int K, long ld, const int* __restrict__ map, cons
     const long o = (long)map[j] * ld + k, n = (long)j * ld + k;
     x1[n] = x0[o];
     r1[n] = r0[o];
-    z1[n] = z0[o];
+    if (z0) z1[n] = z0[o];
     p1[n] = p0[o];
 }
 
@@ -344,6 +344,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     double* rz_part = pq_part + (size_t)n * npq;
     double* rr_part = rz_part + (size_t)n * nblk;
     const T* kin = kin_of<T>(c);
+    // BF16x3 with the preconditioner: fused direction update (no z pass)
+    const bool fused = pre && sizeof(T) == sizeof(float) && c.opts.precision == PDEP_MIXED_BF16X3;
     int cur = 0, ncur = n;
 
     hipLaunchKernelGGL(k_iota_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, sc.shift, sc.thr2, sc.s_shift[0],
@@ -392,7 +394,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             {
                 ProfScope prof_(K_MISC, s, 8.0 * nk * npw * sizeof(cplx<T>));
                 hipLaunchKernelGGL(k_gather_state<T>, dim3((npw + 255) / 256, nk), dim3(256), 0, s, npw, ld, dmap,
-                                   X[cur], R[cur], Z[cur], P[cur], X[nxt], R[nxt], Z[nxt], P[nxt]);
+                                   X[cur], R[cur], fused ? nullptr : Z[cur], P[cur], X[nxt], R[nxt], Z[nxt],
+                                   P[nxt]);
                 hipLaunchKernelGGL(k_gather_slots, dim3((nk + 255) / 256), dim3(256), 0, s, nk, dmap, sc.s_rz[cur],
                                    sc.s_shift[cur], sc.s_thr2[cur], sc.s_iters[cur], sc.s_id[cur], sc.s_rz[nxt],
                                    sc.s_shift[nxt], sc.s_thr2[nxt], sc.s_iters[nxt], sc.s_id[nxt], sc.active);
@@ -416,7 +419,24 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             // of H (partial sums per stick group), <r, z> = <r, K r> (r in range(P_c)) and
             // ||r||^2 from the step that updates r.  Without the preconditioner z = r, q
             // is projected every time and the products are separate passes.
-            if (pre) {
+            if (pre && fused) {
+                // z = P_c K r is never stored: the coefficient GEMM applies K to r on the
+                // fly and the update GEMM writes p = K r - Psi S + beta p directly
+                apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
+                st.op_applications++;
+                launch_cg_step1<T>(ncur, npw, x, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre,
+                                   s, rz_part, rr_part, sc.rz_new, sc.rr, half);
+                if constexpr (sizeof(T) == sizeof(float)) {
+                    float* Sr = reinterpret_cast<float*>(S);
+                    float* wr = static_cast<float*>(c.ws(W_SPLIT, ((size_t)8 << 20) * sizeof(float2)));
+                    const long lp = sphere_ld(c.basis.npw), lds = coef_ld(nv);
+                    launch_gemm_ahb_x3_real(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
+                                            (size_t)16 << 20, s, kin, sh, kPrecondFloor);
+                    launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
+                                           sc.rz_new, rz, sc.active, p, ld, s);
+                }
+                if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
+            } else if (pre) {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
                 st.op_applications++;
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s,
@@ -430,7 +450,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, sc.pq, 1, sc.active, kin, sh, ncur, pre, s);
                 launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s, half);
             }
-            launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
+            if (!(pre && fused)) launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
             launch_cg_check(ncur, sc.rr, sc.s_thr2[cur], sc.active, sc.s_iters[cur], rz, sc.rz_new, sc.n_active, 1,
                             s);
