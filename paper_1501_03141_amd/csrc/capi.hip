@@ -54,16 +54,19 @@ enum CapiSlot { C_IN = pdep::WS_CAPI_IN, C_OUT = pdep::WS_CAPI_OUT, C_STAGE = pd
 
 void check_ctx(pdep_ctx* ctx) { PDEP_REQUIRE(ctx != nullptr, PDEP_EINVAL, "null context"); }
 
-// Build the resident u_v(r) = Inv(c_v) grids and the FP32 copies of Psi and V.
+// Build the resident packed orbital grids u_2j(r) + i u_2j+1(r) (the orbitals are real
+// in r, so one complex grid holds two of them; the last one alone for odd N_v) and the
+// FP32 copies of Psi and V.
 void finish_setup(Ctx& c) {
     const pdep::Basis& b = c.basis;
     const int nv = c.nv, npw = b.npw;
     hipStream_t s = c.stream;
-    c.u64.ensure(&c.al, (size_t)nv * b.ng * sizeof(double2));
+    const int nvp = pdep::pair_count(nv, nv);
+    c.upair.ensure(&c.al, (size_t)nvp * b.ng * sizeof(double2));
     double2* sticks = static_cast<double2*>(c.ws(pdep::WS_SETUP_STICKS, (size_t)nv * b.dims.nz * b.dims.sld *
                                                                            sizeof(double2)));
-    pdep::launch_sphere_to_sticks<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nv, nullptr, sticks, s);
-    pdep::launch_slab_inv_store<double>(b.dims, b.tables, sticks, nv, c.u64.as<double2>(), nullptr, s);
+    pdep::launch_sphere_to_sticks_pair<double>(b.dims, b.tables, c.psi64.as<double2>(), npw, nv, sticks, s, nv);
+    pdep::launch_slab_inv_store<double>(b.dims, b.tables, sticks, nvp, c.upair.as<double2>(), nullptr, s);
     // FP32 copy with the padded sphere row stride (zero padding): 16-byte aligned rows
     const long ld32 = pdep::sphere_ld(npw);
     c.psi32.ensure(&c.al, (size_t)nv * ld32 * sizeof(float2));

@@ -554,13 +554,28 @@ __global__ __launch_bounds__(kRegStickGroup) void k_sticks_to_sphere_reg(
 // potential acts on each part separately, and after the forward transform W of the
 // product a_G = (W_G + conj W_-G) / 2, b_G = (W_G - conj W_-G) / 2i.
 
-// Half-sphere rows 2j, 2j + 1 -> sticks of packed row j (inverse z transforms).  The
+// Rows come in groups of `group` consecutive rows (all rows: one group); packed row j is
+// pair j' of group g (j = g * ceil(group / 2) + j'), i.e. rows g * group + 2 j' and the
+// next one, which is absent (zero) when it falls outside the group or past nrows.
+struct PairRows {
+    int a;
+    bool has_b;
+};
+__device__ __forceinline__ PairRows pair_rows(int pr, int group, int nrows) {
+    const int hp = (group + 1) / 2;
+    const int g = pr / hp, j = pr - g * hp;
+    const int a = g * group + 2 * j;
+    return PairRows{a, 2 * j + 1 < group && a + 1 < nrows};
+}
+
+// Half-sphere rows a, b of packed row j -> its sticks (inverse z transforms).  The
 // entries k > c come from the mirrors npw - 1 - k (conjugated); the centre is taken
-// real.  Row 2j + 1 is zero when it does not exist (odd nrows).
+// real.
 template <typename T, int NZ_>
 __global__ __launch_bounds__(kThreads) void k_sphere_to_sticks_pair(FftDims d, BasisTables t,
                                                                     const cplx<T>* __restrict__ in, long ld_in,
-                                                                    int nrows, cplx<T>* __restrict__ sticks) {
+                                                                    int nrows, int group,
+                                                                    cplx<T>* __restrict__ sticks) {
     extern __shared__ __align__(16) unsigned char smem[];
     using C = cplx<T>;
     const int NZ = NZ_ ? NZ_ : d.nz;
@@ -570,13 +585,14 @@ __global__ __launch_bounds__(kThreads) void k_sphere_to_sticks_pair(FftDims d, B
     const int s0 = blockIdx.x * SG;
     const int ns_here = min(SG, d.ns - s0);
     const int pr = blockIdx.y;
-    const bool has_b = 2 * pr + 1 < nrows;
+    const PairRows rw = pair_rows(pr, group, nrows);
+    const bool has_b = rw.has_b;
     for (int e = threadIdx.x; e < SG * NZ; e += kThreads) buf[e] = mk<T>(0, 0);
     load_tw<T>(twz, t, 2, NZ);
     __syncthreads();
     const int k0 = t.stick_start[s0], k1 = t.stick_start[s0 + ns_here];
     const int npw = d.npw, c = (npw - 1) / 2;
-    const C* a = in + (long)(2 * pr) * ld_in;
+    const C* a = in + (long)rw.a * ld_in;
     const C* b = a + ld_in;
     const int off = s0 * NZ;
     for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
@@ -601,16 +617,17 @@ __global__ __launch_bounds__(kThreads) void k_sphere_to_sticks_pair(FftDims d, B
     }
 }
 
-// Sticks of packed row j -> half-sphere rows 2j, 2j + 1 with the shifted-H epilogue
-// out = F + (kin - shift[row % nshift]) x and, when dot_part is non-null, the partial
-// sums of Re<x, out> over the full sphere (weight 2 off the centre) per workgroup.  A
-// workgroup transforms SG / 2 sticks of the front half (s <= (ns - 1) / 2, which hold
-// every entry k <= c) and their mirrors ns - 1 - s.
+// Sticks of packed row j -> half-sphere rows a, b (pair_rows) with the epilogue
+// EPI_SHIFTED_H, out = F + (kin - shift[row % nshift]) x and, when dot_part is non-null,
+// the partial sums of Re<x, out> over the full sphere (weight 2 off the centre) per
+// workgroup; or EPI_SCALE, out = alpha F.  A workgroup transforms SG / 2 sticks of the
+// front half (s <= (ns - 1) / 2, which hold every entry k <= c) and their mirrors
+// ns - 1 - s.
 template <typename T, int NZ_>
 __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere_pair(
-    FftDims d, BasisTables t, const cplx<T>* __restrict__ sticks, int nrows, cplx<T>* __restrict__ out, long ld_out,
-    const cplx<T>* __restrict__ x, long ld_x, const T* __restrict__ kin, const double* __restrict__ shift,
-    int nshift, double* __restrict__ dot_part) {
+    FftDims d, BasisTables t, const cplx<T>* __restrict__ sticks, int nrows, int group, cplx<T>* __restrict__ out,
+    long ld_out, int epi, double alpha, const cplx<T>* __restrict__ x, long ld_x, const T* __restrict__ kin,
+    const double* __restrict__ shift, int nshift, double* __restrict__ dot_part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[2][kThreads];
     using C = cplx<T>;
@@ -637,12 +654,26 @@ __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere_pair(
     const int c = (d.npw - 1) / 2;
     const int k0 = t.stick_start[s0], k1 = min(t.stick_start[s0 + nf], c + 1);
     const T inv_ng = T(1.0 / ((double)d.nx * d.ny * d.nz));
-    const T half = T(0.5) * inv_ng;
-    const int ra = 2 * pr, rb = ra + 1;
-    const bool has_b = rb < nrows;
-    const T sha = (T)shift[ra % nshift], shb = has_b ? (T)shift[rb % nshift] : T(0);
+    const PairRows rw = pair_rows(pr, group, nrows);
+    const int ra = rw.a, rb = ra + 1;
+    const bool has_b = rw.has_b;
     C* oa = out + (long)ra * ld_out;
     C* ob = oa + ld_out;
+    if (epi == EPI_SCALE) {
+        const T half = T(0.5 * alpha) * inv_ng;
+        for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
+            const int pos = t.stick_pos[k];
+            const int st = pos / NZ, iz = pos - st * NZ;
+            const int j = st - s0;
+            const C W = buf[j * NZ + iz];
+            const C Wm = buf[(SGH + j) * NZ + (iz == 0 ? 0 : NZ - iz)];
+            oa[k] = mk<T>(half * (W.x + Wm.x), half * (W.y - Wm.y));
+            if (has_b) ob[k] = mk<T>(half * (W.y + Wm.y), half * (Wm.x - W.x));
+        }
+        return;
+    }
+    const T half = T(0.5) * inv_ng;
+    const T sha = (T)shift[ra % nshift], shb = has_b ? (T)shift[rb % nshift] : T(0);
     const C* xa = x + (long)ra * ld_x;
     const C* xb = xa + ld_x;
     double acca = 0.0, accb = 0.0;
@@ -1083,30 +1114,38 @@ int sticks_to_sphere_pair_groups(const FftDims& d) {
     return ((d.ns + 1) / 2 + sgh - 1) / sgh;
 }
 
+int pair_count(int nrows, int group) {
+    const int g = group > 0 ? group : nrows;
+    return (nrows / g) * ((g + 1) / 2) + ((nrows % g) + 1) / 2;
+}
+
 template <typename T>
 void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
-                                  cplx<T>* sticks, hipStream_t s) {
+                                  cplx<T>* sticks, hipStream_t s, int group) {
     if (nrows <= 0) return;
     check_sticks(d);
-    const int npair = (nrows + 1) / 2;
+    const int npair = pair_count(nrows, group);
     check_rows(npair);
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_SPHERE_TO_STICKS64 : K_SPHERE_TO_STICKS, s,
                     (double)nrows * hp + (double)npair * sk);
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sphere_to_sticks_pair<T, NZ>), stick_grid(d, npair), dim3(kThreads), stick_lds<T>(d), s,
-                           d, t, in, ld_in, nrows, sticks);
+                           d, t, in, ld_in, nrows, group > 0 ? group : nrows, sticks);
     });
     PDEP_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows,
-                                  cplx<T>* out, long ld_out, const cplx<T>* x, long ld_x, const T* kin,
-                                  const double* shift, int nshift, hipStream_t s, double* dot_part) {
+                                  cplx<T>* out, long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x,
+                                  const T* kin, const double* shift, int nshift, hipStream_t s, double* dot_part,
+                                  int group) {
     if (nrows <= 0) return;
+    PDEP_REQUIRE(epi == EPI_SHIFTED_H || (epi == EPI_SCALE && !dot_part), PDEP_EINVAL,
+                 "sticks_to_sphere_pair: EPI_SHIFTED_H, or EPI_SCALE without dot products");
     check_sticks(d);
-    const int npair = (nrows + 1) / 2;
+    const int npair = pair_count(nrows, group);
     check_rows(npair);
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_STICKS_TO_SPHERE64 : K_STICKS_TO_SPHERE, s,
@@ -1114,7 +1153,8 @@ void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const 
     const dim3 grid(sticks_to_sphere_pair_groups(d), npair);
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sticks_to_sphere_pair<T, NZ>), grid, dim3(kThreads), stick_lds<T>(d), s, d, t, sticks,
-                           nrows, out, ld_out, x, ld_x, kin, shift, nshift > 0 ? nshift : 1, dot_part);
+                           nrows, group > 0 ? group : nrows, out, ld_out, epi, alpha, x, ld_x, kin, shift,
+                           nshift > 0 ? nshift : 1, dot_part);
     });
     PDEP_HIP(hipGetLastError());
 }
@@ -1244,10 +1284,10 @@ template <typename T> int sticks_to_sphere_groups(const FftDims& d) {
                                              int, const double*, hipStream_t, double*);                           \
     template int sticks_to_sphere_groups<T>(const FftDims&);                                                      \
     template void launch_sphere_to_sticks_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, long, int,  \
-                                                  cplx<T>*, hipStream_t);                                         \
+                                                  cplx<T>*, hipStream_t, int);                                    \
     template void launch_sticks_to_sphere_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, int,        \
-                                                  cplx<T>*, long, const cplx<T>*, long, const T*, const double*,  \
-                                                  int, hipStream_t, double*);                                     \
+                                                  cplx<T>*, long, int, double, const cplx<T>*, long, const T*,    \
+                                                  const double*, int, hipStream_t, double*, int);                 \
     template void launch_slab_hv<T>(const FftDims&, const BasisTables&, cplx<T>*, int, const T*, hipStream_t);    \
     template void launch_slab_inv_store<T>(const FftDims&, const BasisTables&, cplx<T>*, int, cplx<T>*, T*,       \
                                            hipStream_t);                                                          \

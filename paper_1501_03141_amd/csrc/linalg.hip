@@ -460,19 +460,6 @@ __global__ void k_half_weights(int K, const cplx<T>* __restrict__ in, long ldi, 
     out[(long)row * ldo + k] = mk<T>(w * v.x, w * v.y);
 }
 
-// Half-sphere rows -> full rows in place: x[npw - 1 - k] = conj x[k] for k < c, and the
-// centre c = (npw - 1) / 2 made real.
-__global__ void k_sym_expand(int npw, double2* __restrict__ x, long ld) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int row = blockIdx.y;
-    const int c = (npw - 1) / 2;
-    if (k > c) return;
-    double2* r = x + (long)row * ld;
-    const double2 v = r[k];
-    if (k == c) r[k].y = 0.0;
-    else r[npw - 1 - k] = make_double2(v.x, -v.y);
-}
-
 // Make rows exactly Hermitian-symmetric: c_k and c_{npw-1-k} (the coefficients of G and
 // -G in the sphere order) <- the symmetric part; the centre (G = 0) becomes real.  One
 // thread per pair k <= npw - 1 - k.
@@ -629,13 +616,6 @@ void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>*
 }
 template void launch_half_weights<float>(int, int, const float2*, long, float2*, long, hipStream_t);
 template void launch_half_weights<double>(int, int, const double2*, long, double2*, long, hipStream_t);
-
-void launch_sym_expand(int nrows, int npw, double2* x, long ld, hipStream_t s) {
-    if (nrows <= 0) return;
-    ProfScope prof_(K_MISC, s, 32.0 * nrows * (double)half_len(npw));
-    hipLaunchKernelGGL(k_sym_expand, rows_grid(half_len(npw), nrows), dim3(256), 0, s, npw, x, ld);
-    PDEP_HIP(hipGetLastError());
-}
 
 void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b, long ldb,
                      double2* out, long ldo, hipStream_t s) {

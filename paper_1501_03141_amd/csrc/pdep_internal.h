@@ -159,17 +159,21 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
 // number of partial dot products per row that launch_sticks_to_sphere<T> writes
 template <typename T> int sticks_to_sphere_groups(const FftDims& d);
 // Paired half-sphere rows (rows real in r, entries k <= c = (npw - 1) / 2 of the sphere
-// order, the rest implied by c_{npw-1-k} = conj c_k): rows 2j and 2j + 1 share packed
-// sticks row j (the transform of a + i b); nrows may be odd.
+// order, the rest implied by c_{npw-1-k} = conj c_k): two rows share one packed sticks
+// row (the transform of a + i b).  The rows form groups of `group` consecutive rows (0:
+// one group) and pairs stay inside a group: packed row g * ceil(group / 2) + j holds
+// rows g * group + 2j and g * group + 2j + 1 (absent past the group or nrows).
+int pair_count(int nrows, int group);
 template <typename T>
 void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const cplx<T>* in, long ld_in, int nrows,
-                                  cplx<T>* sticks, hipStream_t s);
-// packed sticks -> half-sphere rows with the EPI_SHIFTED_H epilogue; dot_part (may be
-// null): Re<x, out> of the full vectors, sticks_to_sphere_pair_groups partials per row
+                                  cplx<T>* sticks, hipStream_t s, int group = 0);
+// packed sticks -> half-sphere rows with EPI_SHIFTED_H (dot_part may be null: Re<x, out>
+// of the full vectors, sticks_to_sphere_pair_groups partials per row) or EPI_SCALE
 template <typename T>
 void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const cplx<T>* sticks, int nrows,
-                                  cplx<T>* out, long ld_out, const cplx<T>* x, long ld_x, const T* kin,
-                                  const double* shift, int nshift, hipStream_t s, double* dot_part);
+                                  cplx<T>* out, long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x,
+                                  const T* kin, const double* shift, int nshift, hipStream_t s, double* dot_part,
+                                  int group = 0);
 int sticks_to_sphere_pair_groups(const FftDims& d);
 // sticks -> inverse (y, x) -> * V(z, x, y) (z-major real grid) -> forward -> sticks, in place.
 template <typename T>
@@ -265,8 +269,6 @@ void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* r
 // out[r][k] = 2 in[r][k] for k < K - 1, in[r][K - 1] at k = K - 1 (half-sphere weights)
 template <typename T>
 void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>* out, long ldo, hipStream_t s);
-// half-sphere rows -> full rows in place (mirror entries npw - 1 - k = conjugates, centre real)
-void launch_sym_expand(int nrows, int npw, double2* x, long ld, hipStream_t s);
 // out[r] = a[rows[r]] - b[r]
 void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b,
                      long ldb, double2* out, long ldo, hipStream_t s);
@@ -333,7 +335,7 @@ struct Ctx {
     Buf vloc64, vloc32;                   // [ng] z-major
     Buf psi64, psi32;                     // [nv][npw] complex FP64; [nv][sphere_ld(npw)] FP32
     Buf psi32w, psi64w;                   // psi32 / psi64 with the half-sphere weights (2 off the centre)
-    Buf u64;                              // [nv][ng] complex grids, z-major
+    Buf upair;                            // [ceil(nv/2)][ng] complex grids u_2j + i u_2j+1, z-major
     Buf eps_dev;                          // [nv] double
     Buf kin32;                            // float kinetic
     // solver work space (grown on demand)

@@ -185,7 +185,7 @@ size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, c
     const size_t nv = (size_t)std::max(1, o.n_v), npw = b.npw, ng = b.ng;
     const size_t ld = (npw + 63) / 64 * 64;
     const size_t sticks_row = (size_t)b.dims.nz * b.dims.sld * 16;
-    const size_t fixed = ng * 12 + nv * npw * 24 + nv * ng * 16 + npw * 64 + ((size_t)64 << 20);
+    const size_t fixed = ng * 12 + nv * npw * 48 + (nv + 1) / 2 * ng * 16 + npw * 64 + ((size_t)64 << 20);
     // ground state (Davidson on N_v + 1 states)
     const size_t want = nv + 1, nbg = want + std::max<size_t>(4, want / 8);
     const size_t mg = std::min(npw, std::max(3 * nbg, nbg + 32));

@@ -165,8 +165,8 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
             if (paired) {
                 launch_sphere_to_sticks_pair<T>(b.dims, b.tables, pc, ld, nr, sk, c.stream);
                 launch_slab_hv<T>(b.dims, b.tables, sk, (nr + 1) / 2, vloc_of<T>(c), c.stream);
-                launch_sticks_to_sphere_pair<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, pc, ld, kin_of<T>(c),
-                                                shc, nsh, c.stream, pqc);
+                launch_sticks_to_sphere_pair<T>(b.dims, b.tables, sk, nr, q + (long)r0 * ld, ld, EPI_SHIFTED_H, 0.0, pc,
+                                                ld, kin_of<T>(c), shc, nsh, c.stream, pqc);
             } else {
                 launch_sphere_to_sticks<T>(b.dims, b.tables, pc, ld, nr, nullptr, sk, c.stream);
                 launch_slab_hv<T>(b.dims, b.tables, sk, nr, vloc_of<T>(c), c.stream);
@@ -633,14 +633,15 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
         double2* b64 = static_cast<double2*>(c.ws(W_B64, (size_t)nrow * ld * sizeof(double2)));
         double2* x64 = static_cast<double2*>(c.ws(W_X64, (size_t)nrow * ld * sizeof(double2)));
         double2* S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow)));
-        // right-hand sides b = -P_c Fwd(dV_i u_v)
-        launch_slab_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.u64.as<double2>(), nv, nrow, sticks,
-                                        s);
-        launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, nrow, b64, ld, EPI_SCALE, -1.0, nullptr, 0, nullptr,
-                                        nullptr, 0, nullptr, s);
-        // dV and u_v are real in r, so b is Hermitian-symmetric up to rounding: make it exact
-        launch_sym_fix(nrow, npw, b64, ld, s);
-        // from here the rows are half spheres (the first half_len(npw) entries of each row)
+        // right-hand sides b = -P_c Fwd(dV_i u_v), two bands per transform: the packed
+        // orbital grids u_2j + i u_2j+1 times the real dV_i give the two products as the
+        // real and imaginary parts.  The rows are half spheres (the first half_len(npw)
+        // entries of each row) from here on.
+        const int nvp = pair_count(nv, nv);
+        launch_slab_fwd_product<double>(b.dims, b.tables, Vr + (long)p0 * ng, c.upair.as<double2>(), nvp, tp * nvp,
+                                        sticks, s);
+        launch_sticks_to_sphere_pair<double>(b.dims, b.tables, sticks, nrow, b64, ld, EPI_SCALE, -1.0, nullptr, 0,
+                                             nullptr, nullptr, 0, s, nullptr, nv);
         double* ref2 = static_cast<double*>(c.ws(W_REF2, (size_t)nrow * sizeof(double)));
         launch_row_dots<double>(nrow, half_len(npw), b64, ld, b64, ld, ref2, nullptr, s, true);
         project_c<double>(c, b64, ld, nrow, S);
@@ -648,13 +649,13 @@ void chi0_core(Ctx& c, int npert, const double* Vr, double* dn_out, double2* out
         solve_rows(c, nrow, b64, x64, ld, st, ref2);
         S = static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow)));
         project_c<double>(c, x64, ld, nrow, S);
-        launch_sym_expand(nrow, npw, x64, ld, s);   // full rows for the density
-        // density response
+        // density response, two bands per transform: Inv(dc_2j + i dc_2j+1) against the
+        // packed orbitals, Re(conj(u_2j + i u_2j+1) (f + i g)) = u_2j f + u_2j+1 g
         sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)nrow * sticks_row_bytes(c)));
-        launch_sphere_to_sticks<double>(b.dims, b.tables, x64, ld, nrow, nullptr, sticks, s);
+        launch_sphere_to_sticks_pair<double>(b.dims, b.tables, x64, ld, nrow, sticks, s, nv);
         double* dn = dn_out ? dn_out + (long)p0 * ng
                             : static_cast<double*>(c.ws(W_DN, (size_t)tp * ng * sizeof(double)));
-        launch_slab_density(b.dims, b.tables, sticks, tp, nv, c.u64.as<double2>(), 4.0 / b.omega, dn, s);
+        launch_slab_density(b.dims, b.tables, sticks, tp, nvp, c.upair.as<double2>(), 4.0 / b.omega, dn, s);
         if (out) {
             launch_slab_fwd_product<double>(b.dims, b.tables, dn, nullptr, 1, tp, sticks, s);
             launch_sticks_to_sphere<double>(b.dims, b.tables, sticks, tp, out + (long)p0 * ld_out, ld_out, EPI_GSCALE,
