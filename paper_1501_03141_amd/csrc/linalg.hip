@@ -50,12 +50,14 @@ constexpr int kPad = 4;
 // K staged 16 complex (32 real) at a time; 4 waves in a 2 x 2 arrangement, each 32 x 32.
 // Split-K: workgroup z covers k in [z * kchunk, (z + 1) * kchunk) and writes its
 // partial product to S + z * N * lds (reduced afterwards in a fixed order).
-template <typename T>
+// REAL: only Re S (imaginary parts stored as zero): the A tile holds only the (re, im)
+// rows, 64 complex rows per workgroup, half the matrix-core work.
+template <typename T, bool REAL>
 __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cplx<T>* __restrict__ A, long lda,
                                                   const cplx<T>* __restrict__ B, long ldb, cplx<T>* __restrict__ S,
                                                   long lds, int kchunk, int real_out) {
-    constexpr int BMC = 32, BN = 64, BKC = 16;
-    constexpr int BMR = 2 * BMC, BKR = 2 * BKC;
+    constexpr int BMC = REAL ? 64 : 32, BN = 64, BKC = 16;
+    constexpr int BMR = 64, BKR = 2 * BKC;
     __shared__ T As[BKR][BMR + kPad];
     __shared__ T Bs[BKR][BN + kPad];
     using Op = Mfma<T>;
@@ -72,16 +74,21 @@ __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cpl
     S += (long)blockIdx.z * N * lds;
     for (int kc = kbeg; kc < kend; kc += BKC) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < BMC * BKC / 256; ++j) {
             const int e = tid + 256 * j;
             const int r = e / BKC, g = e % BKC;
             cplx<T> v;
             v.x = 0; v.y = 0;
             if (m0 + r < M && kc + g < kend) v = A[(long)(m0 + r) * lda + kc + g];
-            As[2 * g][2 * r] = v.x;
-            As[2 * g + 1][2 * r] = v.y;
-            As[2 * g][2 * r + 1] = -v.y;
-            As[2 * g + 1][2 * r + 1] = v.x;
+            if constexpr (REAL) {
+                As[2 * g][r] = v.x;
+                As[2 * g + 1][r] = v.y;
+            } else {
+                As[2 * g][2 * r] = v.x;
+                As[2 * g + 1][2 * r] = v.y;
+                As[2 * g][2 * r + 1] = -v.y;
+                As[2 * g + 1][2 * r + 1] = v.x;
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -114,9 +121,17 @@ __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cpl
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int mr = wm + 16 * a + Op::row(lane, i);       // real row in the tile
-                const int m = m0 + (mr >> 1), part = mr & 1;
                 const int n = n0 + wn + 16 * b + (lane & 15);
-                if (m < M && n < N) So[((long)n * lds + m) * 2 + part] = (real_out && part) ? T(0) : acc[a][b][i];
+                if constexpr (REAL) {
+                    const int m = m0 + mr;
+                    if (m < M && n < N) {
+                        So[((long)n * lds + m) * 2] = acc[a][b][i];
+                        So[((long)n * lds + m) * 2 + 1] = T(0);
+                    }
+                } else {
+                    const int m = m0 + (mr >> 1), part = mr & 1;
+                    if (m < M && n < N) So[((long)n * lds + m) * 2 + part] = (real_out && part) ? T(0) : acc[a][b][i];
+                }
             }
 }
 
@@ -144,12 +159,14 @@ __global__ void k_splitk_reduce(int M, int N, long lds, int splits, const cplx<T
 // (columns) and m' = 2m + s (contraction).  Workgroup tile: 64 rows n x 64 complex
 // columns (128 real), contraction staged 16 complex (32 real) at a time; 4 waves in a
 // 2 x 2 arrangement, each 32 rows x 64 real columns.
-template <typename T>
+// REAL: the imaginary parts of S are taken as zero; the contraction then runs over m
+// directly (32 m per step, half the matrix-core work).
+template <typename T, bool REAL>
 __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const cplx<T>* __restrict__ A, long lda,
                                                      const cplx<T>* __restrict__ S, long lds, double alpha,
                                                      double beta, cplx<T>* __restrict__ Y, long ldy) {
-    constexpr int BN = 64, BKC = 64, BMC = 16;
-    constexpr int BKR = 2 * BKC, BMR = 2 * BMC;
+    constexpr int BN = 64, BKC = 64, BMC = REAL ? 32 : 16;
+    constexpr int BKR = 2 * BKC, BMR = 32;
     __shared__ T Ss[BMR][BN + kPad];    // [m'][n]
     __shared__ T Bs[BMR][BKR + kPad];   // [m'][k']
     using Op = Mfma<T>;
@@ -163,26 +180,35 @@ __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const 
         for (int b = 0; b < 4; ++b) acc[a][b] = typename Op::acc{0, 0, 0, 0};
     for (int mc = 0; mc < M; mc += BMC) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {        // S: 64 rows x 16 complex
+        for (int j = 0; j < BN * BMC / 256; ++j) {        // S: 64 rows x BMC complex
             const int e = tid + 256 * j;
             const int r = e / BMC, mm = e % BMC;
             cplx<T> v;
             v.x = 0; v.y = 0;
             if (n0 + r < N && mc + mm < M) v = S[(long)(n0 + r) * lds + mc + mm];
-            Ss[2 * mm][r] = v.x;
-            Ss[2 * mm + 1][r] = v.y;
+            if constexpr (REAL) {
+                Ss[mm][r] = v.x;
+            } else {
+                Ss[2 * mm][r] = v.x;
+                Ss[2 * mm + 1][r] = v.y;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {        // A: 16 complex rows x 64 complex columns
+        for (int j = 0; j < BMC * BKC / 256; ++j) {       // A: BMC complex rows x 64 complex columns
             const int e = tid + 256 * j;
             const int mm = e / BKC, g = e % BKC;
             cplx<T> v;
             v.x = 0; v.y = 0;
             if (mc + mm < M && k0 + g < K) v = A[(long)(mc + mm) * lda + k0 + g];
-            Bs[2 * mm][2 * g] = v.x;
-            Bs[2 * mm][2 * g + 1] = v.y;
-            Bs[2 * mm + 1][2 * g] = -v.y;
-            Bs[2 * mm + 1][2 * g + 1] = v.x;
+            if constexpr (REAL) {
+                Bs[mm][2 * g] = v.x;
+                Bs[mm][2 * g + 1] = v.y;
+            } else {
+                Bs[2 * mm][2 * g] = v.x;
+                Bs[2 * mm][2 * g + 1] = v.y;
+                Bs[2 * mm + 1][2 * g] = -v.y;
+                Bs[2 * mm + 1][2 * g + 1] = v.x;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -487,7 +513,8 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
                      long lds, cplx<T>* work, size_t work_elems, hipStream_t s, bool real_out) {
     if (M <= 0 || N <= 0) return;
     PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_ahb: N too large");
-    dim3 grid((M + 31) / 32, (N + 63) / 64);
+    const int bmc = real_out ? 64 : 32;
+    dim3 grid((M + bmc - 1) / bmc, (N + 63) / 64);
     // split K when the output tiles alone cannot fill the chip (about 1k workgroups)
     int splits = 1;
     const long tiles = (long)grid.x * grid.y;
@@ -498,11 +525,16 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
     const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
     if (splits > 1) splits = (K + kchunk - 1) / kchunk;
     grid.z = splits;
+    // algorithmic flops: complex products (8 real flops) or, for real_out, their real parts (4)
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_GEMM_AHB64 : K_GEMM_AHB, s,
                     ((double)M + N) * K * sizeof(cplx<T>) + (double)M * N * sizeof(cplx<T>),
-                    8.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_ahb<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, splits > 1 ? work : S, lds,
-                       kchunk, real_out ? 1 : 0);
+                    (real_out ? 4.0 : 8.0) * (double)M * N * K);
+    if (real_out)
+        hipLaunchKernelGGL((k_gemm_ahb<T, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                           splits > 1 ? work : S, lds, kchunk, 1);
+    else
+        hipLaunchKernelGGL((k_gemm_ahb<T, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                           splits > 1 ? work : S, lds, kchunk, 0);
     PDEP_HIP(hipGetLastError());
     if (splits > 1) {
         const long tot = (long)N * M;
@@ -523,14 +555,19 @@ void launch_splitk_reduce_f32(int M, int N, long lds, int splits, const float2* 
 
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds, double alpha,
-                        double beta, cplx<T>* Y, long ldy, hipStream_t s) {
+                        double beta, cplx<T>* Y, long ldy, hipStream_t s, bool real_s) {
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_update: N too large");
     dim3 grid((K + 63) / 64, (N + 63) / 64);
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_GEMM_UPDATE64 : K_GEMM_UPDATE, s,
                     (double)M * K * sizeof(cplx<T>) + (double)N * M * sizeof(cplx<T>) +
-                    (double)N * K * sizeof(cplx<T>) * (beta != 0.0 ? 2.0 : 1.0), 8.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_update<T>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y, ldy);
+                    (double)N * K * sizeof(cplx<T>) * (beta != 0.0 ? 2.0 : 1.0), (real_s ? 4.0 : 8.0) * (double)M * N * K);
+    if (real_s)
+        hipLaunchKernelGGL((k_gemm_update<T, true>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y,
+                           ldy);
+    else
+        hipLaunchKernelGGL((k_gemm_update<T, false>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y,
+                           ldy);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -678,7 +715,7 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
     template void launch_gemm_ahb<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, cplx<T>*,      \
                                      long, cplx<T>*, size_t, hipStream_t, bool);                              \
     template void launch_gemm_update<T>(int, int, int, const cplx<T>*, long, const cplx<T>*, long, double,     \
-                                        double, cplx<T>*, long, hipStream_t);                                 \
+                                        double, cplx<T>*, long, hipStream_t, bool);                           \
     template void launch_row_dots<T>(int, int, const cplx<T>*, long, const cplx<T>*, long, double*, double*,   \
                                      hipStream_t, bool);                                                      \
     template void launch_cg_init<T>(int, int, const cplx<T>*, long, cplx<T>*, cplx<T>*, cplx<T>*, const T*,    \

@@ -202,10 +202,11 @@ void launch_transpose_grid(int nx, int ny, int nz, int nrows, const double* in, 
 template <typename T>
 void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, cplx<T>* S,
                      long lds, cplx<T>* work, size_t work_elems, hipStream_t s, bool real_out = false);
-// Y[n][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S: N x M; Y must not alias A or S)
+// Y[n][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S: N x M; Y must not alias A or S);
+// real_s: the imaginary parts of S are zero (and not read)
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds,
-                        double alpha, double beta, cplx<T>* Y, long ldy, hipStream_t s);
+                        double alpha, double beta, cplx<T>* Y, long ldy, hipStream_t s, bool real_s = false);
 // BF16x3 variants of the two GEMMs above for FP32 operands (16 significant bits per
 // product; for the inner solve of the refinement only).  lda/ldb/lds multiples of 4.
 void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float2* S,

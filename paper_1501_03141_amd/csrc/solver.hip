@@ -86,7 +86,7 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     if constexpr (sizeof(T) == sizeof(double)) {
         launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
                            true);
-        launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), npw, St, lds, -1.0, 1.0, Y, ld, c.stream);
+        launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), npw, St, lds, -1.0, 1.0, Y, ld, c.stream, true);
     } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
@@ -97,7 +97,7 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
             launch_gemm_update_x3_real(nv, nrows, nh, psi_of<T>(c), lp, Sr, lds, -1.0, 1.0, Y, ld, c.stream);
         } else {
             launch_gemm_ahb<T>(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
-            launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream);
+            launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), lp, St, lds, -1.0, 1.0, Y, ld, c.stream, true);
         }
     }
 }
