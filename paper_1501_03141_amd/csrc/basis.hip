@@ -168,6 +168,11 @@ void build_basis(const pdep_cell& cell, Basis& b) {
         const int s1 = std::min(d.ns, s0 + kRegStickGroup);
         d.sg_max = std::max(d.sg_max, b.stick_start[s1] - b.stick_start[s0]);
     }
+    d.sgp_max = 0;
+    for (int s0 = 0; s0 < (d.ns + 1) / 2; s0 += kPairStickGroup) {
+        const int s1 = std::min((d.ns + 1) / 2, s0 + kPairStickGroup);
+        d.sgp_max = std::max(d.sgp_max, b.stick_start[s1] - b.stick_start[s0]);
+    }
     // every stick covers a symmetric mz range (convex, inversion-symmetric sphere)
     for (int s = 0; s < d.ns; ++s) {
         const int k0 = b.stick_start[s], cnt = b.stick_start[s + 1] - k0;

@@ -718,6 +718,99 @@ __global__ __launch_bounds__(kThreads) void k_sticks_to_sphere_pair(
     }
 }
 
+// Register-resident form of the paired sticks-to-sphere pass (FP32, EPI_SHIFTED_H): 128
+// threads, one z stick each with the whole line in registers; threads 0..63 take
+// kPairStickGroup front sticks, threads 64..127 their mirrors.  The transforms land in
+// two LDS arrays indexed by the front entry k (the mirror one holding W at -G_k), from
+// which the epilogue separates the two rows as in k_sticks_to_sphere_pair.
+template <int NZ>
+__global__ __launch_bounds__(2 * kPairStickGroup) void k_sticks_to_sphere_pair_reg(
+    FftDims d, BasisTables t, const float2* __restrict__ sticks, int nrows, int group, float2* __restrict__ out,
+    long ld_out, const float2* __restrict__ x, long ld_x, const float* __restrict__ kin,
+    const double* __restrict__ shift, int nshift, double* __restrict__ dot_part) {
+    constexpr int HALF = (NZ + 1) / 2;
+    constexpr int GS = kPairStickGroup, NT = 2 * kPairStickGroup;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][NT];
+    float2* bufF = reinterpret_cast<float2*>(smem);
+    float2* bufM = bufF + d.sgp_max;
+    const int nfront = (d.ns + 1) / 2;
+    const int s0 = blockIdx.x * GS, pr = blockIdx.y;
+    const int nf = min(GS, nfront - s0);
+    const int kb = t.stick_start[s0], ke = t.stick_start[s0 + nf];
+    const int tid = threadIdx.x;
+    const bool mir = tid >= GS;                 // wave-uniform
+    const int j = mir ? tid - GS : tid;
+    if (j < nf) {
+        const int sf = s0 + j;
+        const int sk = mir ? d.ns - 1 - sf : sf;
+        const float2* src = sticks + (long)pr * NZ * d.sld + sk;
+        float2 v[NZ], X[NZ];
+        sfor<0, NZ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            v[i] = src[(long)i * d.sld];
+        });
+        dft_reg<float, -1, NZ, 1>(v, X);
+        const int ks = t.stick_start[sf] - kb, kz = (t.stick_start[sf + 1] - t.stick_start[sf] - 1) / 2;
+        float2* line = (mir ? bufM : bufF) + ks + kz;
+        const int sgn = mir ? -1 : 1;           // the mirror stick's mz lands at the front entry of -mz
+        sfor<0, NZ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int mz = i < HALF ? i : i - NZ;
+            if (mz >= -kz && mz <= kz) line[sgn * mz] = X[i];
+        });
+    }
+    __syncthreads();
+    const int c = (d.npw - 1) / 2;
+    const int k1 = min(ke, c + 1);
+    const float inv_ng = 1.0f / (float)((double)d.nx * d.ny * d.nz);
+    const float half = 0.5f * inv_ng;
+    const PairRows rw = pair_rows(pr, group, nrows);
+    const int ra = rw.a, rb = ra + 1;
+    const bool has_b = rw.has_b;
+    const float sha = (float)shift[ra % nshift], shb = has_b ? (float)shift[rb % nshift] : 0.f;
+    float2* oa = out + (long)ra * ld_out;
+    float2* ob = oa + ld_out;
+    const float2* xa = x + (long)ra * ld_x;
+    const float2* xb = xa + ld_x;
+    double acca = 0.0, accb = 0.0;
+    for (int k = kb + tid; k < k1; k += NT) {
+        const float2 W = bufF[k - kb], Wm = bufM[k - kb];
+        const double w = k == c ? 1.0 : 2.0;
+        const float kk = kin[k];
+        {
+            const float2 xv = xa[k];
+            const float dk = kk - sha;
+            const float2 ov = make_float2(half * (W.x + Wm.x) + dk * xv.x, half * (W.y - Wm.y) + dk * xv.y);
+            oa[k] = ov;
+            acca += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+        }
+        if (has_b) {
+            const float2 xv = xb[k];
+            const float dk = kk - shb;
+            const float2 ov = make_float2(half * (W.y + Wm.y) + dk * xv.x, half * (Wm.x - W.x) + dk * xv.y);
+            ob[k] = ov;
+            accb += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+        }
+    }
+    if (dot_part) {
+        red[0][tid] = acca;
+        red[1][tid] = accb;
+        __syncthreads();
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                red[0][tid] += red[0][tid + s];
+                red[1][tid] += red[1][tid + s];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            dot_part[(long)ra * gridDim.x + blockIdx.x] = red[0][0];
+            if (has_b) dot_part[(long)rb * gridDim.x + blockIdx.x] = red[1][0];
+        }
+    }
+}
+
 // ------------------------------------------------------------------- slab passes ---
 // A workgroup owns one z slab of one row: an nx x ny tile in LDS, element (ix, iy) at
 // ix * ny + iy.  The non-empty x columns are ix = mx mod nx for |mx| <= mxmax.
@@ -1109,7 +1202,15 @@ void launch_sticks_to_sphere(const FftDims& d, const BasisTables& t, const cplx<
     PDEP_HIP(hipGetLastError());
 }
 
-int sticks_to_sphere_pair_groups(const FftDims& d) {
+// The register paired pass applies to FP32 lines of a compiled length up to 48 whose two
+// staging arrays fit 64 KB of LDS.
+bool pair_reg_ok(const FftDims& d) {
+    const bool len = d.nz == 16 || d.nz == 24 || d.nz == 32 || d.nz == 48;
+    return len && d.sgp_max > 0 && 2 * (size_t)d.sgp_max * sizeof(float2) <= 65536;
+}
+
+template <typename T> int sticks_to_sphere_pair_groups(const FftDims& d) {
+    if (sizeof(T) == sizeof(float) && pair_reg_ok(d)) return ((d.ns + 1) / 2 + kPairStickGroup - 1) / kPairStickGroup;
     const int sgh = sticks_per_group(d.nz) / 2;
     return ((d.ns + 1) / 2 + sgh - 1) / sgh;
 }
@@ -1150,7 +1251,20 @@ void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const 
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_STICKS_TO_SPHERE64 : K_STICKS_TO_SPHERE, s,
                     (double)npair * sk + 2.0 * nrows * hp);
-    const dim3 grid(sticks_to_sphere_pair_groups(d), npair);
+    const dim3 grid(sticks_to_sphere_pair_groups<T>(d), npair);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (epi == EPI_SHIFTED_H && pair_reg_ok(d)) {
+            const size_t lds = 2 * (size_t)d.sgp_max * sizeof(float2);
+            with_n(d.nz, [&]<int NZ>() {
+                if constexpr (NZ > 0 && NZ <= 48)
+                    hipLaunchKernelGGL((k_sticks_to_sphere_pair_reg<NZ>), grid, dim3(2 * kPairStickGroup), lds, s, d,
+                                       t, sticks, nrows, group > 0 ? group : nrows, out, ld_out, x, ld_x, kin, shift,
+                                       nshift > 0 ? nshift : 1, dot_part);
+            });
+            PDEP_HIP(hipGetLastError());
+            return;
+        }
+    }
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sticks_to_sphere_pair<T, NZ>), grid, dim3(kThreads), stick_lds<T>(d), s, d, t, sticks,
                            nrows, group > 0 ? group : nrows, out, ld_out, epi, alpha, x, ld_x, kin, shift,
@@ -1283,6 +1397,7 @@ template <typename T> int sticks_to_sphere_groups(const FftDims& d) {
                                              long, int, double, const cplx<T>*, long, const T*, const double*,     \
                                              int, const double*, hipStream_t, double*);                           \
     template int sticks_to_sphere_groups<T>(const FftDims&);                                                      \
+    template int sticks_to_sphere_pair_groups<T>(const FftDims&);                                                 \
     template void launch_sphere_to_sticks_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, long, int,  \
                                                   cplx<T>*, hipStream_t, int);                                    \
     template void launch_sticks_to_sphere_pair<T>(const FftDims&, const BasisTables&, const cplx<T>*, int,        \

@@ -498,10 +498,12 @@ void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B
     const int BMC = 32 * WM, BN = 16 * CT * (4 / WM);
     PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
     dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
+    // split K until about 512 workgroups (two per CU; more splits only add partial-sum
+    // traffic: measured best at 512 for N_v = 128 and 512)
     int splits = 1;
     const long tiles = (long)grid.x * grid.y;
     if (work && tiles < 512) {
-        splits = (int)std::min<long>((1024 + tiles - 1) / tiles, std::max(1, K / 256));
+        splits = (int)std::min<long>((512 + tiles - 1) / tiles, std::max(1, K / 256));
         while (splits > 1 && (size_t)splits * N * lds > work_elems) --splits;
     }
     const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;

@@ -118,11 +118,14 @@ struct FftDims {
     int ns;                   // number of sticks
     int sld;                  // stick leading dimension of the sticks buffer (>= ns)
     int sg_max;               // most sphere entries in one group of kRegStickGroup sticks
+    int sgp_max;              // most sphere entries in one group of kPairStickGroup front sticks
     AxisPlan px, py, pz;
 };
 
 // Sticks per workgroup of the register stick passes.
 constexpr int kRegStickGroup = 128;
+// Front sticks per workgroup of the register paired sticks-to-sphere pass (each with its mirror).
+constexpr int kPairStickGroup = 64;
 
 // Device tables of the sphere / grid (one set per context).
 struct BasisTables {
@@ -174,7 +177,7 @@ void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const 
                                   cplx<T>* out, long ld_out, int epi, double alpha, const cplx<T>* x, long ld_x,
                                   const T* kin, const double* shift, int nshift, hipStream_t s, double* dot_part,
                                   int group = 0);
-int sticks_to_sphere_pair_groups(const FftDims& d);
+template <typename T> int sticks_to_sphere_pair_groups(const FftDims& d);
 // sticks -> inverse (y, x) -> * V(z, x, y) (z-major real grid) -> forward -> sticks, in place.
 template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s);

@@ -136,7 +136,7 @@ template <typename T> int fft_chunk_rule(const Ctx& c) {
 }
 
 // Partial dot products per row written by the epilogue of apply_op<T> on half-sphere rows.
-int op_dot_groups(const FftDims& d) { return sticks_to_sphere_pair_groups(d); }
+template <typename T> int op_dot_groups(const FftDims& d) { return sticks_to_sphere_pair_groups<T>(d); }
 
 // q = [P_c] (H - shift) p: stick pass, slab pass with V_loc, stick pass with the
 // kinetic/shift epilogue, then (optionally) the P_c GEMM pair.  pq_part (may be null,
@@ -152,7 +152,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
     PDEP_REQUIRE(half || !(project || pq_part), PDEP_EINVAL, "apply_op: projection and dots need half-sphere rows");
     cplx<T>* sk = static_cast<cplx<T>*>(sticks_buf);
     const bool paired = half;
-    const int npq = op_dot_groups(b.dims);
+    const int npq = op_dot_groups<T>(b.dims);
     auto chain = [&](int chunk) {
         if (paired) chunk += chunk & 1;   // pairs never straddle two blocks
         for (int r0 = 0; r0 < nrows; r0 += chunk) {
@@ -339,7 +339,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const int pre = c.opts.precond;
     // per-row partial sums: <p, q> (stick groups of the H epilogue), <r, K r> and ||r||^2
     // (blocks of the CG step)
-    const int npq = op_dot_groups(c.basis.dims), nblk = (npw + 255) / 256;
+    const int npq = op_dot_groups<T>(c.basis.dims), nblk = (npw + 255) / 256;
     double* pq_part = static_cast<double*>(c.ws(W_PQP, (size_t)n * (npq + 2 * nblk) * sizeof(double) + 64));
     double* rz_part = pq_part + (size_t)n * npq;
     double* rr_part = rz_part + (size_t)n * nblk;
