@@ -22,6 +22,7 @@
 // sizes are compile-time template parameters (all index arithmetic is then by
 // constants); other sizes use the same code with run-time sizes.  Twiddles come from
 // tables exp(-2 pi i m / n) built in extended precision on the host.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -925,14 +926,19 @@ __global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cpl
 //   5. stick rows copied back.
 // The stick rows and the transpose plane share LDS: every thread holds its line in
 // registers across the barrier that separates reading one from writing the other.
-template <int NL>
+// MX >= 0: the sphere's largest |mx| as a compile-time constant (must equal d.mxmax), so
+// that the x lines read their non-empty columns and write back the needed outputs at
+// fixed indices and the unused outputs of the forward x transform are never computed.
+// (A zero-padded (column, my) square for the y lines as well measured no faster.)
+template <int NL, int MX>
 __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, float2* __restrict__ sticks,
                                                      const float* __restrict__ Vr) {
     constexpr int ZG = 256 / NL;
     constexpr int HALF = (NL + 1) / 2;   // index i holds frequency i (i < HALF) or i - NL
     extern __shared__ __align__(16) unsigned char smem[];
     float2* lds = reinterpret_cast<float2*>(smem);
-    const int ax = d.ax, mxmax = d.mxmax, sld = d.sld, nz = d.nz;
+    const int mxmax = MX >= 0 ? MX : d.mxmax, sld = d.sld, nz = d.nz;
+    const int ax = 2 * mxmax + 1;
     const int axp = ax | 1;
     const int z0 = blockIdx.x * ZG, row = blockIdx.y;
     const int tid = threadIdx.x;
@@ -1291,6 +1297,11 @@ void launch_slab(const FftDims& d, const BasisTables& t, int nrows, cplx<T>* sti
 
 }  // namespace
 
+// Compiled sphere radius of the register slab kernel per line length: the largest |mx|
+// of a 12 Ha sphere on the grids of the workloads (n = 16, 24, 32, 48 with L = 20 n / 48
+// bohr; also 10 Ha at 32^3 and 15 bohr).  Other radii use the run-time form.
+constexpr int slab_mx_const(int n) { return n == 16 ? 5 : n == 24 ? 7 : n == 32 ? 10 : n == 48 ? 15 : -1; }
+
 // LDS of the register slab kernel for line length nl (0 if it does not apply).
 size_t slab_reg_lds(const FftDims& d, int nl) {
     if (d.nx != d.ny || d.nx != nl) return 0;
@@ -1319,8 +1330,12 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
                     check_rows(nrows);
                     constexpr int ZG = 256 / N;
                     ProfScope prof_(K_SLAB_HV, s, bytes, flops);
-                    hipLaunchKernelGGL((k_slab_hv_reg<N>), dim3((d.nz + ZG - 1) / ZG, nrows), dim3(256), lds, s, d,
-                                       t, sticks, Vz);
+                    const dim3 grid((d.nz + ZG - 1) / ZG, nrows);
+                    if (d.mxmax == slab_mx_const(N))
+                        hipLaunchKernelGGL((k_slab_hv_reg<N, slab_mx_const(N)>), grid, dim3(256), lds, s, d, t,
+                                           sticks, Vz);
+                    else
+                        hipLaunchKernelGGL((k_slab_hv_reg<N, -1>), grid, dim3(256), lds, s, d, t, sticks, Vz);
                     PDEP_HIP(hipGetLastError());
                     done = true;
                 }

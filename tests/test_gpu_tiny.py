@@ -246,3 +246,23 @@ def test_odd_row_count_parity(mode):
     print("odd rows", st, "relerr", err)
     assert st["n_rhs"] == 3 and st["n_notconv"] == 0
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("mode", ["bf16x3"])
+def test_fine_grid_runtime_radius_parity(mode):
+    """The tiny sphere (5 Ha, 10 bohr) on a 48^3 grid: the register slab pass runs with
+    a run-time sphere radius (|mx| <= 5 on 48-point lines, not the compiled one)."""
+    from paper_1501_03141_amd import pdep
+    Wf = inputs.Workload("tiny_fine", (10.0,) * 3, (48,) * 3, 5.0, 4, 4, 8, 1e-10, 1511)
+    V = inputs.vloc(Wf)
+    m = R.make_model(Wf.L, Wf.n, Wf.ecut, V, naive=False)
+    gs = R.ground_state(m, Wf.n_v, full=True)
+    phi = inputs.trial_block(m.miller[m.nz], 3, 213)
+    want = R.chi0bar_apply(m, gs, phi)
+    with pdep.Context(Wf.L, Wf.n, Wf.ecut, V, Wf.n_v, precision=pdep.PDEP_MIXED_BF16X3, cg_tol=1e-10,
+                      psi=gs.C, eps=gs.eps) as c:
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print("fine grid", st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= 1e-8
