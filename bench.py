@@ -195,7 +195,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-bands", type=int, default=12)
+    ap.add_argument("--cpu-bands", type=int, default=48)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--precision", choices=["bf16x3", "mixed_fp32"], default="bf16x3",
                     help="mixed mode of the timed steps (the other one is timed once beside it)")
