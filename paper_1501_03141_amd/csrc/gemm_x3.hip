@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float d = kb[j][q] - sh;
-                    const float f = 1.f / (d > kfloor ? d : kfloor);
+                    const float f = __builtin_amdgcn_rcpf(d > kfloor ? d : kfloor);
                     rb[j][2 * q] *= f;
                     rb[j][2 * q + 1] *= f;
                 }
@@ -255,14 +255,13 @@ __device__ __forceinline__ void load8f(const float* p, int avail, float (&v)[8])
 // Requires lda and lds multiples of 4 (16-byte aligned loads).
 // FUSED (the CG direction update): Y = p and, for active rows n only,
 //   p <- K r - sum_m S[n][m] A[m][k] + beta_n p,  K = 1 / max(kin[k] - shift[n], floor),
-//   beta_n = rz_new[n] / rz[n] (0 when rz[n] = 0); alpha and beta are unused.
+//   beta_n from the array beta; alpha and beta are unused.
 struct DirUpdate {
     const float2* r;
     long ldr;
     const float* kin;
     const double* shift;
-    const double* rz_new;
-    const double* rz;
+    const float* beta;
     const int* active;
     float kfloor;
 };
@@ -342,15 +341,14 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             for (int i = 0; i < 4; ++i) {
                 const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
                 if (n >= N || !du.active[n]) continue;
-                const double den = du.rz[n];
-                const float bn = (float)(den != 0.0 ? du.rz_new[n] / den : 0.0);
+                const float bn = du.beta[n];
                 const float sh = (float)du.shift[n];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = k0 + 16 * t + lr;
                     if (k < K) {
                         const float d = du.kin[k] - sh;
-                        const float f = 1.f / (d > du.kfloor ? d : du.kfloor);
+                        const float f = __builtin_amdgcn_rcpf(d > du.kfloor ? d : du.kfloor);
                         const float2 rv = du.r[(long)n * du.ldr + k];
                         float2* y = Y + (long)n * ldy + k;
                         const float2 pv = *y;
@@ -571,8 +569,8 @@ void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, 
 }
 
 void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
-                            long ldr, const float* kin, const double* shift, double kfloor, const double* rz_new,
-                            const double* rz, const int* active, float2* p, long ldp, hipStream_t s) {
+                            long ldr, const float* kin, const double* shift, double kfloor, const float* beta,
+                            const int* active, float2* p, long ldp, hipStream_t s) {
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
                  "cg_direction_x3: leading dimensions must be multiples of 4");
@@ -580,7 +578,7 @@ void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, cons
     dim3 grid((K + 63) / 64, (N + 127) / 128);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
                     (double)N * K * sizeof(float2) * 3.0, 4.0 * (double)M * N * K);
-    const DirUpdate du{r, ldr, kin, shift, rz_new, rz, active, (float)kfloor};
+    const DirUpdate du{r, ldr, kin, shift, beta, active, (float)kfloor};
     hipLaunchKernelGGL(k_gemm_update_x3r<true>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p, ldp,
                        du);
     PDEP_HIP(hipGetLastError());

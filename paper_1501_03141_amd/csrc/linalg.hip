@@ -353,9 +353,11 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
 }
 
 // rz[row] = sum_g rz_part[row][g], rr[row] likewise (g in order); inactive rows skipped.
+// beta (may be null): rz[row] / rz_old[row] (0 when rz_old[row] = 0), the CG direction factor.
 __global__ void k_sum_parts(int nrows, int nparts, const double* __restrict__ rz_part,
                             const double* __restrict__ rr_part, const int* __restrict__ active,
-                            double* __restrict__ rz, double* __restrict__ rr) {
+                            double* __restrict__ rz, double* __restrict__ rr, const double* __restrict__ rz_old,
+                            float* __restrict__ beta) {
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= nrows || !active[row]) return;
     double a = 0.0, b = 0.0;
@@ -365,6 +367,10 @@ __global__ void k_sum_parts(int nrows, int nparts, const double* __restrict__ rz
     }
     rz[row] = a;
     rr[row] = b;
+    if (beta) {
+        const double d = rz_old[row];
+        beta[row] = (float)(d != 0.0 ? a / d : 0.0);
+    }
 }
 
 template <typename T>
@@ -594,7 +600,7 @@ template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p, const cplx<T>* q,
                      long ld, const double* rz, const double* pq, int npq, const int* active, const T* kin,
                      const double* shift, int nshift, int precond, hipStream_t s, double* rz_part,
-                     double* rr_part, double* rz_new, double* rr, bool half) {
+                     double* rr_part, double* rz_new, double* rr, bool half, float* beta) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s, 7.0 * nrows * (double)K * sizeof(cplx<T>));
     hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
@@ -603,7 +609,7 @@ void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const
     PDEP_HIP(hipGetLastError());
     if (rz_part) {
         hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)rows_grid(K, nrows).x,
-                           rz_part, rr_part, active, rz_new, rr);
+                           rz_part, rr_part, active, rz_new, rr, rz, beta);
         PDEP_HIP(hipGetLastError());
     }
 }
@@ -723,7 +729,7 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
     template void launch_cg_step1<T>(int, int, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,   \
                                      long, const double*, const double*, int, const int*, const T*,            \
                                      const double*, int, int, hipStream_t, double*, double*, double*,          \
-                                     double*, bool);                                                          \
+                                     double*, bool, float*);                                                  \
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \
