@@ -255,13 +255,16 @@ __device__ __forceinline__ void load8f(const float* p, int avail, float (&v)[8])
 // Requires lda and lds multiples of 4 (16-byte aligned loads).
 // FUSED (the CG direction update): Y = p and, for active rows n only,
 //   p <- K r - sum_m S[n][m] A[m][k] + beta_n p,  K = 1 / max(kin[k] - shift[n], floor),
-//   beta_n from the array beta; alpha and beta are unused.
+//   beta_n from the array beta; alpha and beta are unused.  Before that, x[n] += a_n p[n]
+//   (the old p) with a_n from the array xalpha (x has the stride of p).
 struct DirUpdate {
     const float2* r;
     long ldr;
     const float* kin;
     const double* shift;
     const float* beta;
+    const float* xalpha;
+    float2* x;
     const int* active;
     float kfloor;
 };
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             for (int i = 0; i < 4; ++i) {
                 const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
                 if (n >= N || !du.active[n]) continue;
-                const float bn = du.beta[n];
+                const float bn = du.beta[n], an = du.xalpha[n];
                 const float sh = (float)du.shift[n];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -351,7 +354,12 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
                         const float f = __builtin_amdgcn_rcpf(d > du.kfloor ? d : du.kfloor);
                         const float2 rv = du.r[(long)n * du.ldr + k];
                         float2* y = Y + (long)n * ldy + k;
+                        float2* xp = du.x + (long)n * ldy + k;
                         const float2 pv = *y;
+                        float2 xv = *xp;
+                        xv.x += an * pv.x;
+                        xv.y += an * pv.y;
+                        *xp = xv;
                         *y = make_float2(f * rv.x - acc[a][2 * t][i] + bn * pv.x,
                                          f * rv.y - acc[a][2 * t + 1][i] + bn * pv.y);
                     }
@@ -570,15 +578,15 @@ void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, 
 
 void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
                             long ldr, const float* kin, const double* shift, double kfloor, const float* beta,
-                            const int* active, float2* p, long ldp, hipStream_t s) {
+                            const float* alpha, float2* x, const int* active, float2* p, long ldp, hipStream_t s) {
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
                  "cg_direction_x3: leading dimensions must be multiples of 4");
     PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "cg_direction_x3: N too large");
     dim3 grid((K + 63) / 64, (N + 127) / 128);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
-                    (double)N * K * sizeof(float2) * 3.0, 4.0 * (double)M * N * K);
-    const DirUpdate du{r, ldr, kin, shift, beta, active, (float)kfloor};
+                    (double)N * K * sizeof(float2) * 5.0, 4.0 * (double)M * N * K);
+    const DirUpdate du{r, ldr, kin, shift, beta, alpha, x, active, (float)kfloor};
     hipLaunchKernelGGL(k_gemm_update_x3r<true>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p, ldp,
                        du);
     PDEP_HIP(hipGetLastError());

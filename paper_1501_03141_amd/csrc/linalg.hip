@@ -311,7 +311,8 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
                            const double* __restrict__ rz, const double* __restrict__ pq, int npq,
                            const int* __restrict__ active, const T* __restrict__ kin,
                            const double* __restrict__ shift, int nshift, int precond,
-                           double* __restrict__ rz_part, double* __restrict__ rr_part, int half) {
+                           double* __restrict__ rz_part, double* __restrict__ rr_part, int half,
+                           float* __restrict__ alpha_out) {
     __shared__ double red[2][256];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
@@ -321,12 +322,17 @@ __global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__
         double den = 0.0;
         for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
         const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
+        if (alpha_out && k == 0) alpha_out[row] = (float)alpha;
         const long o = (long)row * ld + k;
-        const cplx<T> pv = p[o], qv = q[o];
-        cplx<T> xv = x[o], rv = r[o];
-        xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+        const cplx<T> qv = q[o];
+        cplx<T> rv = r[o];
+        if (x) {   // null: x is updated later (with alpha_out) by the caller
+            const cplx<T> pv = p[o];
+            cplx<T> xv = x[o];
+            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+            x[o] = xv;
+        }
         rv.x -= alpha * qv.x; rv.y -= alpha * qv.y;
-        x[o] = xv;
         r[o] = rv;
         const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
         if (z) z[o] = mk<T>(f * rv.x, f * rv.y);
@@ -600,12 +606,12 @@ template <typename T>
 void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const cplx<T>* p, const cplx<T>* q,
                      long ld, const double* rz, const double* pq, int npq, const int* active, const T* kin,
                      const double* shift, int nshift, int precond, hipStream_t s, double* rz_part,
-                     double* rr_part, double* rz_new, double* rr, bool half, float* beta) {
+                     double* rr_part, double* rz_new, double* rr, bool half, float* beta, float* alpha_out) {
     if (nrows <= 0) return;
-    ProfScope prof_(K_CG_UPDATE, s, 7.0 * nrows * (double)K * sizeof(cplx<T>));
+    ProfScope prof_(K_CG_UPDATE, s, (x ? 6.0 : 3.0) * nrows * (double)K * sizeof(cplx<T>));
     hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
                        npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part,
-                       half ? 1 : 0);
+                       half ? 1 : 0, alpha_out);
     PDEP_HIP(hipGetLastError());
     if (rz_part) {
         hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)rows_grid(K, nrows).x,
@@ -729,7 +735,7 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
     template void launch_cg_step1<T>(int, int, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, const cplx<T>*,   \
                                      long, const double*, const double*, int, const int*, const T*,            \
                                      const double*, int, int, hipStream_t, double*, double*, double*,          \
-                                     double*, bool, float*);                                                  \
+                                     double*, bool, float*, float*);                                          \
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \

@@ -225,11 +225,12 @@ void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, con
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
                                 double alpha, double beta, float2* Y, long ldy, hipStream_t s);
 // CG direction update with the projected preconditioned residual formed in the GEMM:
-// for active rows n, p[n] <- K r[n] - sum_m S[n][m] A[m] + beta[n] p[n], where
-// S = Re(A^H K r) comes from launch_gemm_ahb_x3_real with the same kin / shift / kfloor.
+// for active rows n, x[n] += alpha[n] p[n] (the old p) and
+// p[n] <- K r[n] - sum_m S[n][m] A[m] + beta[n] p[n], where S = Re(A^H K r) comes from
+// launch_gemm_ahb_x3_real with the same kin / shift / kfloor; x and p share the stride.
 void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
                             long ldr, const float* kin, const double* shift, double kfloor, const float* beta,
-                            const int* active, float2* p, long ldp, hipStream_t s);
+                            const float* alpha, float2* x, const int* active, float2* p, long ldp, hipStream_t s);
 // floor of the CG preconditioner 1 / max(1/2|G|^2 - e_v, floor) (Hartree)
 constexpr double kPrecondFloor = 0.1;
 // S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)
@@ -254,7 +255,7 @@ void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const
                      const cplx<T>* q, long ld, const double* rz, const double* pq, int npq, const int* active,
                      const T* kin, const double* shift, int nshift, int precond, hipStream_t s,
                      double* rz_part = nullptr, double* rr_part = nullptr, double* rz_new = nullptr,
-                     double* rr = nullptr, bool half = false, float* beta = nullptr);
+                     double* rr = nullptr, bool half = false, float* beta = nullptr, float* alpha_out = nullptr);
 template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new,
                      double* rz, const int* active, hipStream_t s);

@@ -424,9 +424,11 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 // fly and the update GEMM writes p = K r - Psi S + beta p directly
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
                 st.op_applications++;
+                // x += alpha p happens in the direction GEMM (which reads the old p anyway)
                 float* beta = reinterpret_cast<float*>(sc.pq);   // sc.pq is not used on this path
-                launch_cg_step1<T>(ncur, npw, x, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre,
-                                   s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta);
+                float* alpha = beta + n;
+                launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active, kin, sh,
+                                   ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta, alpha);
                 if constexpr (sizeof(T) == sizeof(float)) {
                     float* Sr = reinterpret_cast<float*>(S);
                     float* wr = static_cast<float*>(c.ws(W_SPLIT, ((size_t)8 << 20) * sizeof(float2)));
@@ -434,7 +436,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                     launch_gemm_ahb_x3_real(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
                                             (size_t)16 << 20, s, kin, sh, kPrecondFloor);
                     launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
-                                           beta, sc.active, p, ld, s);
+                                           beta, alpha, x, sc.active, p, ld, s);
                 }
                 if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
             } else if (pre) {
