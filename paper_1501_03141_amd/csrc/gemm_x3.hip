@@ -268,30 +268,30 @@ struct DirUpdate {
     const int* active;
     float kfloor;
 };
-template <bool FUSED>
+template <bool FUSED, int AR = 2>
 __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, const float2* __restrict__ A,
                                                          long lda, const float* __restrict__ S, long lds,
                                                          float alpha, float beta, float2* __restrict__ Y, long ldy,
                                                          DirUpdate du) {
-    constexpr int BK = 64, BNR = 128;
+    constexpr int BK = 64, BNR = 64 * AR;   // AR 16-row halves per wave
     __shared__ __align__(16) unsigned char As[2][2 * BK * kRowB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k0 = blockIdx.x * BK, n0 = blockIdx.y * BNR;
     const int lr = lane & 15, lq = lane >> 4;
 
-    x3_f4 acc[2][8];   // [a: 16-row half of the wave's rows][b: 16 real columns]
+    x3_f4 acc[AR][8];   // [a: 16-row part of the wave's rows][b: 16 real columns]
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AR; ++a)
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = x3_f4{0.f, 0.f, 0.f, 0.f};
 
     // A staging: thread -> (rows 2 mp and 2 mp + 1, 4 consecutive k from kg)
     const int mp = tid & 15, kg = 4 * (tid >> 4);
-    float rs[2][8], ra[2][8];
+    float rs[AR][8], ra[2][8];
     auto fetch = [&](int mc) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int n = n0 + 32 * wave + 16 * a + lr;
+        for (int a = 0; a < AR; ++a) {
+            const int n = n0 + 16 * AR * wave + 16 * a + lr;
             const int m = mc + 8 * lq;
             const int avail = n < N ? M - m : 0;
             load8f(S + (long)(n < N ? n : 0) * lds + m, avail, rs[a]);
@@ -316,9 +316,9 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
                 *reinterpret_cast<uint32_t*>(&As[0][off]) = w.x;
                 *reinterpret_cast<uint32_t*>(&As[1][off]) = w.y;
             }
-        x3_u4 sh[2], sl[2];
+        x3_u4 sh[AR], sl[AR];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < AR; ++a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint2 w = split2(rs[a][2 * q], rs[a][2 * q + 1]);
@@ -333,16 +333,16 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             const x3_u4 bh = *reinterpret_cast<const x3_u4*>(&As[0][off]);
             const x3_u4 bl = *reinterpret_cast<const x3_u4*>(&As[1][off]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a) acc[a][b] = mma3(sh[a], sl[a], bh, bl, acc[a][b]);
+            for (int a = 0; a < AR; ++a) acc[a][b] = mma3(sh[a], sl[a], bh, bl, acc[a][b]);
         }
         __syncthreads();
     }
     if constexpr (FUSED) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < AR; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
+                const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i;
                 if (n >= N || !du.active[n]) continue;
                 const float bn = du.beta[n], an = du.xalpha[n];
                 const float sh = (float)du.shift[n];
@@ -367,12 +367,12 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             }
     } else {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < AR; ++a)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int n = n0 + 32 * wave + 16 * a + 4 * lq + i;
+                    const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i;
                     const int k = k0 + 16 * t + lr;
                     if (n < N && k < K) {
                         float2* y = Y + (long)n * ldy + k;
@@ -582,13 +582,15 @@ void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, cons
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
                  "cg_direction_x3: leading dimensions must be multiples of 4");
-    PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "cg_direction_x3: N too large");
-    dim3 grid((K + 63) / 64, (N + 127) / 128);
+    // 16 rows per wave (64 per workgroup): the epilogue-heavy fused form runs 6-10% faster
+    // than with 32 at N_v = 128 (equal at 512)
+    PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "cg_direction_x3: N too large");
+    dim3 grid((K + 63) / 64, (N + 63) / 64);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
                     (double)N * K * sizeof(float2) * 5.0, 4.0 * (double)M * N * K);
     const DirUpdate du{r, ldr, kin, shift, beta, alpha, x, active, (float)kfloor};
-    hipLaunchKernelGGL(k_gemm_update_x3r<true>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p, ldp,
-                       du);
+    hipLaunchKernelGGL((k_gemm_update_x3r<true, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p,
+                       ldp, du);
     PDEP_HIP(hipGetLastError());
 }
 

@@ -437,23 +437,32 @@ __global__ void k_axpy_rows(int K, const cplx<T>* __restrict__ d, long ldd, cons
     x[xr * ldx + k] = xv;
 }
 
-// out[row] = a[rows[row]] - b[row]
-__global__ void k_sub_rows(int K, const double2* __restrict__ a, long lda, const int* __restrict__ rows,
-                           const double2* __restrict__ b, long ldb, double2* __restrict__ out, long ldo) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int row = blockIdx.y;
-    if (k >= K) return;
-    const long ar = rows ? rows[row] : row;
-    const double2 x = a[ar * lda + k], y = b[(long)row * ldb + k];
-    out[(long)row * ldo + k] = make_double2(x.x - y.x, x.y - y.y);
-}
-
-__global__ void k_scatter_rows(int K, const double2* __restrict__ src, long lds, const int* __restrict__ rows,
-                               double2* __restrict__ dst, long ldd) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int row = blockIdx.y;
-    if (k >= K) return;
-    dst[(long)rows[row] * ldd + k] = src[(long)row * lds + k];
+// r[rows[row]] = b[rows[row]] - q[row] and out[row] = ||r||^2 (half-sphere weights when
+// half), one workgroup per row.
+__global__ __launch_bounds__(256) void k_residual_rows(int K, const double2* __restrict__ b, long ldb,
+                                                       const int* __restrict__ rows, const double2* __restrict__ q,
+                                                       long ldq, double2* __restrict__ r, long ldr,
+                                                       double* __restrict__ out, int half) {
+    __shared__ double red[256];
+    const int row = blockIdx.x;
+    const long ir = rows[row];
+    const double2* br = b + ir * ldb;
+    const double2* qr = q + (long)row * ldq;
+    double2* rr = r + ir * ldr;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < K; k += 256) {
+        const double2 bv = br[k], qv = qr[k];
+        const double2 v = make_double2(bv.x - qv.x, bv.y - qv.y);
+        rr[k] = v;
+        acc += half_weight(half, k, K) * (v.x * v.x + v.y * v.y);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[row] = red[0];
 }
 
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
@@ -666,21 +675,15 @@ void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>*
 template void launch_half_weights<float>(int, int, const float2*, long, float2*, long, hipStream_t);
 template void launch_half_weights<double>(int, int, const double2*, long, double2*, long, hipStream_t);
 
-void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b, long ldb,
-                     double2* out, long ldo, hipStream_t s) {
+void launch_residual_rows(int nrows, int K, const double2* b, long ldb, const int* rows, const double2* q, long ldq,
+                          double2* r, long ldr, double* out, bool half, hipStream_t s) {
     if (nrows <= 0) return;
-    ProfScope prof_(K_MISC, s);
-    hipLaunchKernelGGL(k_sub_rows, rows_grid(K, nrows), dim3(256), 0, s, K, a, lda, rows, b, ldb, out, ldo);
+    ProfScope prof_(K_MISC, s, 3.0 * nrows * (double)K * sizeof(double2));
+    hipLaunchKernelGGL(k_residual_rows, dim3(nrows), dim3(256), 0, s, K, b, ldb, rows, q, ldq, r, ldr, out,
+                       half ? 1 : 0);
     PDEP_HIP(hipGetLastError());
 }
 
-void launch_scatter_rows(int nrows, int K, const double2* src, long lds, const int* rows, double2* dst, long ldd,
-                         hipStream_t s) {
-    if (nrows <= 0) return;
-    ProfScope prof_(K_MISC, s);
-    hipLaunchKernelGGL(k_scatter_rows, rows_grid(K, nrows), dim3(256), 0, s, K, src, lds, rows, dst, ldd);
-    PDEP_HIP(hipGetLastError());
-}
 
 void launch_sym_fix(int nrows, int npw, double2* x, long ld, hipStream_t s) {
     if (nrows <= 0) return;

@@ -274,12 +274,9 @@ void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* r
 // out[r][k] = 2 in[r][k] for k < K - 1, in[r][K - 1] at k = K - 1 (half-sphere weights)
 template <typename T>
 void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>* out, long ldo, hipStream_t s);
-// out[r] = a[rows[r]] - b[r]
-void launch_sub_rows(int nrows, int K, const double2* a, long lda, const int* rows, const double2* b,
-                     long ldb, double2* out, long ldo, hipStream_t s);
-// dst[rows[r]] = src[r]
-void launch_scatter_rows(int nrows, int K, const double2* src, long lds, const int* rows, double2* dst,
-                         long ldd, hipStream_t s);
+// res[rows[r]] = b[rows[r]] - q[r] and out[r] = ||res[rows[r]]||^2 (half-sphere weights when half)
+void launch_residual_rows(int nrows, int K, const double2* b, long ldb, const int* rows, const double2* q, long ldq,
+                          double2* res, long ldr, double* out, bool half, hipStream_t s);
 // rows <- their Hermitian-symmetric part (c_{-G} = conj c_G; -G_k sits at npw - 1 - k)
 void launch_sym_fix(int nrows, int npw, double2* x, long ld, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);

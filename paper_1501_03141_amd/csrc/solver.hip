@@ -560,15 +560,17 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         }
         std::vector<int> its(na);
         PDEP_HIP(hipMemcpyAsync(its.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
-        // true FP64 residual of the rows just updated
-        launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
-        apply_op<double>(c, xa, qa, ld, na, sc.shift, na, true, true,
+        // true FP64 residual of the rows just updated (all rows: no gather needed)
+        const double2* xin = x64;
+        if (na < n) {
+            launch_convert_rows<double, double>(na, npw, x64, ld, d_rows, nullptr, xa, ld, s);
+            xin = xa;
+        }
+        apply_op<double>(c, xin, qa, ld, na, sc.shift, na, true, true,
                          c.ws(W_STICKS, (size_t)na * sticks_row_bytes(c)),
                          static_cast<double2*>(c.ws(W_S, coef_bytes(nv, na))));
         st.op_applications++;
-        launch_sub_rows(na, npw, b64, ld, d_rows, qa, ld, qa, ld, s);
-        launch_scatter_rows(na, npw, qa, ld, d_rows, r64, ld, s);
-        launch_row_dots<double>(na, npw, qa, ld, qa, ld, sc.rr, nullptr, s, true);
+        launch_residual_rows(na, npw, b64, ld, d_rows, qa, ld, r64, ld, sc.rr, true, s);
         PDEP_HIP(hipMemcpyAsync(dots.data(), sc.rr, na * sizeof(double), hipMemcpyDeviceToHost, s));
         PDEP_HIP(hipStreamSynchronize(s));
         int itmax = 0;
