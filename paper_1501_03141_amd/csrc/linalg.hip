@@ -72,14 +72,32 @@ __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cpl
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     S += (long)blockIdx.z * N * lds;
-    for (int kc = kbeg; kc < kend; kc += BKC) {
+    // the next step's tiles are loaded into registers while the current one is multiplied
+    constexpr int NA = BMC * BKC / 256;
+    cplx<T> pa[NA], pb[4];
+    auto fetch = [&](int kc) {
 #pragma unroll
-        for (int j = 0; j < BMC * BKC / 256; ++j) {
+        for (int j = 0; j < NA; ++j) {
             const int e = tid + 256 * j;
             const int r = e / BKC, g = e % BKC;
-            cplx<T> v;
-            v.x = 0; v.y = 0;
-            if (m0 + r < M && kc + g < kend) v = A[(long)(m0 + r) * lda + kc + g];
+            pa[j].x = 0; pa[j].y = 0;
+            if (m0 + r < M && kc + g < kend) pa[j] = A[(long)(m0 + r) * lda + kc + g];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j;
+            const int r = e / BKC, g = e % BKC;
+            pb[j].x = 0; pb[j].y = 0;
+            if (n0 + r < N && kc + g < kend) pb[j] = B[(long)(n0 + r) * ldb + kc + g];
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int kc = kbeg; kc < kend; kc += BKC) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const int e = tid + 256 * j;
+            const int r = e / BKC, g = e % BKC;
+            const cplx<T> v = pa[j];
             if constexpr (REAL) {
                 As[2 * g][r] = v.x;
                 As[2 * g + 1][r] = v.y;
@@ -94,13 +112,11 @@ __global__ __launch_bounds__(256) void k_gemm_ahb(int M, int N, int K, const cpl
         for (int j = 0; j < 4; ++j) {
             const int e = tid + 256 * j;
             const int r = e / BKC, g = e % BKC;
-            cplx<T> v;
-            v.x = 0; v.y = 0;
-            if (n0 + r < N && kc + g < kend) v = B[(long)(n0 + r) * ldb + kc + g];
-            Bs[2 * g][r] = v.x;
-            Bs[2 * g + 1][r] = v.y;
+            Bs[2 * g][r] = pb[j].x;
+            Bs[2 * g + 1][r] = pb[j].y;
         }
         __syncthreads();
+        if (kc + BKC < kend) fetch(kc + BKC);
 #pragma unroll
         for (int kk = 0; kk < BKR; kk += 4) {
             const int kr = kk + (lane >> 4), c = lane & 15;
@@ -178,28 +194,46 @@ __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = typename Op::acc{0, 0, 0, 0};
-    for (int mc = 0; mc < M; mc += BMC) {
+    // the next step's tiles are loaded into registers while the current one is multiplied
+    constexpr int NS = BN * BMC / 256, NA = BMC * BKC / 256;
+    T psr[NS], psi[REAL ? 1 : NS];   // S tile (real parts; imaginary parts unless REAL)
+    cplx<T> pa[NA];
+    auto fetch = [&](int mc) {
 #pragma unroll
-        for (int j = 0; j < BN * BMC / 256; ++j) {        // S: 64 rows x BMC complex
+        for (int j = 0; j < NS; ++j) {        // S: 64 rows x BMC complex
             const int e = tid + 256 * j;
             const int r = e / BMC, mm = e % BMC;
-            cplx<T> v;
-            v.x = 0; v.y = 0;
-            if (n0 + r < N && mc + mm < M) v = S[(long)(n0 + r) * lds + mc + mm];
+            const bool in = n0 + r < N && mc + mm < M;
+            const T* sp = reinterpret_cast<const T*>(S + (long)(in ? n0 + r : 0) * lds + (in ? mc + mm : 0));
+            psr[j] = in ? sp[0] : T(0);
+            if constexpr (!REAL) psi[j] = in ? sp[1] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {        // A: BMC complex rows x 64 complex columns
+            const int e = tid + 256 * j;
+            const int mm = e / BKC, g = e % BKC;
+            pa[j].x = 0; pa[j].y = 0;
+            if (mc + mm < M && k0 + g < K) pa[j] = A[(long)(mc + mm) * lda + k0 + g];
+        }
+    };
+    fetch(0);
+    for (int mc = 0; mc < M; mc += BMC) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int e = tid + 256 * j;
+            const int r = e / BMC, mm = e % BMC;
             if constexpr (REAL) {
-                Ss[mm][r] = v.x;
+                Ss[mm][r] = psr[j];
             } else {
-                Ss[2 * mm][r] = v.x;
-                Ss[2 * mm + 1][r] = v.y;
+                Ss[2 * mm][r] = psr[j];
+                Ss[2 * mm + 1][r] = psi[j];
             }
         }
 #pragma unroll
-        for (int j = 0; j < BMC * BKC / 256; ++j) {       // A: BMC complex rows x 64 complex columns
+        for (int j = 0; j < NA; ++j) {
             const int e = tid + 256 * j;
             const int mm = e / BKC, g = e % BKC;
-            cplx<T> v;
-            v.x = 0; v.y = 0;
-            if (mc + mm < M && k0 + g < K) v = A[(long)(mc + mm) * lda + k0 + g];
+            const cplx<T> v = pa[j];
             if constexpr (REAL) {
                 Bs[mm][2 * g] = v.x;
                 Bs[mm][2 * g + 1] = v.y;
@@ -211,6 +245,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const 
             }
         }
         __syncthreads();
+        if (mc + BMC < M) fetch(mc + BMC);
 #pragma unroll
         for (int kk = 0; kk < BMR; kk += 4) {
             const int kr = kk + (lane >> 4), c = lane & 15;
