@@ -438,7 +438,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                     launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
                                            beta, alpha, x, sc.active, p, ld, s);
                 }
-                if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
+                // r is re-projected at the end of every second group (every 8 iterations)
+                if (k == nstep - 1 && (it / poll) % 2 == 1) project_c<T>(c, r, ld, ncur, S);
             } else if (pre) {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
                 st.op_applications++;
