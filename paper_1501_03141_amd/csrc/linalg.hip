@@ -321,8 +321,14 @@ __global__ __launch_bounds__(256) void k_row_dots(int K, const cplx<T>* __restri
 // floored (in Hartree) where it is small or negative.
 template <typename T>
 __device__ __forceinline__ T precond_factor(const T* kin, int k, double shift) {
-    const double d = (double)kin[k] - shift;
-    return (T)(1.0 / (d > kPrecondFloor ? d : kPrecondFloor));
+    if constexpr (sizeof(T) == sizeof(float)) {
+        // FP32 rows: the single-instruction reciprocal, as in the BF16x3 GEMMs that apply K
+        const float d = kin[k] - (float)shift, fl = (float)kPrecondFloor;
+        return __builtin_amdgcn_rcpf(d > fl ? d : fl);
+    } else {
+        const double d = (double)kin[k] - shift;
+        return (T)(1.0 / (d > kPrecondFloor ? d : kPrecondFloor));
+    }
 }
 
 template <typename T>
@@ -340,40 +346,50 @@ __global__ void k_cg_init(int K, const cplx<T>* __restrict__ b, long ld, cplx<T>
     z[o] = mk<T>(f * bv.x, f * bv.y);
 }
 
+// Rows of the CG step per workgroup column: each thread takes kStep1Elems entries of a
+// row (stride 256), so the per-row scalars (alpha from the <p, q> partials) are formed
+// once per kStep1Elems entries.
+constexpr int kStep1Elems = 4;
+
 template <typename T>
-__global__ void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__ r, cplx<T>* __restrict__ z,
-                           const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q, long ld,
-                           const double* __restrict__ rz, const double* __restrict__ pq, int npq,
-                           const int* __restrict__ active, const T* __restrict__ kin,
-                           const double* __restrict__ shift, int nshift, int precond,
-                           double* __restrict__ rz_part, double* __restrict__ rr_part, int half,
-                           float* __restrict__ alpha_out) {
+__global__ __launch_bounds__(256) void k_cg_step1(int K, cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
+                                                  cplx<T>* __restrict__ z, const cplx<T>* __restrict__ p,
+                                                  const cplx<T>* __restrict__ q, long ld,
+                                                  const double* __restrict__ rz, const double* __restrict__ pq,
+                                                  int npq, const int* __restrict__ active, const T* __restrict__ kin,
+                                                  const double* __restrict__ shift, int nshift, int precond,
+                                                  double* __restrict__ rz_part, double* __restrict__ rr_part, int half,
+                                                  float* __restrict__ alpha_out) {
     __shared__ double red[2][256];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
     if (!active[row]) return;                         // whole block: one row
+    double den = 0.0;
+    for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
+    const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
+    if (alpha_out && blockIdx.x == 0 && threadIdx.x == 0) alpha_out[row] = (float)alpha;
+    const double sh = shift[row % nshift];
     double srz = 0.0, srr = 0.0;
-    if (k < K) {
-        double den = 0.0;
-        for (int g = 0; g < npq; ++g) den += pq[(long)row * npq + g];
-        const T alpha = (T)(den > 0.0 ? rz[row] / den : 0.0);
-        if (alpha_out && k == 0) alpha_out[row] = (float)alpha;
-        const long o = (long)row * ld + k;
-        const cplx<T> qv = q[o];
-        cplx<T> rv = r[o];
-        if (x) {   // null: x is updated later (with alpha_out) by the caller
-            const cplx<T> pv = p[o];
-            cplx<T> xv = x[o];
-            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
-            x[o] = xv;
+#pragma unroll
+    for (int e = 0; e < kStep1Elems; ++e) {
+        const int k = (blockIdx.x * kStep1Elems + e) * 256 + threadIdx.x;
+        if (k < K) {
+            const long o = (long)row * ld + k;
+            const cplx<T> qv = q[o];
+            cplx<T> rv = r[o];
+            if (x) {   // null: x is updated later (with alpha_out) by the caller
+                const cplx<T> pv = p[o];
+                cplx<T> xv = x[o];
+                xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+                x[o] = xv;
+            }
+            rv.x -= alpha * qv.x; rv.y -= alpha * qv.y;
+            r[o] = rv;
+            const T f = precond ? precond_factor(kin, k, sh) : T(1);
+            if (z) z[o] = mk<T>(f * rv.x, f * rv.y);
+            const double n2 = half_weight(half, k, K) * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
+            srr += n2;
+            srz += (double)f * n2;
         }
-        rv.x -= alpha * qv.x; rv.y -= alpha * qv.y;
-        r[o] = rv;
-        const T f = precond ? precond_factor(kin, k, shift[row % nshift]) : T(1);
-        if (z) z[o] = mk<T>(f * rv.x, f * rv.y);
-        const double n2 = half_weight(half, k, K) * ((double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y);
-        srr = n2;
-        srz = (double)f * n2;
     }
     if (rz_part) {   // <r, K r> and ||r||^2 over this block (fixed-order tree)
         red[0][threadIdx.x] = srz;
@@ -653,13 +669,14 @@ void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const
                      double* rr_part, double* rz_new, double* rr, bool half, float* beta, float* alpha_out) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s, (x ? 6.0 : 3.0) * nrows * (double)K * sizeof(cplx<T>));
-    hipLaunchKernelGGL(k_cg_step1<T>, rows_grid(K, nrows), dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq,
-                       npq > 0 ? npq : 1, active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part,
-                       half ? 1 : 0, alpha_out);
+    const dim3 grid = rows_grid((K + kStep1Elems - 1) / kStep1Elems, nrows);
+    hipLaunchKernelGGL(k_cg_step1<T>, grid, dim3(256), 0, s, K, x, r, z, p, q, ld, rz, pq, npq > 0 ? npq : 1,
+                       active, kin, shift, nshift > 0 ? nshift : 1, precond, rz_part, rr_part, half ? 1 : 0,
+                       alpha_out);
     PDEP_HIP(hipGetLastError());
     if (rz_part) {
-        hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)rows_grid(K, nrows).x,
-                           rz_part, rr_part, active, rz_new, rr, rz, beta);
+        hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, (int)grid.x, rz_part,
+                           rr_part, active, rz_new, rr, rz, beta);
         PDEP_HIP(hipGetLastError());
     }
 }
