@@ -157,7 +157,12 @@ typedef struct pdep_ctx pdep_ctx;
  * complex (host) orthonormal occupied coefficients in S order with eps_in their
  * N_v energies; when NULL the library finds the N_v lowest eigenpairs of H with an
  * FP64 block Davidson to opts.gs_tol and checks the gap (PDEP_EGAP below
- * opts.gap_min).  *out receives the new context (NULL on error). */
+ * opts.gap_min).  Either way the orbitals are then replaced by an orthonormal basis
+ * of the same subspace made of functions real in r (c_{-G} = conj c_G), each a Ritz
+ * vector of H, with the Ritz values as energies (H is real in r, so a complete
+ * occupied eigenspace has such a basis); caller orbitals whose span is not closed
+ * under complex conjugation in r give PDEP_EINVAL.  *out receives the new context
+ * (NULL on error). */
 int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
                const double* psi_in, const double* eps_in, pdep_ctx** out);
 
@@ -166,8 +171,8 @@ int pdep_get_info(pdep_ctx* ctx, pdep_info* info);
 /* Miller indices of S, 3 * N_pw int32 (host), lexicographic (mx, my, mz). */
 int pdep_get_gvectors(pdep_ctx* ctx, int32_t* miller);
 
-/* Occupied energies (N_v doubles) and coefficients (N_v x N_pw complex), host.
- * Either pointer may be NULL. */
+/* Occupied energies (N_v doubles) and coefficients (N_v x N_pw complex, real in r:
+ * the basis pdep_setup keeps), host.  Either pointer may be NULL. */
 int pdep_get_orbitals(pdep_ctx* ctx, double* eps, double* psi);
 
 /* chi0bar applied to n_pert potentials (Eq. chiisamatrixinpdep with V_pert = phi~):

@@ -102,3 +102,20 @@ def test_small_chi0_bf16x3_parity(oracle_small):
     err = _relerr(got, want)
     print("stats", st, "relerr max", err.max())
     assert err.max() <= 1e-8
+
+
+def test_small_chain_block_tuning_repeatable(oracle_small):
+    """32 perturbations x 32 bands = 1024 systems: the first application times the
+    transform chain for several block sizes on the live data before the real pass, and
+    picks one.  Rows are independent, so a second call (tuned size reused) must give
+    bit-identical results."""
+    V, m, gs = oracle_small
+    from paper_1501_03141_amd import pdep
+    phi = inputs.trial_block(m.miller[m.nz], 32, W.seed + 11)
+    with _ctx(V, gs, precision=pdep.PDEP_MIXED_BF16X3) as c:
+        a, st_a = c.chi0_apply(phi)
+        b, st_b = c.chi0_apply(phi)
+    print("chunk", st_a["fft_chunk"], st_b["fft_chunk"])
+    assert st_a["n_rhs"] == 1024
+    assert st_a["fft_chunk"] > 0 and st_a["fft_chunk"] == st_b["fft_chunk"]
+    assert np.array_equal(a, b)
