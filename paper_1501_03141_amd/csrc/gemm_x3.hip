@@ -23,6 +23,7 @@
 //   gemm_update_real  Y[n][k] += sum_m S[n][m] A[m][k] with S real: a real GEMM over the
 //                     interleaved columns k' = 2k + c of Y and A.
 #include <cstdint>
+#include <type_traits>
 
 #include "pdep_internal.h"
 
@@ -84,6 +85,18 @@ __device__ __forceinline__ void load4(const float2* p, int avail, float (&v)[8])
     }
 }
 
+// Store v to p[0..3], entries at or beyond `avail` left untouched.
+__device__ __forceinline__ void store4(float2* p, int avail, const float (&v)[8]) {
+    if (avail >= 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4*>(p + 2) = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < avail) p[q] = make_float2(v[2 * q], v[2 * q + 1]);
+    }
+}
+
 constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad (conflict-free b128 reads)
 
 // S[n][m] = sum_{k in chunk z} conj(A[m][k]) B[n][k].
@@ -94,15 +107,25 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 // REAL: only the real parts, written as floats (Sv: float [N][lds]); otherwise complex
 // (Sv: float2 [N][lds], imaginary parts stored as zero when real_out is set).  With kin
 // non-null, B[n][k] is taken times the CG preconditioner 1 / max(kin[k] - shift[n], floor).
-template <int WM, int CT, bool REAL>
+//
+// STEP (REAL, kin set, a single m tile): B is the CG residual r before the step of this
+// iteration; every workgroup first forms alpha = <r, K r> / <p, q> of its rows from the
+// previous <r, K r> and the partial sums of <p, q>, stages r - alpha q in place of r,
+// writes it back to B (each entry of B is staged by exactly one workgroup), and adds its
+// half-sphere weighted |r|^2 and K |r|^2 in FP64; the four lanes of a row combine them
+// and the workgroup's sums go to rz_part / rr_part [n][blockIdx.z].  Inactive rows are
+// left as they are.
+template <int WM, int CT, bool REAL, bool STEP>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
                                                      const float2* __restrict__ B, long ldb, void* __restrict__ Sv,
                                                      long lds, int kchunk, int real_out, const float* __restrict__ kin,
-                                                     const double* __restrict__ shift, float kfloor) {
+                                                     const double* __restrict__ shift, float kfloor,
+                                                     CgStepFuse cs) {
     constexpr int NSUB = REAL ? 1 : 2;   // row tiles of A: real part, imaginary part
     constexpr int WN = 4 / WM;
     constexpr int BMC = 32 * WM, BN = 16 * CT * WN;
     constexpr int IT = BN / 64;   // B staging items per thread (4 complex each)
+    static_assert(!STEP || REAL, "the fused CG step works on real coefficients");
     __shared__ __align__(16) unsigned char Bs[2][BN * kRowB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -111,6 +134,27 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
     const int kend = min(K, kbeg + kchunk);
     const long zoff = (long)blockIdx.z * N * lds;
     const int lr = lane & 15, lq = lane >> 4;
+
+    float alp[IT], qb[IT][8];
+    bool act[IT];
+    double srz[IT], srr[IT];
+    if constexpr (STEP) {
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int n = n0 + ((tid + 256 * j) >> 2);
+            act[j] = n < N && cs.active[n];
+            double a = 0.0;
+            if (act[j]) {
+                double den = 0.0;
+                for (int g = 0; g < cs.npq; ++g) den += cs.pq[(long)n * cs.npq + g];
+                a = den > 0.0 ? cs.rz[n] / den : 0.0;
+                if (blockIdx.z == 0 && (tid & 3) == 0) cs.alpha_out[n] = (float)a;
+            }
+            alp[j] = (float)a;
+            srz[j] = 0.0;
+            srr[j] = 0.0;
+        }
+    }
 
     x3_f4 acc[2][NSUB][CT];
 #pragma unroll
@@ -135,6 +179,7 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
             const int n = n0 + (e >> 2), k = kc + 4 * (e & 3);
             const int avail = n < N ? kend - k : 0;
             load4(B + (long)(n < N ? n : 0) * ldb + k, avail, rb[j]);
+            if constexpr (STEP) load4(cs.q + (long)(n < N ? n : 0) * ldb + k, act[j] ? avail : 0, qb[j]);
             if (kin) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) kb[j][q] = q < avail ? kin[k + q] : 0.f;
@@ -148,7 +193,28 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             const int e = tid + 256 * j;
-            if (kin) {
+            if constexpr (STEP) {
+                const int n = n0 + (e >> 2), k = kc + 4 * (e & 3);
+                if (act[j]) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) rb[j][q] -= alp[j] * qb[j][q];
+                    store4(const_cast<float2*>(B) + (long)n * ldb + k, kend - k, rb[j]);
+                }
+                const float sh = n < N ? (float)shift[n] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float d = kb[j][q] - sh;
+                    const float f = __builtin_amdgcn_rcpf(d > kfloor ? d : kfloor);
+                    // entries past the chunk were read as zero and add nothing
+                    const double w = k + q == K - 1 ? 1.0 : 2.0;
+                    const double n2 = w * ((double)rb[j][2 * q] * (double)rb[j][2 * q] +
+                                           (double)rb[j][2 * q + 1] * (double)rb[j][2 * q + 1]);
+                    srr[j] += n2;
+                    srz[j] += (double)f * n2;
+                    rb[j][2 * q] *= f;
+                    rb[j][2 * q + 1] *= f;
+                }
+            } else if (kin) {
                 const int n = n0 + (e >> 2);
                 const float sh = n < N ? (float)shift[n] : 0.f;
 #pragma unroll
@@ -200,6 +266,21 @@ __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const 
                 for (int s = 0; s < NSUB; ++s) acc[g][s][c] = mma3(ah[g][s], al[g][s], bh, bl, acc[g][s][c]);
         }
         __syncthreads();
+    }
+    if constexpr (STEP) {
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            double a = srz[j], b = srr[j];
+            a += __shfl_xor(a, 1);
+            b += __shfl_xor(b, 1);
+            a += __shfl_xor(a, 2);
+            b += __shfl_xor(b, 2);
+            const int n = n0 + ((tid + 256 * j) >> 2);
+            if ((tid & 3) == 0 && act[j]) {
+                cs.rz_part[(long)n * gridDim.z + blockIdx.z] = a;
+                cs.rr_part[(long)n * gridDim.z + blockIdx.z] = b;
+            }
+        }
     }
 #pragma unroll
     for (int g = 0; g < 2; ++g)
@@ -265,6 +346,7 @@ struct DirUpdate {
     const float* beta;
     const float* xalpha;
     float2* x;
+    const int* xrow;   // row of x that slot n updates (null: row n)
     const int* active;
     float kfloor;
 };
@@ -346,6 +428,7 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
                 if (n >= N || !du.active[n]) continue;
                 const float bn = du.beta[n], an = du.xalpha[n];
                 const float sh = (float)du.shift[n];
+                const long xo = (long)(du.xrow ? du.xrow[n] : n) * ldy;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = k0 + 16 * t + lr;
@@ -354,7 +437,7 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
                         const float f = __builtin_amdgcn_rcpf(d > du.kfloor ? d : du.kfloor);
                         const float2 rv = du.r[(long)n * du.ldr + k];
                         float2* y = Y + (long)n * ldy + k;
-                        float2* xp = du.x + (long)n * ldy + k;
+                        float2* xp = du.x + xo + k;
                         const float2 pv = *y;
                         float2 xv = *xp;
                         xv.x += an * pv.x;
@@ -493,10 +576,11 @@ namespace {
 
 // REAL: S and work are float arrays (real parts only).
 template <bool REAL>
-void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, void* S, long lds,
-                 void* work, size_t work_elems, hipStream_t s, bool real_out, const float* kin = nullptr,
-                 const double* shift = nullptr, float kfloor = 0.f) {
-    if (M <= 0 || N <= 0) return;
+int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, void* S, long lds,
+                void* work, size_t work_elems, hipStream_t s, bool real_out, const float* kin = nullptr,
+                const double* shift = nullptr, float kfloor = 0.f, const CgStepFuse* cs = nullptr,
+                int max_parts = 0) {
+    if (M <= 0 || N <= 0) return 0;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
     // eight column tiles per wave when all four waves run along m and are mostly full
@@ -504,35 +588,55 @@ void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B
     const int BMC = 32 * WM, BN = 16 * CT * (4 / WM);
     PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
     dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
+    if (cs) {
+        PDEP_REQUIRE(REAL && kin && grid.x == 1 && max_parts > 0, PDEP_EINVAL,
+                     "gemm_ahb_x3: the fused CG step needs real output, the preconditioner and one m tile");
+    }
     // split K until about 512 workgroups (two per CU; more splits only add partial-sum
     // traffic: measured best at 512 for N_v = 128 and 512)
     int splits = 1;
     const long tiles = (long)grid.x * grid.y;
     if (work && tiles < 512) {
         splits = (int)std::min<long>((512 + tiles - 1) / tiles, std::max(1, K / 256));
+        if (cs) splits = std::min(splits, max_parts);
         while (splits > 1 && (size_t)splits * N * lds > work_elems) --splits;
     }
     const int kchunk = splits > 1 ? ((K + splits - 1) / splits + 15) / 16 * 16 : K;
     if (splits > 1) splits = (K + kchunk - 1) / kchunk;
     grid.z = splits;
-    // algorithmic: complex products (8 real flops) or their real parts (4)
+    // algorithmic: complex products (8 real flops) or their real parts (4); the fused
+    // step also reads q and writes r back
     const double esz = REAL ? sizeof(float) : sizeof(float2);
-    ProfScope prof_(K_GEMM_AHB, s, ((double)M + N) * K * sizeof(float2) + (double)M * N * esz,
+    ProfScope prof_(K_GEMM_AHB, s,
+                    ((double)M + N * (cs ? 3.0 : 1.0)) * K * sizeof(float2) + (double)M * N * esz,
                     (REAL ? 4.0 : 8.0) * (double)M * N * K);
     void* out = splits > 1 ? work : S;
     const int ro = (real_out && splits == 1) ? 1 : 0;
-    if (WM == 1)
-        hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro, kin, shift, kfloor);
-    else if (WM == 2)
-        hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro, kin, shift, kfloor);
-    else if (CT == 8)
-        hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro, kin, shift, kfloor);
-    else
-        hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4, REAL>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out, lds,
-                           kchunk, ro, kin, shift, kfloor);
+    const CgStepFuse none{};
+    auto launch = [&](auto step) {
+        constexpr bool ST = decltype(step)::value;
+        const CgStepFuse& c = cs ? *cs : none;
+        if (WM == 1)
+            hipLaunchKernelGGL((k_gemm_ahb_x3<1, 4, REAL, ST>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out,
+                               lds, kchunk, ro, kin, shift, kfloor, c);
+        else if (WM == 2)
+            hipLaunchKernelGGL((k_gemm_ahb_x3<2, 4, REAL, ST>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out,
+                               lds, kchunk, ro, kin, shift, kfloor, c);
+        else if (CT == 8)
+            hipLaunchKernelGGL((k_gemm_ahb_x3<4, 8, REAL, ST>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out,
+                               lds, kchunk, ro, kin, shift, kfloor, c);
+        else
+            hipLaunchKernelGGL((k_gemm_ahb_x3<4, 4, REAL, ST>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, out,
+                               lds, kchunk, ro, kin, shift, kfloor, c);
+    };
+    if constexpr (REAL) {
+        if (cs)
+            launch(std::true_type{});
+        else
+            launch(std::false_type{});
+    } else {
+        launch(std::false_type{});
+    }
     PDEP_HIP(hipGetLastError());
     if (splits > 1) {
         if constexpr (REAL) {
@@ -545,6 +649,7 @@ void gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B
                                      real_out);
         }
     }
+    return splits;
 }
 
 }  // namespace
@@ -560,6 +665,16 @@ void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, con
     PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_real: lds must be a multiple of 4");
     PDEP_REQUIRE(!kin || (shift && kfloor > 0), PDEP_EINVAL, "gemm_ahb_x3_real: preconditioner needs shifts");
     gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor);
+}
+
+int launch_gemm_ahb_x3_step(int M, int N, int K, const float2* A, long lda, float2* r, long ldr, float* S, long lds,
+                            float* work, size_t work_elems, hipStream_t s, const float* kin, const double* shift,
+                            double kfloor, const CgStepFuse& cs, int max_parts) {
+    PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_step: lds must be a multiple of 4");
+    PDEP_REQUIRE(kin && shift && kfloor > 0, PDEP_EINVAL, "gemm_ahb_x3_step: the step needs the preconditioner");
+    PDEP_REQUIRE(M <= 128, PDEP_EINVAL, "gemm_ahb_x3_step: at most 128 coefficient rows");
+    return gemm_ahb_x3<true>(M, N, K, A, lda, r, ldr, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor,
+                             &cs, max_parts);
 }
 
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
@@ -578,7 +693,8 @@ void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, 
 
 void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
                             long ldr, const float* kin, const double* shift, double kfloor, const float* beta,
-                            const float* alpha, float2* x, const int* active, float2* p, long ldp, hipStream_t s) {
+                            const float* alpha, float2* x, const int* xrow, const int* active, float2* p, long ldp,
+                            hipStream_t s) {
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
                  "cg_direction_x3: leading dimensions must be multiples of 4");
@@ -588,7 +704,7 @@ void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, cons
     dim3 grid((K + 63) / 64, (N + 63) / 64);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
                     (double)N * K * sizeof(float2) * 5.0, 4.0 * (double)M * N * K);
-    const DirUpdate du{r, ldr, kin, shift, beta, alpha, x, active, (float)kfloor};
+    const DirUpdate du{r, ldr, kin, shift, beta, alpha, x, xrow, active, (float)kfloor};
     hipLaunchKernelGGL((k_gemm_update_x3r<true, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, -1.f, 0.f, p,
                        ldp, du);
     PDEP_HIP(hipGetLastError());

@@ -224,13 +224,35 @@ void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, con
                              const double* shift = nullptr, double kfloor = 0.0);
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
                                 double alpha, double beta, float2* Y, long ldy, hipStream_t s);
+// The residual update of a preconditioned CG step, for the rows of launch_gemm_ahb_x3_step.
+struct CgStepFuse {
+    const float2* q = nullptr;     // q = (H - shift) p of this iteration, stride as r
+    const double* rz = nullptr;    // <r, K r> before the step
+    const double* pq = nullptr;    // partial sums of <p, q>, npq per row
+    int npq = 0;
+    const int* active = nullptr;   // rows not active are left unchanged
+    float* alpha_out = nullptr;    // alpha = <r, K r> / <p, q> of the active rows
+    double* rz_part = nullptr;     // [row][part] partial sums of the new <r, K r> ...
+    double* rr_part = nullptr;     // ... and of the new ||r||^2 (half-sphere weights)
+};
+// launch_gemm_ahb_x3_real (with the preconditioner) on r after the step: for the active
+// rows r <- r - alpha q, written back in place, with <r, K r> and ||r||^2 of the new r as
+// partial sums (M <= 128).  Returns the number of parts per row (<= max_parts).
+int launch_gemm_ahb_x3_step(int M, int N, int K, const float2* A, long lda, float2* r, long ldr, float* S, long lds,
+                            float* work, size_t work_elems, hipStream_t s, const float* kin, const double* shift,
+                            double kfloor, const CgStepFuse& cs, int max_parts);
+// rz[row] = sum_g rz_part[row][g], rr[row] likewise, beta[row] = rz[row] / rz_old[row]
+// for the active rows (nparts parts per row, summed in order)
+void launch_sum_parts(int nrows, int nparts, const double* rz_part, const double* rr_part, const int* active,
+                      double* rz, double* rr, const double* rz_old, float* beta, hipStream_t s);
 // CG direction update with the projected preconditioned residual formed in the GEMM:
-// for active rows n, x[n] += alpha[n] p[n] (the old p) and
+// for active rows n, x[xrow[n]] += alpha[n] p[n] (the old p; xrow null: row n) and
 // p[n] <- K r[n] - sum_m S[n][m] A[m] + beta[n] p[n], where S = Re(A^H K r) comes from
 // launch_gemm_ahb_x3_real with the same kin / shift / kfloor; x and p share the stride.
 void launch_cg_direction_x3(int M, int N, int K, const float2* A, long lda, const float* S, long lds, const float2* r,
                             long ldr, const float* kin, const double* shift, double kfloor, const float* beta,
-                            const float* alpha, float2* x, const int* active, float2* p, long ldp, hipStream_t s);
+                            const float* alpha, float2* x, const int* xrow, const int* active, float2* p, long ldp,
+                            hipStream_t s);
 // floor of the CG preconditioner 1 / max(1/2|G|^2 - e_v, floor) (Hartree)
 constexpr double kPrecondFloor = 0.1;
 // S[n][m] = sum_z P[z][n][m], z = 0, 1, ... in order (split-K partial products)

@@ -262,7 +262,7 @@ __global__ void k_gather_state(int K, long ld, const int* __restrict__ map, cons
     const int j = blockIdx.y;
     if (k >= K) return;
     const long o = (long)map[j] * ld + k, n = (long)j * ld + k;
-    x1[n] = x0[o];
+    if (x0) x1[n] = x0[o];
     r1[n] = r0[o];
     if (z0) z1[n] = z0[o];
     p1[n] = p0[o];
@@ -351,7 +351,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     hipLaunchKernelGGL(k_iota_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, sc.shift, sc.thr2, sc.s_shift[0],
                        sc.s_thr2[0], sc.s_id[0], sc.s_iters[0]);
     PDEP_HIP(hipGetLastError());
-    launch_cg_init<T>(n, npw, b, ld, X[0], R[0], Z[0], kin, sc.s_shift[0], n, pre, s);
+    // fused path: x lives in xout at the caller's row (slot ids start as the identity)
+    launch_cg_init<T>(n, npw, b, ld, fused ? xout : X[0], R[0], Z[0], kin, sc.s_shift[0], n, pre, s);
     if (pre) project_c<T>(c, Z[0], ld, n, S);
     PDEP_HIP(hipMemcpyAsync(P[0], Z[0], vbytes, hipMemcpyDeviceToDevice, s));
     launch_row_dots<T>(n, npw, R[0], ld, Z[0], ld, sc.s_rz[0], sc.rr, s, half);
@@ -368,9 +369,10 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
         const int nr = (int)list.size();
         PDEP_HIP(hipMemcpyAsync(dmap + n, list.data(), nr * sizeof(int), hipMemcpyHostToDevice, s));
         {
-            ProfScope prof_(K_MISC, s, 2.0 * nr * npw * sizeof(cplx<T>));
-            hipLaunchKernelGGL(k_retire<T>, dim3((npw + 255) / 256, nr), dim3(256), 0, s, npw, ld, dmap + n,
-                               sc.s_id[cur], X[cur], xout);
+            ProfScope prof_(K_MISC, s, fused ? 0.0 : 2.0 * nr * npw * sizeof(cplx<T>));
+            if (!fused)   // the fused path accumulates x in place (row s_id of xout)
+                hipLaunchKernelGGL(k_retire<T>, dim3((npw + 255) / 256, nr), dim3(256), 0, s, npw, ld, dmap + n,
+                                   sc.s_id[cur], X[cur], xout);
             hipLaunchKernelGGL(k_retire_iters, dim3((nr + 255) / 256), dim3(256), 0, s, nr, dmap + n, sc.s_id[cur],
                                sc.s_iters[cur], sc.iters);
         }
@@ -394,10 +396,10 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             PDEP_HIP(hipMemcpyAsync(dmap, keep.data(), nk * sizeof(int), hipMemcpyHostToDevice, s));
             const int nxt = 1 - cur;
             {
-                ProfScope prof_(K_MISC, s, 8.0 * nk * npw * sizeof(cplx<T>));
+                ProfScope prof_(K_MISC, s, (fused ? 4.0 : 8.0) * nk * npw * sizeof(cplx<T>));
                 hipLaunchKernelGGL(k_gather_state<T>, dim3((npw + 255) / 256, nk), dim3(256), 0, s, npw, ld, dmap,
-                                   X[cur], R[cur], fused ? nullptr : Z[cur], P[cur], X[nxt], R[nxt], Z[nxt],
-                                   P[nxt]);
+                                   fused ? nullptr : X[cur], R[cur], fused ? nullptr : Z[cur], P[cur], X[nxt], R[nxt],
+                                   Z[nxt], P[nxt]);
                 hipLaunchKernelGGL(k_gather_slots, dim3((nk + 255) / 256), dim3(256), 0, s, nk, dmap, sc.s_rz[cur],
                                    sc.s_shift[cur], sc.s_thr2[cur], sc.s_iters[cur], sc.s_id[cur], sc.s_rz[nxt],
                                    sc.s_shift[nxt], sc.s_thr2[nxt], sc.s_iters[nxt], sc.s_id[nxt], sc.active);
@@ -429,16 +431,34 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 // x += alpha p happens in the direction GEMM (which reads the old p anyway)
                 float* beta = reinterpret_cast<float*>(sc.pq);   // sc.pq is not used on this path
                 float* alpha = beta + n;
-                launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active, kin, sh,
-                                   ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta, alpha);
                 if constexpr (sizeof(T) == sizeof(float)) {
                     float* Sr = reinterpret_cast<float*>(S);
                     float* wr = static_cast<float*>(c.ws(W_SPLIT, ((size_t)8 << 20) * sizeof(float2)));
                     const long lp = sphere_ld(c.basis.npw), lds = coef_ld(nv);
-                    launch_gemm_ahb_x3_real(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
-                                            (size_t)16 << 20, s, kin, sh, kPrecondFloor);
+                    if (nv <= 128) {
+                        // r -= alpha q and its inner products inside the coefficient GEMM
+                        CgStepFuse cs;
+                        cs.q = q;
+                        cs.rz = rz;
+                        cs.pq = pq_part;
+                        cs.npq = npq;
+                        cs.active = sc.active;
+                        cs.alpha_out = alpha;
+                        cs.rz_part = rz_part;
+                        cs.rr_part = rr_part;
+                        const int nparts = launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld,
+                                                                   Sr, lds, wr, (size_t)16 << 20, s, kin, sh,
+                                                                   kPrecondFloor, cs, nblk);
+                        launch_sum_parts(ncur, nparts, rz_part, rr_part, sc.active, sc.rz_new, sc.rr, rz, beta, s);
+                    } else {
+                        launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active,
+                                           kin, sh, ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta,
+                                           alpha);
+                        launch_gemm_ahb_x3_real(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
+                                                (size_t)16 << 20, s, kin, sh, kPrecondFloor);
+                    }
                     launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
-                                           beta, alpha, x, sc.active, p, ld, s);
+                                           beta, alpha, xout, sc.s_id[cur], sc.active, p, ld, s);
                 }
                 // r is re-projected every 8 iterations
                 if ((it + k + 1) % 8 == 0) project_c<T>(c, r, ld, ncur, S);
