@@ -38,7 +38,7 @@ namespace {
 
 enum Slot {
     W_B64 = 0, W_X64, W_R64, W_XA, W_QA, W_RHS, W_CX, W_CR, W_CZ, W_CP, W_CQ, W_STICKS, W_S, W_SCAL,
-    W_ROWS, W_VR, W_DN, W_REF2, W_CX2, W_CR2, W_CZ2, W_CP2, W_XOUT, W_MAP, W_SPLIT, W_PQP, W_LAST
+    W_ROWS, W_VR, W_DN, W_REF2, W_XOUT, W_MAP, W_SPLIT, W_PQP, W_LAST
 };
 static_assert(W_LAST <= WS_SOLVER_END, "solver work-space slots overlap the others");
 
@@ -253,35 +253,33 @@ CgScalars cg_scalars(Ctx& c, int n) {
 }
 
 // Compaction kernels.  map[j] = old slot of new slot j.
+// Compaction in place: live slot src[j] (at or beyond the new count) moves into the
+// retired slot dst[j] (below it); the two sets are disjoint, so no slot is both read and
+// written.
 template <typename T>
-__global__ void k_gather_state(int K, long ld, const int* __restrict__ map, const cplx<T>* __restrict__ x0,
-                               const cplx<T>* __restrict__ r0, const cplx<T>* __restrict__ z0,
-                               const cplx<T>* __restrict__ p0, cplx<T>* __restrict__ x1, cplx<T>* __restrict__ r1,
-                               cplx<T>* __restrict__ z1, cplx<T>* __restrict__ p1) {
+__global__ void k_move_state(int K, long ld, const int* __restrict__ dst, const int* __restrict__ src,
+                             cplx<T>* x, cplx<T>* r, cplx<T>* z, cplx<T>* p) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (k >= K) return;
-    const long o = (long)map[j] * ld + k, n = (long)j * ld + k;
-    if (x0) x1[n] = x0[o];
-    r1[n] = r0[o];
-    if (z0) z1[n] = z0[o];
-    p1[n] = p0[o];
+    const long o = (long)src[j] * ld + k, n = (long)dst[j] * ld + k;
+    if (x) x[n] = x[o];
+    r[n] = r[o];
+    if (z) z[n] = z[o];
+    p[n] = p[o];
 }
 
-__global__ void k_gather_slots(int n, const int* __restrict__ map, const double* __restrict__ rz0,
-                               const double* __restrict__ sh0, const double* __restrict__ th0,
-                               const int* __restrict__ it0, const int* __restrict__ id0, double* __restrict__ rz1,
-                               double* __restrict__ sh1, double* __restrict__ th1, int* __restrict__ it1,
-                               int* __restrict__ id1, int* __restrict__ active) {
+__global__ void k_move_slots(int nm, const int* __restrict__ dst, const int* __restrict__ src, double* rz,
+                             double* sh, double* th, int* it, int* id, int* active) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int o = map[j];
-    rz1[j] = rz0[o];
-    sh1[j] = sh0[o];
-    th1[j] = th0[o];
-    it1[j] = it0[o];
-    id1[j] = id0[o];
-    active[j] = 1;
+    if (j >= nm) return;
+    const int d = dst[j], o = src[j];
+    rz[d] = rz[o];
+    sh[d] = sh[o];
+    th[d] = th[o];
+    it[d] = it[o];
+    id[d] = id[o];
+    active[d] = 1;
 }
 
 // Retire slots: Xout[id[o]] = x[o], iters_out[id[o]] = iters[o] for o in list.
@@ -327,10 +325,10 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const int npw = half_len(c.basis.npw), nv = c.nv;
     hipStream_t s = c.stream;
     const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
-    cplx<T>* X[2] = {static_cast<cplx<T>*>(c.ws(W_CX, vbytes)), static_cast<cplx<T>*>(c.ws(W_CX2, vbytes))};
-    cplx<T>* R[2] = {static_cast<cplx<T>*>(c.ws(W_CR, vbytes)), static_cast<cplx<T>*>(c.ws(W_CR2, vbytes))};
-    cplx<T>* Z[2] = {static_cast<cplx<T>*>(c.ws(W_CZ, vbytes)), static_cast<cplx<T>*>(c.ws(W_CZ2, vbytes))};
-    cplx<T>* P[2] = {static_cast<cplx<T>*>(c.ws(W_CP, vbytes)), static_cast<cplx<T>*>(c.ws(W_CP2, vbytes))};
+    cplx<T>* x = static_cast<cplx<T>*>(c.ws(W_CX, vbytes));
+    cplx<T>* r = static_cast<cplx<T>*>(c.ws(W_CR, vbytes));
+    cplx<T>* z = static_cast<cplx<T>*>(c.ws(W_CZ, vbytes));
+    cplx<T>* p = static_cast<cplx<T>*>(c.ws(W_CP, vbytes));
     cplx<T>* q = static_cast<cplx<T>*>(c.ws(W_CQ, vbytes));
     cplx<T>* xout = static_cast<cplx<T>*>(c.ws(W_XOUT, vbytes));
     int* dmap = static_cast<int*>(c.ws(W_MAP, (size_t)2 * n * sizeof(int) + 64));
@@ -346,24 +344,24 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const T* kin = kin_of<T>(c);
     // BF16x3 with the preconditioner: fused direction update (no z pass)
     const bool fused = pre && sizeof(T) == sizeof(float) && c.opts.precision == PDEP_MIXED_BF16X3;
-    int cur = 0, ncur = n;
+    int ncur = n;
 
     hipLaunchKernelGGL(k_iota_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, sc.shift, sc.thr2, sc.s_shift[0],
                        sc.s_thr2[0], sc.s_id[0], sc.s_iters[0]);
     PDEP_HIP(hipGetLastError());
     // fused path: x lives in xout at the caller's row (slot ids start as the identity)
-    launch_cg_init<T>(n, npw, b, ld, fused ? xout : X[0], R[0], Z[0], kin, sc.s_shift[0], n, pre, s);
-    if (pre) project_c<T>(c, Z[0], ld, n, S);
-    PDEP_HIP(hipMemcpyAsync(P[0], Z[0], vbytes, hipMemcpyDeviceToDevice, s));
-    launch_row_dots<T>(n, npw, R[0], ld, Z[0], ld, sc.s_rz[0], sc.rr, s, half);
+    launch_cg_init<T>(n, npw, b, ld, fused ? xout : x, r, z, kin, sc.s_shift[0], n, pre, s);
+    if (pre) project_c<T>(c, z, ld, n, S);
+    PDEP_HIP(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, s));
+    launch_row_dots<T>(n, npw, r, ld, z, ld, sc.s_rz[0], sc.rr, s, half);
     launch_fill_i32(sc.active, n, 1, s);
     launch_fill_zero(sc.n_active, sizeof(int), s);
     launch_cg_check(n, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], sc.s_rz[0], nullptr, sc.n_active, 0, s);
     int h_active = 0;
     PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
     PDEP_HIP(hipStreamSynchronize(s));
-    std::vector<int> flags, keep, ret;
-    // retire the slots in `list` (host) of set `cur`
+    std::vector<int> flags, keep, ret, mv;
+    // retire the slots in `list` (host)
     auto retire = [&](const std::vector<int>& list) {
         if (list.empty()) return;
         const int nr = (int)list.size();
@@ -372,9 +370,9 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             ProfScope prof_(K_MISC, s, fused ? 0.0 : 2.0 * nr * npw * sizeof(cplx<T>));
             if (!fused)   // the fused path accumulates x in place (row s_id of xout)
                 hipLaunchKernelGGL(k_retire<T>, dim3((npw + 255) / 256, nr), dim3(256), 0, s, npw, ld, dmap + n,
-                                   sc.s_id[cur], X[cur], xout);
-            hipLaunchKernelGGL(k_retire_iters, dim3((nr + 255) / 256), dim3(256), 0, s, nr, dmap + n, sc.s_id[cur],
-                               sc.s_iters[cur], sc.iters);
+                                   sc.s_id[0], x, xout);
+            hipLaunchKernelGGL(k_retire_iters, dim3((nr + 255) / 256), dim3(256), 0, s, nr, dmap + n, sc.s_id[0],
+                               sc.s_iters[0], sc.iters);
         }
         PDEP_HIP(hipGetLastError());
     };
@@ -384,7 +382,8 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     const int poll = 2;
     while (h_active > 0 && it < maxit) {
         if (h_active < ncur && (10 * h_active < 9 * ncur)) {
-            // compact: retire converged slots, gather live state into the other set
+            // compact: retire converged slots, then fill the holes they leave below the new
+            // count with the live slots above it (state is moved only for those)
             flags.resize(ncur);
             PDEP_HIP(hipMemcpyAsync(flags.data(), sc.active, ncur * sizeof(int), hipMemcpyDeviceToHost, s));
             PDEP_HIP(hipStreamSynchronize(s));
@@ -392,27 +391,29 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             ret.clear();
             for (int j = 0; j < ncur; ++j) (flags[j] ? keep : ret).push_back(j);
             retire(ret);
+            // move the live slots at or beyond nk into the retired slots below it
             const int nk = (int)keep.size();
-            PDEP_HIP(hipMemcpyAsync(dmap, keep.data(), nk * sizeof(int), hipMemcpyHostToDevice, s));
-            const int nxt = 1 - cur;
-            {
-                ProfScope prof_(K_MISC, s, (fused ? 4.0 : 8.0) * nk * npw * sizeof(cplx<T>));
-                hipLaunchKernelGGL(k_gather_state<T>, dim3((npw + 255) / 256, nk), dim3(256), 0, s, npw, ld, dmap,
-                                   fused ? nullptr : X[cur], R[cur], fused ? nullptr : Z[cur], P[cur], X[nxt], R[nxt],
-                                   Z[nxt], P[nxt]);
-                hipLaunchKernelGGL(k_gather_slots, dim3((nk + 255) / 256), dim3(256), 0, s, nk, dmap, sc.s_rz[cur],
-                                   sc.s_shift[cur], sc.s_thr2[cur], sc.s_iters[cur], sc.s_id[cur], sc.s_rz[nxt],
-                                   sc.s_shift[nxt], sc.s_thr2[nxt], sc.s_iters[nxt], sc.s_id[nxt], sc.active);
+            mv.clear();
+            for (int j : ret)
+                if (j < nk) mv.push_back(j);
+            const int nm = (int)mv.size();
+            for (int j : keep)
+                if (j >= nk) mv.push_back(j);
+            if (nm > 0) {
+                PDEP_HIP(hipMemcpyAsync(dmap, mv.data(), 2 * nm * sizeof(int), hipMemcpyHostToDevice, s));
+                ProfScope prof_(K_MISC, s, ((fused ? 4.0 : 8.0) * nm) * npw * sizeof(cplx<T>));
+                hipLaunchKernelGGL(k_move_state<T>, dim3((npw + 255) / 256, nm), dim3(256), 0, s, npw, ld, dmap,
+                                   dmap + nm, fused ? nullptr : x, r, fused ? nullptr : z, p);
+                hipLaunchKernelGGL(k_move_slots, dim3((nm + 255) / 256), dim3(256), 0, s, nm, dmap, dmap + nm,
+                                   sc.s_rz[0], sc.s_shift[0], sc.s_thr2[0], sc.s_iters[0], sc.s_id[0], sc.active);
+                PDEP_HIP(hipGetLastError());
             }
-            PDEP_HIP(hipGetLastError());
-            PDEP_HIP(hipStreamSynchronize(s));   // keep / ret host vectors are reused
-            cur = nxt;
+            PDEP_HIP(hipStreamSynchronize(s));   // keep / ret / mv host vectors are reused
             ncur = nk;
         }
         const int nstep = std::min(poll, maxit - it);
-        cplx<T> *x = X[cur], *r = R[cur], *z = Z[cur], *p = P[cur];
-        double* rz = sc.s_rz[cur];
-        double* sh = sc.s_shift[cur];
+        double* rz = sc.s_rz[0];
+        double* sh = sc.s_shift[0];
         for (int k = 0; k < nstep; ++k) {
             // With the preconditioner z = P_c K r is projected every iteration, so p stays in
             // range(P_c) and q = (H - shift) p needs no projection: <p, q> and the update of
@@ -458,7 +459,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                                                 (size_t)16 << 20, s, kin, sh, kPrecondFloor);
                     }
                     launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
-                                           beta, alpha, xout, sc.s_id[cur], sc.active, p, ld, s);
+                                           beta, alpha, xout, sc.s_id[0], sc.active, p, ld, s);
                 }
                 // r is re-projected every 8 iterations
                 if ((it + k + 1) % 8 == 0) project_c<T>(c, r, ld, ncur, S);
@@ -478,7 +479,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             }
             if (!(pre && fused)) launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             launch_fill_zero(sc.n_active, sizeof(int), s);
-            launch_cg_check(ncur, sc.rr, sc.s_thr2[cur], sc.active, sc.s_iters[cur], rz, sc.rz_new, sc.n_active, 1,
+            launch_cg_check(ncur, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], rz, sc.rz_new, sc.n_active, 1,
                             s);
         }
         it += nstep;
