@@ -1023,6 +1023,222 @@ __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, f
         for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
 }
 
+// ---------------------------------------------- FP64 slab pass, lines on lane quads ---
+// A double line of length NL does not fit one lane's registers, so each line is held by
+// the four lanes of a DPP quad (lanes 4u .. 4u + 3; lane t = 0..3 of the quad), NL / 4
+// values each, and split by one radix-4 step whose butterflies combine values across the
+// quad in two radix-2 exchanges (quad_perm [1, 0, 3, 2] and [2, 3, 0, 1]).  All lanes of
+// a quad always take the same branch.
+
+template <int CTRL> __device__ __forceinline__ double quad_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+// v of lane t ^ 1 (CTRL 0xB1) or t ^ 2 (CTRL 0x4E)
+template <int CTRL> __device__ __forceinline__ double2 quad_swap(double2 v) {
+    return make_double2(quad_swap<CTRL>(v.x), quad_swap<CTRL>(v.y));
+}
+constexpr int kSwap1 = 0xB1, kSwap2 = 0x4E;
+
+// Per-lane constants of the quad transforms: sign factors of the two exchanges and the
+// quarter-turn factor of lane 3, so that every butterfly is branch-free multiply-adds.
+struct QuadLane {
+    int t;          // lane in the quad
+    double s1, s2;  // -1 for the lanes that take (other - mine) in the t^1 / t^2 exchange
+    double qc, qs;  // exp(SIGN 2 pi i / 4) for lane 3 (SIGN +1: (0, 1)), 1 otherwise
+};
+template <int SIGN> __device__ __forceinline__ QuadLane quad_lane(int t) {
+    QuadLane L;
+    L.t = t;
+    L.s1 = (t & 1) ? -1.0 : 1.0;
+    L.s2 = (t >> 1) ? -1.0 : 1.0;
+    L.qc = t == 3 ? 0.0 : 1.0;
+    L.qs = t == 3 ? (double)SIGN : 0.0;
+    return L;
+}
+// mine * sign + other
+__device__ __forceinline__ double2 quad_bfly(double2 mine, double2 other, double sg) {
+    return make_double2(fma(sg, mine.x, other.x), fma(sg, mine.y, other.y));
+}
+__device__ __forceinline__ double2 cmul_d(double2 a, double c, double s) {
+    return make_double2(fma(a.x, c, -a.y * s), fma(a.x, s, a.y * c));
+}
+
+// Position of the lane's block in the output of quad_dft_dit (and in the input of
+// quad_dft_dif): lane t holds indices k + (N / 4) quad_block(t).
+__device__ __forceinline__ int quad_block(int t) { return (t >> 1) + 2 * (t & 1); }
+
+// Length-N DFT (exponent sign SIGN) of a line on a quad, decimation in time: lane t
+// holds x[4j + t] in v[j]; on return it holds X[k + (N / 4) quad_block(t)] in v[k].
+// With t = t0 + 2 t1 and y_t = w^(t k) E_t[k] (E_t the length-N/4 DFT of the lane's
+// values): the exchange across t1 forms B_t0(t1) = y_t0 + (-1)^t1 y_(t0+2), the one
+// across t0 forms X[k + (N/4)(t1 + 2 t0)] = B_0(t1) + (-1)^t0 w4^t1 B_1(t1).
+// tw[e] = exp(2 pi i e / N), e < N (conjugated for SIGN -1).
+template <int SIGN, int N>
+__device__ __forceinline__ void quad_dft_dit(double2 (&v)[N / 4], const QuadLane& L, const double2* tw) {
+    constexpr int Q = N / 4;
+    double2 E[Q];
+    dft_reg<double, SIGN, Q, 1>(v, E);
+    sfor<0, Q>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        double2 y = E[k];
+        if constexpr (k > 0) {
+            const double2 w = tw[(L.t * k) % N];
+            y = cmul_d(y, w.x, SIGN * w.y);
+        }
+        const double2 bq = cmul_d(quad_bfly(y, quad_swap<kSwap2>(y), L.s2), L.qc, L.qs);
+        v[k] = quad_bfly(bq, quad_swap<kSwap1>(bq), L.s1);
+    });
+}
+
+// Decimation in frequency: lane t holds x[n + (N / 4) quad_block(t)] in v[n]; on return
+// it holds X[4k + t] in v[k].  With s = quad_block(t) = s0 + 2 s1 (s0 = t >> 1,
+// s1 = t & 1): the exchange across s1 forms C_s0(s1) = x_s0 + (-1)^s1 x_(s0+2), the one
+// across s0 forms Z_t = C_0(s1) + (-1)^s0 w4^s1 C_1(s1), and lane t finishes with the
+// length-N/4 DFT of w^(t n) Z_t[n].
+template <int SIGN, int N>
+__device__ __forceinline__ void quad_dft_dif(double2 (&v)[N / 4], const QuadLane& L, const double2* tw) {
+    constexpr int Q = N / 4;
+    double2 a[Q];
+    sfor<0, Q>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        const double2 x = v[n];
+        const double2 c = cmul_d(quad_bfly(x, quad_swap<kSwap1>(x), L.s1), L.qc, L.qs);
+        double2 z = quad_bfly(c, quad_swap<kSwap2>(c), L.s2);
+        if constexpr (n > 0) {
+            const double2 w = tw[(L.t * n) % N];
+            z = cmul_d(z, w.x, SIGN * w.y);
+        }
+        a[n] = z;
+    });
+    dft_reg<double, SIGN, Q, 1>(a, v);
+}
+
+// Slab data elements (double2) of the lane-quad kernel: ZG = 64 / nl stick rows or
+// transpose planes, whichever is larger (they share LDS).
+__host__ __device__ inline int quad64_data_elems(const FftDims& d, int nl) {
+    const int zg = 64 / nl, axp = (2 * d.mxmax + 1) | 1;
+    const int a = zg * d.sld, b = zg * nl * axp;
+    return a > b ? a : b;
+}
+
+// Slab pass of H (V multiply), FP64, NX = NY = NL (a multiple of 4): the register slab
+// pass with every line on a lane quad.  A workgroup of 256 threads (64 quads) takes
+// ZG = 64 / NL consecutive z slabs of one row: stick rows to LDS; one quad per (slab,
+// non-empty column): inverse y DFT into the transpose plane [slab][iy][column]; one
+// quad per (slab, iy): inverse x DFT (decimation in time), times V(z, x, y), forward x
+// DFT (decimation in frequency, which takes the input in the order the inverse left
+// it), non-empty columns written back; one quad per (slab, column): forward y DFT into
+// the stick row; stick rows back.  Stick rows and transpose planes share LDS (every
+// quad holds its line in registers across the barrier between).
+template <int NL>
+__global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t, double2* __restrict__ sticks,
+                                                        const double* __restrict__ Vr) {
+    static_assert(NL % 4 == 0 && NL <= 64, "lines split over a lane quad");
+    constexpr int Q = NL / 4, H = NL / 2;
+    constexpr int ZG = 64 / NL;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* lds = reinterpret_cast<double2*>(smem);
+    const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
+    const int ax = 2 * mxmax + 1;
+    const int axp = ax | 1;
+    const int z0 = blockIdx.x * ZG, row = blockIdx.y;
+    const int tid = threadIdx.x, u = tid >> 2, tl = tid & 3;
+    const int blk = Q * quad_block(tl);
+    const int zl = u / NL, li = u - zl * NL;   // x passes: (slab, iy)
+    const int zc = u / ax, lc = u - zc * ax;   // y passes: (slab, column)
+    const int nzh = min(ZG, nz - z0);
+    const bool xact = zl < nzh;
+    const bool col = zc < nzh;
+    double2* g = sticks + ((long)row * nz + z0) * sld;
+    const int ns = d.ns;
+    // twiddles exp(2 pi i e / NL) behind the slab data
+    double2* tw = lds + quad64_data_elems(d, NL);
+    if (tid < NL) {
+        const double ang = 6.283185307179586476925 * tid / NL;
+        tw[tid] = make_double2(cos(ang), sin(ang));
+    }
+    for (int zz = 0; zz < nzh; ++zz)
+        for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+    __syncthreads();
+    const QuadLane Lp = quad_lane<+1>(tl), Lm = quad_lane<-1>(tl);
+
+    int s0 = 0, my0 = 0;
+    double2 v[Q];
+    if (col) {
+        s0 = t.col_start[lc];
+        my0 = t.col_my0[lc];
+        const double2* sr = lds + zc * sld + s0 - my0;
+        sfor<0, Q>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int iy = 4 * j + tl;
+            const int my = iy < H ? iy : iy - NL;
+            const double2 val = sr[min(max(my, my0), -my0)];
+            v[j] = (my >= my0 && my <= -my0) ? val : make_double2(0.0, 0.0);
+        });
+    }
+    __syncthreads();
+    double2* tp = lds + (long)zl * NL * axp;   // transpose plane of the x-pass slab: [iy][column]
+    double2* tc = lds + (long)zc * NL * axp;   // transpose plane of the y-pass slab
+    if (col) {
+        quad_dft_dit<+1, NL>(v, Lp, tw);
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            tc[(k + blk) * axp + lc] = v[k];
+        });
+    }
+    __syncthreads();
+    if (xact) {
+        const double2* tr = tp + li * axp + mxmax;
+        sfor<0, Q>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int ix = 4 * j + tl;
+            const int mx = ix < H ? ix : ix - NL;
+            const double2 val = tr[min(max(mx, -mxmax), mxmax)];
+            v[j] = (mx >= -mxmax && mx <= mxmax) ? val : make_double2(0.0, 0.0);
+        });
+        quad_dft_dit<+1, NL>(v, Lp, tw);
+        const double* vz = Vr + (long)(z0 + zl) * NL * NL + li;
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const double vv = vz[(k + blk) * NL];
+            v[k].x *= vv;
+            v[k].y *= vv;
+        });
+        quad_dft_dif<-1, NL>(v, Lm, tw);
+        double2* tw2 = tp + li * axp + mxmax;
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int ix = 4 * k + tl;
+            const int mx = ix < H ? ix : ix - NL;
+            if (mx >= -mxmax && mx <= mxmax) tw2[mx] = v[k];
+        });
+    }
+    __syncthreads();
+    if (col) {
+        sfor<0, Q>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            v[j] = tc[(4 * j + tl) * axp + lc];
+        });
+    }
+    __syncthreads();
+    if (col) {
+        quad_dft_dit<-1, NL>(v, Lm, tw);
+        double2* sw = lds + zc * sld + s0 - my0;
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int iy = k + blk;
+            const int my = iy < H ? iy : iy - NL;
+            if (my >= my0 && my <= -my0) sw[my] = v[k];
+        });
+    }
+    __syncthreads();
+    for (int zz = 0; zz < nzh; ++zz)
+        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+}
+
 constexpr int kMaxAcc = 24;
 
 // Density: dn_i(z, x, y) = scale * Re sum_v conj(u_v(z, x, y)) Inv(sticks[i * nv + v])(z, x, y).
@@ -1311,6 +1527,14 @@ size_t slab_reg_lds(const FftDims& d, int nl) {
     return bytes <= 65536 ? bytes : 0;
 }
 
+// LDS of the FP64 lane-quad slab kernel for line length nl (0 if it does not apply):
+// the slab data and nl twiddles.
+size_t slab_quad64_lds(const FftDims& d, int nl) {
+    if (d.nx != d.ny || d.nx != nl || nl % 4 != 0 || nl > 64 || 2 * d.mxmax + 1 > nl) return 0;
+    const size_t bytes = ((size_t)quad64_data_elems(d, nl) + nl) * sizeof(double2);
+    return bytes <= 65536 ? bytes : 0;
+}
+
 template <typename T>
 void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int nrows, const T* Vz, hipStream_t s) {
     const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
@@ -1321,6 +1545,24 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
     const double flops = (double)nrows * (lines_y * 5.0 * d.ny * std::log2((double)d.ny) +
                                           lines_x * 5.0 * d.nx * std::log2((double)d.nx) +
                                           2.0 * d.nx * d.ny * d.nz);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        bool done = false;
+        with_n(d.nx, [&]<int N>() {
+            if constexpr (N > 0 && N <= 64 && N % 4 == 0) {
+                const size_t lds = slab_quad64_lds(d, N);
+                if (lds > 0 && nrows > 0) {
+                    check_rows(nrows);
+                    constexpr int ZG = 64 / N;
+                    ProfScope prof_(K_SLAB_HV64, s, bytes, flops);
+                    const dim3 grid((d.nz + ZG - 1) / ZG, nrows);
+                    hipLaunchKernelGGL((k_slab_hv_quad64<N>), grid, dim3(256), lds, s, d, t, sticks, Vz);
+                    PDEP_HIP(hipGetLastError());
+                    done = true;
+                }
+            }
+        });
+        if (done || nrows <= 0) return;
+    }
     if constexpr (sizeof(T) == sizeof(float)) {
         bool done = false;
         with_n(d.nx, [&]<int N>() {
