@@ -1239,6 +1239,179 @@ __global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t
         for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
 }
 
+// Density on lane quads (FP64, NX = NY = NL): for ZG = 64 / NL slabs of perturbation
+// `pert`, loop over the nv stick rows of its bands: inverse y into the transpose plane,
+// inverse x (decimation in time: the lane holds x = k + (NL/4) quad_block(t) of line iy),
+// accumulate Re(conj(u_v) f) in registers; scaled sums written at the end.
+template <int NL>
+__global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTables t,
+                                                             const double2* __restrict__ sticks, int nv,
+                                                             const double2* __restrict__ u, double scale,
+                                                             double* __restrict__ dn) {
+    constexpr int Q = NL / 4, H = NL / 2;
+    constexpr int ZG = 64 / NL;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* lds = reinterpret_cast<double2*>(smem);
+    const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
+    const int ax = 2 * mxmax + 1;
+    const int axp = ax | 1;
+    const int z0 = blockIdx.x * ZG, pert = blockIdx.y;
+    const int tid = threadIdx.x, uq = tid >> 2, tl = tid & 3;
+    const int blk = Q * quad_block(tl);
+    const int zl = uq / NL, li = uq - zl * NL;   // x passes: (slab, iy)
+    const int zc = uq / ax, lc = uq - zc * ax;   // y passes: (slab, column)
+    const int nzh = min(ZG, nz - z0);
+    const bool xact = zl < nzh;
+    const bool col = zc < nzh;
+    const long ng = (long)NL * NL * nz;
+    const int ns = d.ns;
+    double2* tw = lds + quad64_data_elems(d, NL);
+    if (tid < NL) {
+        const double ang = 6.283185307179586476925 * tid / NL;
+        tw[tid] = make_double2(cos(ang), sin(ang));
+    }
+    const QuadLane Lp = quad_lane<+1>(tl);
+    const int s0 = col ? t.col_start[lc] : 0, my0 = col ? t.col_my0[lc] : 0;
+    double2* tp = lds + (long)zl * NL * axp;
+    double2* tc = lds + (long)zc * NL * axp;
+    double acc[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc[k] = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        const double2* g = sticks + (((long)pert * nv + v) * nz + z0) * sld;
+        __syncthreads();   // the previous band's transpose planes are read
+        for (int zz = 0; zz < nzh; ++zz)
+            for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+        __syncthreads();
+        double2 w[Q];
+        if (col) {
+            const double2* sr = lds + zc * sld + s0 - my0;
+            sfor<0, Q>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const int iy = 4 * j + tl;
+                const int my = iy < H ? iy : iy - NL;
+                const double2 val = sr[min(max(my, my0), -my0)];
+                w[j] = (my >= my0 && my <= -my0) ? val : make_double2(0.0, 0.0);
+            });
+        }
+        __syncthreads();
+        if (col) {
+            quad_dft_dit<+1, NL>(w, Lp, tw);
+            sfor<0, Q>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                tc[(k + blk) * axp + lc] = w[k];
+            });
+        }
+        __syncthreads();
+        if (xact) {
+            const double2* tr = tp + li * axp + mxmax;
+            sfor<0, Q>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const int ix = 4 * j + tl;
+                const int mx = ix < H ? ix : ix - NL;
+                const double2 val = tr[min(max(mx, -mxmax), mxmax)];
+                w[j] = (mx >= -mxmax && mx <= mxmax) ? val : make_double2(0.0, 0.0);
+            });
+            quad_dft_dit<+1, NL>(w, Lp, tw);
+            const double2* uz = u + (long)v * ng + (long)(z0 + zl) * NL * NL + li;
+            sfor<0, Q>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const double2 uu = uz[(k + blk) * NL];
+                acc[k] += uu.x * w[k].x + uu.y * w[k].y;
+            });
+        }
+    }
+    if (xact) {
+        double* out = dn + (long)pert * ng + (long)(z0 + zl) * NL * NL + li;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) out[(k + blk) * NL] = scale * acc[k];
+    }
+}
+
+// Forward slab pass on lane quads (FP64, NX = NY = NL): grid V_r[row / nv] u[row % nv]
+// (PRODUCT) or V_r[row] (real) -> forward x (decimation in frequency on the lane's
+// contiguous x block) into the transpose plane -> forward y (decimation in time) -> the
+// row's sticks.
+template <int NL, bool PRODUCT>
+__global__ __launch_bounds__(256) void k_slab_fwd_quad64(FftDims d, BasisTables t, double2* __restrict__ sticks,
+                                                         const double* __restrict__ Vr,
+                                                         const double2* __restrict__ u, int nv) {
+    constexpr int Q = NL / 4, H = NL / 2;
+    constexpr int ZG = 64 / NL;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* lds = reinterpret_cast<double2*>(smem);
+    const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
+    const int ax = 2 * mxmax + 1;
+    const int axp = ax | 1;
+    const int z0 = blockIdx.x * ZG, row = blockIdx.y;
+    const int tid = threadIdx.x, uq = tid >> 2, tl = tid & 3;
+    const int blk = Q * quad_block(tl);
+    const int zl = uq / NL, li = uq - zl * NL;
+    const int zc = uq / ax, lc = uq - zc * ax;
+    const int nzh = min(ZG, nz - z0);
+    const bool xact = zl < nzh;
+    const bool col = zc < nzh;
+    const long ng = (long)NL * NL * nz;
+    double2* tw = lds + quad64_data_elems(d, NL);
+    if (tid < NL) {
+        const double ang = 6.283185307179586476925 * tid / NL;
+        tw[tid] = make_double2(cos(ang), sin(ang));
+    }
+    __syncthreads();
+    const QuadLane Lm = quad_lane<-1>(tl);
+    double2 w[Q];
+    double2* tp = lds + (long)zl * NL * axp;
+    double2* tc = lds + (long)zc * NL * axp;
+    if (xact) {
+        const long zo = (long)(z0 + zl) * NL * NL + li;
+        const double* vz = Vr + (PRODUCT ? (long)(row / nv) : (long)row) * ng + zo;
+        sfor<0, Q>([&](auto nc) {
+            constexpr int n = decltype(nc)::value;
+            const double vv = vz[(n + blk) * NL];
+            if constexpr (PRODUCT) {
+                const double2 uu = u[(long)(row % nv) * ng + zo + (n + blk) * NL];
+                w[n] = make_double2(vv * uu.x, vv * uu.y);
+            } else {
+                w[n] = make_double2(vv, 0.0);
+            }
+        });
+        quad_dft_dif<-1, NL>(w, Lm, tw);
+        double2* tw2 = tp + li * axp + mxmax;
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int ix = 4 * k + tl;
+            const int mx = ix < H ? ix : ix - NL;
+            if (mx >= -mxmax && mx <= mxmax) tw2[mx] = w[k];
+        });
+    }
+    __syncthreads();
+    int s0 = 0, my0 = 0;
+    if (col) {
+        s0 = t.col_start[lc];
+        my0 = t.col_my0[lc];
+        sfor<0, Q>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            w[j] = tc[(4 * j + tl) * axp + lc];
+        });
+    }
+    __syncthreads();
+    if (col) {
+        quad_dft_dit<-1, NL>(w, Lm, tw);
+        double2* sw = lds + zc * sld + s0 - my0;
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int iy = k + blk;
+            const int my = iy < H ? iy : iy - NL;
+            if (my >= my0 && my <= -my0) sw[my] = w[k];
+        });
+    }
+    __syncthreads();
+    double2* g = sticks + ((long)row * nz + z0) * sld;
+    const int ns = d.ns;
+    for (int zz = 0; zz < nzh; ++zz)
+        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+}
+
 constexpr int kMaxAcc = 24;
 
 // Density: dn_i(z, x, y) = scale * Re sum_v conj(u_v(z, x, y)) Inv(sticks[i * nv + v])(z, x, y).
@@ -1607,6 +1780,32 @@ void launch_slab_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr
                              cplx<T>* sticks, hipStream_t s) {
     const double sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     const double g = (double)d.nx * d.ny * d.nz;
+    if constexpr (sizeof(T) == sizeof(double)) {
+        bool done = false;
+        with_n(d.nx, [&]<int N>() {
+            if constexpr (N > 0 && N <= 64 && N % 4 == 0) {
+                const size_t lds = slab_quad64_lds(d, N);
+                if (lds > 0 && nrows > 0) {
+                    check_rows(nrows);
+                    constexpr int ZG = 64 / N;
+                    const dim3 grid((d.nz + ZG - 1) / ZG, nrows);
+                    if (u) {
+                        ProfScope prof_(K_SLAB_FWD_PRODUCT, s,
+                                        (double)nrows * (sk + g * sizeof(cplx<T>)) + g * sizeof(T) * (nrows / nv));
+                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, true>), grid, dim3(256), lds, s, d, t, sticks, Vr,
+                                           u, nv);
+                    } else {
+                        ProfScope prof_(K_SLAB_FWD_PRODUCT, s, (double)nrows * (sk + g * sizeof(T)));
+                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, false>), grid, dim3(256), lds, s, d, t, sticks,
+                                           Vr, nullptr, 1);
+                    }
+                    PDEP_HIP(hipGetLastError());
+                    done = true;
+                }
+            }
+        });
+        if (done || nrows <= 0) return;
+    }
     if (u)
         launch_slab<T, SLAB_FWD_PRODUCT>(d, t, nrows, sticks, Vr, u, nv, nullptr, nullptr, s, K_SLAB_FWD_PRODUCT,
                                          (double)nrows * (sk + g * sizeof(cplx<T>)) + g * sizeof(T) * (nrows / nv));
@@ -1624,6 +1823,22 @@ void launch_slab_density(const FftDims& d, const BasisTables& t, const double2* 
     const double g = (double)d.nx * d.ny * d.nz;
     ProfScope prof_(K_SLAB_DENSITY, s,
                     (double)npert * nv * ((double)d.nz * d.ns * 16.0 + g * 16.0) + (double)npert * g * 8.0);
+    bool done = false;
+    with_n(d.nx, [&]<int N>() {
+        if constexpr (N > 0 && N <= 64 && N % 4 == 0) {
+            const size_t lds = slab_quad64_lds(d, N);
+            if (lds > 0) {
+                constexpr int ZG = 64 / N;
+                hipLaunchKernelGGL((k_slab_density_quad64<N>), dim3((d.nz + ZG - 1) / ZG, npert), dim3(256), lds, s,
+                                   d, t, sticks, nv, u, scale, dn);
+                done = true;
+            }
+        }
+    });
+    if (done) {
+        PDEP_HIP(hipGetLastError());
+        return;
+    }
     with_nxy(d.nx, d.ny, [&]<int N>() {
         hipLaunchKernelGGL((k_slab_density<N, N>), dim3(d.nz, npert), dim3(kThreads), slab_lds<double>(d), s, d, t,
                            sticks, nv, u, scale, dn);
