@@ -266,3 +266,27 @@ def test_fine_grid_runtime_radius_parity(mode):
     print("fine grid", st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("grid,cell,ecut", [((24, 24, 24), (10.0, 10.0, 10.0), 5.0),
+                                            ((64, 64, 16), (12.0, 12.0, 3.0), 4.0)])
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_lane_quad_grids_parity(grid, cell, ecut, mode):
+    """The FP64 slab, density and forward passes with lines on lane quads at the line
+    lengths the medium tests do not reach: 24 (two slabs per workgroup) and 64 (one slab,
+    a 16-point z axis), in the FP64 mode and as the refinement of the BF16x3 mode."""
+    from paper_1501_03141_amd import pdep
+    Wg = inputs.Workload("quad_grid", cell, grid, ecut, 2, 4, 6, 1e-10, 1513)
+    V = inputs.vloc(Wg)
+    m = R.make_model(Wg.L, Wg.n, Wg.ecut, V, naive=False)
+    gs = R.ground_state(m, Wg.n_v, full=True)
+    phi = inputs.trial_block(m.miller[m.nz], 5, 217)
+    want = R.chi0bar_apply(m, gs, phi)
+    prec = pdep.PDEP_FP64 if mode == "fp64" else pdep.PDEP_MIXED_BF16X3
+    with pdep.Context(Wg.L, Wg.n, Wg.ecut, V, Wg.n_v, precision=prec, cg_tol=1e-10, psi=gs.C,
+                      eps=gs.eps) as c:
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print(grid, mode, "npw", m.miller.shape[0], st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)
