@@ -23,6 +23,8 @@
 // with A = P_c (H - e_v) applied as stick pass -> slab pass (V_loc) -> stick pass with
 // the kinetic/shift epilogue -> P_c GEMM pair, and K the diagonal kinetic preconditioner
 // 1/max(1, 1/2|G|^2 - e_v) (the paper does not fix K; it only changes iteration counts).
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -76,6 +78,30 @@ size_t coef_bytes(int nv, int nrows) { return (size_t)nrows * coef_ld(nv) * size
 // copies psi32w / psi64w), and the update touches the half sphere only.  S: work space
 // of coef_bytes(nv, nrows).  In the BF16x3 mode the FP32 pair runs on the bf16 matrix
 // cores (three products, real coefficients).
+namespace {
+
+// out[i] = Re in[i]
+__global__ void k_real_parts(long n, const double2* __restrict__ in, double* __restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i].x;
+}
+
+// The context's rocBLAS handle (created on first use), bound to the context stream.
+rocblas_handle ctx_blas(Ctx& c) {
+    if (!c.blas) {
+        rocblas_handle nh = nullptr;
+        PDEP_REQUIRE(rocblas_create_handle(&nh) == rocblas_status_success, PDEP_EDEVICE,
+                     "rocblas_create_handle failed");
+        c.blas = nh;
+        c.own_blas = true;
+    }
+    rocblas_handle h = static_cast<rocblas_handle>(c.blas);
+    rocblas_set_stream(h, c.stream);
+    return h;
+}
+
+}  // namespace
+
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv, nh = half_len(npw);
@@ -84,9 +110,28 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
     cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
     if constexpr (sizeof(T) == sizeof(double)) {
+        // Real coefficients over half spheres.  S = Re(Psi_w^H Y) by the split-K MFMA GEMM
+        // (real parts written as complex with zero imaginary parts); with the rows read as
+        // real vectors of 2 nh doubles, Y -= S Psi is a plain DGEMM (rocBLAS, column-major
+        // views of the row-major arrays).
+        if (nrows <= 0) return;
         launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
                            true);
-        launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), npw, St, lds, -1.0, 1.0, Y, ld, c.stream, true);
+        // the real parts, contiguous, in the split-K buffer (free once the GEMM is done)
+        PDEP_REQUIRE((size_t)nrows * lds <= 2 * split_elems, PDEP_EINVAL, "project_c: too many rows");
+        double* Sr = reinterpret_cast<double*>(work);
+        const long ne = (long)nrows * lds;
+        rocblas_handle h = ctx_blas(c);
+        const double one = 1.0, mone = -1.0;
+        ProfScope prof_(K_GEMM_UPDATE64, c.stream, 16.0 * nv * nh + 32.0 * nrows * nh + 24.0 * nv * nrows,
+                        4.0 * nv * (double)nrows * nh);
+        hipLaunchKernelGGL(k_real_parts, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c.stream, ne,
+                           reinterpret_cast<const double2*>(St), Sr);
+        PDEP_HIP(hipGetLastError());
+        PDEP_REQUIRE(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, 2 * nh, nrows, nv, &mone,
+                                   reinterpret_cast<const double*>(c.psi64.get()), 2 * npw, Sr, lds, &one,
+                                   reinterpret_cast<double*>(Y), 2 * ld) == rocblas_status_success,
+                     PDEP_EDEVICE, "rocblas_dgemm (projection update) failed");
     } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
