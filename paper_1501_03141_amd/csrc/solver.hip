@@ -117,21 +117,26 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
         if (nrows <= 0) return;
         launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
                            true);
-        // the real parts, contiguous, in the split-K buffer (free once the GEMM is done)
-        PDEP_REQUIRE((size_t)nrows * lds <= 2 * split_elems, PDEP_EINVAL, "project_c: too many rows");
+        // the real parts, contiguous, in the split-K buffer (free once the GEMM is done),
+        // in blocks of rows that fit it
         double* Sr = reinterpret_cast<double*>(work);
-        const long ne = (long)nrows * lds;
+        const int rblk = (int)std::min<long>(nrows, (long)(2 * split_elems) / lds);
         rocblas_handle h = ctx_blas(c);
         const double one = 1.0, mone = -1.0;
         ProfScope prof_(K_GEMM_UPDATE64, c.stream, 16.0 * nv * nh + 32.0 * nrows * nh + 24.0 * nv * nrows,
                         4.0 * nv * (double)nrows * nh);
-        hipLaunchKernelGGL(k_real_parts, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c.stream, ne,
-                           reinterpret_cast<const double2*>(St), Sr);
-        PDEP_HIP(hipGetLastError());
-        PDEP_REQUIRE(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, 2 * nh, nrows, nv, &mone,
-                                   reinterpret_cast<const double*>(c.psi64.get()), 2 * npw, Sr, lds, &one,
-                                   reinterpret_cast<double*>(Y), 2 * ld) == rocblas_status_success,
-                     PDEP_EDEVICE, "rocblas_dgemm (projection update) failed");
+        for (int r0 = 0; r0 < nrows; r0 += rblk) {
+            const int nr = std::min(rblk, nrows - r0);
+            const long ne = (long)nr * lds;
+            hipLaunchKernelGGL(k_real_parts, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c.stream, ne,
+                               reinterpret_cast<const double2*>(St + (long)r0 * lds), Sr);
+            PDEP_HIP(hipGetLastError());
+            PDEP_REQUIRE(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, 2 * nh, nr, nv, &mone,
+                                       reinterpret_cast<const double*>(c.psi64.get()), 2 * npw, Sr, lds, &one,
+                                       reinterpret_cast<double*>(Y + (long)r0 * ld), 2 * ld) ==
+                             rocblas_status_success,
+                         PDEP_EDEVICE, "rocblas_dgemm (projection update) failed");
+        }
     } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
