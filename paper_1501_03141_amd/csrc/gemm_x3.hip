@@ -313,6 +313,35 @@ __global__ void k_splitk_reduce_real(int M, int N, long lds, int splits, const f
     S[n * lds + m] = v;
 }
 
+// The fused CG step's reductions in one launch: threads e < N M reduce the split-K partial
+// products as k_splitk_reduce_real (when splits > 1); the next N threads form, for the
+// active rows, rz_new = sum of the <r, K r> parts, rr = sum of the ||r||^2 parts (parts
+// in order) and beta = rz_new / rz_old (0 when rz_old = 0).
+__global__ void k_reduce_step(int M, int N, long lds, int splits, const float* __restrict__ P, float* __restrict__ S,
+                              CgStepFuse cs) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nm = splits > 1 ? (long)N * M : 0;
+    if (e < nm) {
+        const long n = e / M, m = e - n * M;
+        const long stride = (long)N * lds;
+        float v = 0.f;
+        for (int z = 0; z < splits; ++z) v += P[z * stride + n * lds + m];
+        S[n * lds + m] = v;
+        return;
+    }
+    const long row = e - nm;
+    if (row >= N || !cs.active[row]) return;
+    double a = 0.0, b = 0.0;
+    for (int g = 0; g < splits; ++g) {
+        a += cs.rz_part[row * splits + g];
+        b += cs.rr_part[row * splits + g];
+    }
+    cs.rz_new[row] = a;
+    cs.rr[row] = b;
+    const double d = cs.rz[row];
+    cs.beta[row] = (float)(d != 0.0 ? a / d : 0.0);
+}
+
 // Eight consecutive floats p[0..7] (16-byte aligned); entries at or beyond `avail` read as zero.
 __device__ __forceinline__ void load8f(const float* p, int avail, float (&v)[8]) {
     if (avail >= 8) {
@@ -638,7 +667,14 @@ int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B,
         launch(std::false_type{});
     }
     PDEP_HIP(hipGetLastError());
-    if (splits > 1) {
+    if (cs) {
+        if constexpr (REAL) {
+            const long tot = (splits > 1 ? (long)N * M : 0) + N;
+            hipLaunchKernelGGL(k_reduce_step, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds, splits,
+                               static_cast<const float*>(work), static_cast<float*>(S), *cs);
+            PDEP_HIP(hipGetLastError());
+        }
+    } else if (splits > 1) {
         if constexpr (REAL) {
             const long tot = (long)N * M;
             hipLaunchKernelGGL(k_splitk_reduce_real, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, N, lds,

@@ -681,15 +681,6 @@ void launch_cg_step1(int nrows, int K, cplx<T>* x, cplx<T>* r, cplx<T>* z, const
     }
 }
 
-void launch_sum_parts(int nrows, int nparts, const double* rz_part, const double* rr_part, const int* active,
-                      double* rz, double* rr, const double* rz_old, float* beta, hipStream_t s) {
-    if (nrows <= 0) return;
-    ProfScope prof_(K_CG_UPDATE, s, 2.0 * nrows * (double)nparts * sizeof(double));
-    hipLaunchKernelGGL(k_sum_parts, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, nparts, rz_part, rr_part,
-                       active, rz, rr, rz_old, beta);
-    PDEP_HIP(hipGetLastError());
-}
-
 template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new, double* rz,
                      const int* active, hipStream_t s) {

@@ -234,17 +234,17 @@ struct CgStepFuse {
     float* alpha_out = nullptr;    // alpha = <r, K r> / <p, q> of the active rows
     double* rz_part = nullptr;     // [row][part] partial sums of the new <r, K r> ...
     double* rr_part = nullptr;     // ... and of the new ||r||^2 (half-sphere weights)
+    double* rz_new = nullptr;      // the sums: new <r, K r> ...
+    double* rr = nullptr;          // ... new ||r||^2 ...
+    float* beta = nullptr;         // ... and beta = new <r, K r> / rz (active rows)
 };
 // launch_gemm_ahb_x3_real (with the preconditioner) on r after the step: for the active
-// rows r <- r - alpha q, written back in place, with <r, K r> and ||r||^2 of the new r as
-// partial sums (M <= 128).  Returns the number of parts per row (<= max_parts).
+// rows r <- r - alpha q, written back in place, and <r, K r>, ||r||^2 of the new r and
+// the CG factor beta (M <= 128).  Returns the number of partial sums per row
+// (<= max_parts).
 int launch_gemm_ahb_x3_step(int M, int N, int K, const float2* A, long lda, float2* r, long ldr, float* S, long lds,
                             float* work, size_t work_elems, hipStream_t s, const float* kin, const double* shift,
                             double kfloor, const CgStepFuse& cs, int max_parts);
-// rz[row] = sum_g rz_part[row][g], rr[row] likewise, beta[row] = rz[row] / rz_old[row]
-// for the active rows (nparts parts per row, summed in order)
-void launch_sum_parts(int nrows, int nparts, const double* rz_part, const double* rr_part, const int* active,
-                      double* rz, double* rr, const double* rz_old, float* beta, hipStream_t s);
 // CG direction update with the projected preconditioned residual formed in the GEMM:
 // for active rows n, x[xrow[n]] += alpha[n] p[n] (the old p; xrow null: row n) and
 // p[n] <- K r[n] - sum_m S[n][m] A[m] + beta[n] p[n], where S = Re(A^H K r) comes from

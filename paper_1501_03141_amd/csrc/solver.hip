@@ -497,10 +497,11 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                         cs.alpha_out = alpha;
                         cs.rz_part = rz_part;
                         cs.rr_part = rr_part;
-                        const int nparts = launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld,
-                                                                   Sr, lds, wr, (size_t)16 << 20, s, kin, sh,
-                                                                   kPrecondFloor, cs, nblk);
-                        launch_sum_parts(ncur, nparts, rz_part, rr_part, sc.active, sc.rz_new, sc.rr, rz, beta, s);
+                        cs.rz_new = sc.rz_new;
+                        cs.rr = sc.rr;
+                        cs.beta = beta;
+                        launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
+                                                (size_t)16 << 20, s, kin, sh, kPrecondFloor, cs, nblk);
                     } else {
                         launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active,
                                            kin, sh, ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta,
