@@ -114,10 +114,10 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 // writes it back to B (each entry of B is staged by exactly one workgroup), and adds its
 // half-sphere weighted |r|^2 and K |r|^2 in FP64; the four lanes of a row combine them
 // and the workgroup's sums go to rz_part / rr_part [n][blockIdx.z].  Inactive rows are
-// left as they are.
+// left as they are.  (B is then written through, so it is not declared restrict.)
 template <int WM, int CT, bool REAL, bool STEP>
 __global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
-                                                     const float2* __restrict__ B, long ldb, void* __restrict__ Sv,
+                                                     const float2* B, long ldb, void* __restrict__ Sv,
                                                      long lds, int kchunk, int real_out, const float* __restrict__ kin,
                                                      const double* __restrict__ shift, float kfloor,
                                                      CgStepFuse cs) {
