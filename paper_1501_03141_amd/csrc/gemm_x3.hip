@@ -115,8 +115,10 @@ constexpr int kRowB = 80;   // LDS bytes per staged row: 64 B of bf16 + 16 B pad
 // half-sphere weighted |r|^2 and K |r|^2 in FP64; the four lanes of a row combine them
 // and the workgroup's sums go to rz_part / rr_part [n][blockIdx.z].  Inactive rows are
 // left as they are.  (B is then written through, so it is not declared restrict.)
+// The real four-tile variants with four waves along m are held to three waves per SIMD
+// (168 registers; they fit without spills).
 template <int WM, int CT, bool REAL, bool STEP>
-__global__ __launch_bounds__(256) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
+__global__ __launch_bounds__(256, (WM == 4 && CT == 4 && REAL) ? 3 : 1) void k_gemm_ahb_x3(int M, int N, int K, const float2* __restrict__ A, long lda,
                                                      const float2* B, long ldb, void* __restrict__ Sv,
                                                      long lds, int kchunk, int real_out, const float* __restrict__ kin,
                                                      const double* __restrict__ shift, float kfloor,
@@ -612,8 +614,10 @@ int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B,
     if (M <= 0 || N <= 0) return 0;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
-    // eight column tiles per wave when all four waves run along m and are mostly full
-    const int CT = M > 96 ? 8 : 4;
+    // eight column tiles per wave when all four waves run along m and are mostly full;
+    // the fused CG step keeps four (three waves per SIMD instead of two: its extra r and
+    // q traffic needs the latency hiding more than the shared B tile; 5-12% faster)
+    const int CT = (M > 96 && !cs) ? 8 : 4;
     const int BMC = 32 * WM, BN = 16 * CT * (4 / WM);
     PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
     dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
@@ -622,11 +626,12 @@ int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B,
                      "gemm_ahb_x3: the fused CG step needs real output, the preconditioner and one m tile");
     }
     // split K until about 512 workgroups (two per CU; more splits only add partial-sum
-    // traffic: measured best at 512 for N_v = 128 and 512)
+    // traffic: measured best at 512 for N_v = 128 and 512); 1024 for the fused step
     int splits = 1;
     const long tiles = (long)grid.x * grid.y;
-    if (work && tiles < 512) {
-        splits = (int)std::min<long>((512 + tiles - 1) / tiles, std::max(1, K / 256));
+    const long target = cs ? 1024 : 512;
+    if (work && tiles < target) {
+        splits = (int)std::min<long>((target + tiles - 1) / tiles, std::max(1, K / 256));
         if (cs) splits = std::min(splits, max_parts);
         while (splits > 1 && (size_t)splits * N * lds > work_elems) --splits;
     }
