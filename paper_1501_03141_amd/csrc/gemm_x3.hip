@@ -318,10 +318,11 @@ __global__ void k_splitk_reduce_real(int M, int N, long lds, int splits, const f
 // The fused CG step's reductions in one launch: threads e < N M reduce the split-K partial
 // products as k_splitk_reduce_real (when splits > 1); the next N threads form, for the
 // active rows, rz_new = sum of the <r, K r> parts, rr = sum of the ||r||^2 parts (parts
-// in order) and beta = rz_new / rz_old (0 when rz_old = 0).
+// in order) and beta = rz_new / rz_old (0 when rz_old = 0); thread 0 clears cs.count.
 __global__ void k_reduce_step(int M, int N, long lds, int splits, const float* __restrict__ P, float* __restrict__ S,
                               CgStepFuse cs) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0 && cs.count) *cs.count = 0;
     const long nm = splits > 1 ? (long)N * M : 0;
     if (e < nm) {
         const long n = e / M, m = e - n * M;

@@ -237,6 +237,7 @@ struct CgStepFuse {
     double* rz_new = nullptr;      // the sums: new <r, K r> ...
     double* rr = nullptr;          // ... new ||r||^2 ...
     float* beta = nullptr;         // ... and beta = new <r, K r> / rz (active rows)
+    int* count = nullptr;          // set to zero (the active-row counter of this iteration)
 };
 // launch_gemm_ahb_x3_real (with the preconditioner) on r after the step: for the active
 // rows r <- r - alpha q, written back in place, and <r, K r>, ||r||^2 of the new r and

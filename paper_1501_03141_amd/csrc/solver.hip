@@ -500,6 +500,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                         cs.rz_new = sc.rz_new;
                         cs.rr = sc.rr;
                         cs.beta = beta;
+                        cs.count = sc.n_active;   // cleared here for the check below
                         launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
                                                 (size_t)16 << 20, s, kin, sh, kPrecondFloor, cs, nblk);
                     } else {
@@ -529,7 +530,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 launch_row_dots<T>(ncur, npw, r, ld, z, ld, sc.rz_new, sc.rr, s, half);
             }
             if (!(pre && fused)) launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
-            launch_fill_zero(sc.n_active, sizeof(int), s);
+            if (!(pre && fused && nv <= 128)) launch_fill_zero(sc.n_active, sizeof(int), s);
             launch_cg_check(ncur, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], rz, sc.rz_new, sc.n_active, 1,
                             s);
         }
