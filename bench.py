@@ -209,7 +209,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path would shard by "
-              "perturbation across GPUs, which this build does not run.", file=sys.stderr)
+              "perturbation across GPUs, which this benchmark does not run.", file=sys.stderr)
         sys.exit(2)
 
     import torch
