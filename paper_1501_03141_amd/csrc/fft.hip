@@ -1240,13 +1240,15 @@ __global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t
         for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
 }
 
-// Density on lane quads (FP64, NX = NY = NL): for ZG = 64 / NL slabs of perturbation
-// `pert`, loop over the nv stick rows of its bands: inverse y into the transpose plane,
-// inverse x (decimation in time: the lane holds x = k + (NL/4) quad_block(t) of line iy),
-// accumulate Re(conj(u_v) f) in registers; scaled sums written at the end.
-template <int NL>
+// Density on lane quads (FP64, NX = NY = NL): for ZG = 64 / NL slabs of PB consecutive
+// perturbations, loop over the nv stick rows of their bands: inverse y into the transpose
+// plane, inverse x (decimation in time: the lane holds x = k + (NL/4) quad_block(t) of
+// line iy), accumulate Re(conj(u_v) f) in registers; scaled sums written at the end.
+// The perturbations of a workgroup share each u_v (read once from memory, then from
+// cache).
+template <int NL, int PB>
 __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTables t,
-                                                             const double2* __restrict__ sticks, int nv,
+                                                             const double2* __restrict__ sticks, int npert, int nv,
                                                              const double2* __restrict__ u, double scale,
                                                              double* __restrict__ dn) {
     constexpr int Q = NL / 4, H = NL / 2;
@@ -1256,7 +1258,8 @@ __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTab
     const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
     const int ax = 2 * mxmax + 1;
     const int axp = ax | 1;
-    const int z0 = blockIdx.x * ZG, pert = blockIdx.y;
+    const int z0 = blockIdx.x * ZG, p0 = blockIdx.y * PB;
+    const int np = min(PB, npert - p0);
     const int tid = threadIdx.x, uq = tid >> 2, tl = tid & 3;
     const int blk = Q * quad_block(tl);
     const int zl = uq / NL, li = uq - zl * NL;   // x passes: (slab, iy)
@@ -1275,57 +1278,67 @@ __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTab
     const int s0 = col ? t.col_start[lc] : 0, my0 = col ? t.col_my0[lc] : 0;
     double2* tp = lds + (long)zl * NL * axp;
     double2* tc = lds + (long)zc * NL * axp;
-    double acc[Q];
+    double acc[PB][Q];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) acc[k] = 0.0;
+    for (int q = 0; q < PB; ++q)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc[q][k] = 0.0;
     for (int v = 0; v < nv; ++v) {
-        const double2* g = sticks + (((long)pert * nv + v) * nz + z0) * sld;
-        __syncthreads();   // the previous band's transpose planes are read
-        for (int zz = 0; zz < nzh; ++zz)
-            for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
-        __syncthreads();
-        double2 w[Q];
-        if (col) {
-            const double2* sr = lds + zc * sld + s0 - my0;
-            sfor<0, Q>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                const int iy = 4 * j + tl;
-                const int my = iy < H ? iy : iy - NL;
-                const double2 val = sr[min(max(my, my0), -my0)];
-                w[j] = (my >= my0 && my <= -my0) ? val : make_double2(0.0, 0.0);
-            });
-        }
-        __syncthreads();
-        if (col) {
-            quad_dft_dit<+1, NL>(w, Lp, tw);
-            sfor<0, Q>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                tc[(k + blk) * axp + lc] = w[k];
-            });
-        }
-        __syncthreads();
-        if (xact) {
-            const double2* tr = tp + li * axp + mxmax;
-            sfor<0, Q>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                const int ix = 4 * j + tl;
-                const int mx = ix < H ? ix : ix - NL;
-                const double2 val = tr[min(max(mx, -mxmax), mxmax)];
-                w[j] = (mx >= -mxmax && mx <= mxmax) ? val : make_double2(0.0, 0.0);
-            });
-            quad_dft_dit<+1, NL>(w, Lp, tw);
-            const double2* uz = u + (long)v * ng + (long)(z0 + zl) * NL * NL + li;
-            sfor<0, Q>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                const double2 uu = uz[(k + blk) * NL];
-                acc[k] += uu.x * w[k].x + uu.y * w[k].y;
-            });
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            if (q >= np) break;   // uniform over the workgroup
+            const double2* g = sticks + (((long)(p0 + q) * nv + v) * nz + z0) * sld;
+            __syncthreads();   // the previous row's transpose planes are read
+            for (int zz = 0; zz < nzh; ++zz)
+                for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+            __syncthreads();
+            double2 w[Q];
+            if (col) {
+                const double2* sr = lds + zc * sld + s0 - my0;
+                sfor<0, Q>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const int iy = 4 * j + tl;
+                    const int my = iy < H ? iy : iy - NL;
+                    const double2 val = sr[min(max(my, my0), -my0)];
+                    w[j] = (my >= my0 && my <= -my0) ? val : make_double2(0.0, 0.0);
+                });
+            }
+            __syncthreads();
+            if (col) {
+                quad_dft_dit<+1, NL>(w, Lp, tw);
+                sfor<0, Q>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    tc[(k + blk) * axp + lc] = w[k];
+                });
+            }
+            __syncthreads();
+            if (xact) {
+                const double2* tr = tp + li * axp + mxmax;
+                sfor<0, Q>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const int ix = 4 * j + tl;
+                    const int mx = ix < H ? ix : ix - NL;
+                    const double2 val = tr[min(max(mx, -mxmax), mxmax)];
+                    w[j] = (mx >= -mxmax && mx <= mxmax) ? val : make_double2(0.0, 0.0);
+                });
+                quad_dft_dit<+1, NL>(w, Lp, tw);
+                const double2* uz = u + (long)v * ng + (long)(z0 + zl) * NL * NL + li;
+                sfor<0, Q>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    const double2 uu = uz[(k + blk) * NL];
+                    acc[q][k] += uu.x * w[k].x + uu.y * w[k].y;
+                });
+            }
         }
     }
     if (xact) {
-        double* out = dn + (long)pert * ng + (long)(z0 + zl) * NL * NL + li;
 #pragma unroll
-        for (int k = 0; k < Q; ++k) out[(k + blk) * NL] = scale * acc[k];
+        for (int q = 0; q < PB; ++q) {
+            if (q >= np) break;
+            double* out = dn + (long)(p0 + q) * ng + (long)(z0 + zl) * NL * NL + li;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) out[(k + blk) * NL] = scale * acc[q][k];
+        }
     }
 }
 
@@ -1834,9 +1847,9 @@ void launch_slab_density(const FftDims& d, const BasisTables& t, const double2* 
         if constexpr (N > 0 && N <= 64 && N % 4 == 0) {
             const size_t lds = slab_quad64_lds(d, N);
             if (lds > 0) {
-                constexpr int ZG = 64 / N;
-                hipLaunchKernelGGL((k_slab_density_quad64<N>), dim3((d.nz + ZG - 1) / ZG, npert), dim3(256), lds, s,
-                                   d, t, sticks, nv, u, scale, dn);
+                constexpr int ZG = 64 / N, PB = 2;
+                hipLaunchKernelGGL((k_slab_density_quad64<N, PB>), dim3((d.nz + ZG - 1) / ZG, (npert + PB - 1) / PB),
+                                   dim3(256), lds, s, d, t, sticks, npert, nv, u, scale, dn);
                 done = true;
             }
         }
