@@ -449,14 +449,17 @@ __global__ void k_cg_step2(int K, cplx<T>* __restrict__ p, const cplx<T>* __rest
 
 __global__ void k_cg_check(int nrows, const double* __restrict__ rr, const double* __restrict__ thr2,
                            int* __restrict__ active, int* __restrict__ iters, double* __restrict__ rz,
-                           const double* __restrict__ rz_new, int* __restrict__ n_active, int count_iter) {
+                           const double* __restrict__ rz_new, int* __restrict__ n_active, int count_iter,
+                           double rr_max) {
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= nrows) return;
     if (active[row]) {
         if (count_iter) iters[row] += 1;
         if (rz_new) rz[row] = rz_new[row];
-        const int still = rr[row] > thr2[row];
+        const bool diverged = rr_max > 0.0 && !(rr[row] <= rr_max);
+        const int still = !diverged && rr[row] > thr2[row];
         active[row] = still;
+        if (diverged) iters[row] = -iters[row] - 1;   // reported as -(iterations) - 1
         if (still) atomicAdd(n_active, 1);
     }
 }
@@ -480,6 +483,7 @@ __global__ void k_axpy_rows(int K, const cplx<T>* __restrict__ d, long ldd, cons
     const int row = blockIdx.y;
     if (k >= K) return;
     const double s = rowscale[row];
+    if (s == 0.0) return;   // a dropped solution (it may hold non-finite values)
     const cplx<T> v = d[(long)row * ldd + k];
     const long xr = rows ? rows[row] : row;
     double2 xv = x[xr * ldx + k];
@@ -691,11 +695,11 @@ void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, co
 }
 
 void launch_cg_check(int nrows, const double* rr, const double* thr2, int* active, int* iters, double* rz,
-                     const double* rz_new, int* n_active, int count_iter, hipStream_t s) {
+                     const double* rz_new, int* n_active, int count_iter, hipStream_t s, double rr_max) {
     if (nrows <= 0) return;
     ProfScope prof_(K_CG_UPDATE, s);
     hipLaunchKernelGGL(k_cg_check, dim3((nrows + 255) / 256), dim3(256), 0, s, nrows, rr, thr2, active, iters, rz,
-                       rz_new, n_active, count_iter);
+                       rz_new, n_active, count_iter, rr_max);
     PDEP_HIP(hipGetLastError());
 }
 

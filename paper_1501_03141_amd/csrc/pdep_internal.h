@@ -283,14 +283,16 @@ template <typename T>
 void launch_cg_step2(int nrows, int K, cplx<T>* p, const cplx<T>* z, long ld, const double* rz_new,
                      double* rz, const int* active, hipStream_t s);
 // active[r] &= rr[r] > thr2[r]; iters[r] += count_iter for rows active on entry; rz <- rz_new;
-// n_active += number of rows still active.
+// n_active += number of rows still active.  rr_max > 0: a row whose rr exceeds it (or is
+// not a number) stops as diverged, its iteration count stored as -(count) - 1.
 void launch_cg_check(int nrows, const double* rr, const double* thr2, int* active, int* iters,
-                     double* rz, const double* rz_new, int* n_active, int count_iter, hipStream_t s);
+                     double* rz, const double* rz_new, int* n_active, int count_iter, hipStream_t s,
+                     double rr_max = 0.0);
 // out[r] = rowscale[r] * in[rows[r]] with precision conversion (rows, rowscale may be null)
 template <typename Tin, typename Tout>
 void launch_convert_rows(int nrows, int K, const cplx<Tin>* in, long ldi, const int* rows,
                          const double* rowscale, cplx<Tout>* out, long ldo, hipStream_t s);
-// x[rows[r]] += rowscale[r] * d[r]
+// x[rows[r]] += rowscale[r] * d[r] (rows with rowscale 0 are left untouched)
 template <typename T>
 void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* rows,
                       const double* rowscale, double2* x, long ldx, hipStream_t s);
@@ -366,6 +368,9 @@ struct Ctx {
     // solver work space (grown on demand)
     void* blas = nullptr;                 // rocblas_handle for rocSOLVER calls
     bool own_blas = false;
+    // the inner FP32 solves of the mixed mode use the BF16x3 projection products (set per
+    // refinement step: rows that diverge with them are solved again with FP32 products)
+    bool pc_x3 = false;
     Buf w[WS_COUNT];
     void* ws(int i, size_t bytes) { w[i].ensure(&al, bytes); return w[i].get(); }
     // rows per launch of the transform chain for FP32 / FP64 rows (0: not tuned yet)

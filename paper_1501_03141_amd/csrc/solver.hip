@@ -140,7 +140,7 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
-        if (c.opts.precision == PDEP_MIXED_BF16X3) {
+        if (c.pc_x3) {
             float* Sr = reinterpret_cast<float*>(S);
             float* wr = reinterpret_cast<float*>(work);
             launch_gemm_ahb_x3_real(nv, nrows, nh, pw, lp, Y, ld, Sr, lds, wr, 2 * split_elems, c.stream);
@@ -393,7 +393,10 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     double* rr_part = rz_part + (size_t)n * nblk;
     const T* kin = kin_of<T>(c);
     // BF16x3 with the preconditioner: fused direction update (no z pass)
-    const bool fused = pre && sizeof(T) == sizeof(float) && c.opts.precision == PDEP_MIXED_BF16X3;
+    const bool fused = pre && sizeof(T) == sizeof(float) && c.pc_x3;
+    // BF16x3 products: a row whose residual grows 100-fold (or is not a number) has
+    // diverged and stops; the refinement solves it again with FP32 products
+    const double rr_max = (sizeof(T) == sizeof(float) && c.pc_x3) ? 1e4 : 0.0;
     int ncur = n;
 
     hipLaunchKernelGGL(k_iota_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, sc.shift, sc.thr2, sc.s_shift[0],
@@ -532,7 +535,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             if (!(pre && fused)) launch_cg_step2<T>(ncur, npw, p, z, ld, sc.rz_new, rz, sc.active, s);
             if (!(pre && fused && nv <= 128)) launch_fill_zero(sc.n_active, sizeof(int), s);
             launch_cg_check(ncur, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], rz, sc.rz_new, sc.n_active, 1,
-                            s);
+                            s, rr_max);
         }
         it += nstep;
         PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -590,6 +593,8 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     rr = bb;
     std::vector<int> it_row(n, 0);
     std::vector<int> rows;
+    // BF16x3 projection products in the inner solves until a row diverges with them
+    bool x3 = c.opts.precision == PDEP_MIXED_BF16X3;
     std::vector<double> hs(3 * (size_t)n);
     for (int step = 0;; ++step) {
         rows.clear();
@@ -629,7 +634,26 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         if (mixed) {
             float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(float2)));
             launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            c.pc_x3 = x3;
             cg_inner<float>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
+            // a diverged row (iterations reported negative) keeps its x: its solution is
+            // dropped, and the remaining steps use FP32 products
+            std::vector<int> itd(na);
+            PDEP_HIP(hipMemcpyAsync(itd.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
+            PDEP_HIP(hipStreamSynchronize(s));
+            bool dropped = false;
+            for (int j = 0; j < na; ++j)
+                if (itd[j] < 0) {
+                    invscale[j] = 0.0;
+                    dropped = true;
+                }
+            if (dropped) {
+                PDEP_HIP(hipMemcpyAsync(d_invscale, invscale.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
+                if (verbose())
+                    fprintf(stderr, "[pdep] refinement step %d: BF16x3 inner solves diverged, FP32 products from here\n",
+                            step + 1), fflush(stderr);
+                x3 = false;
+            }
             launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s);
         } else {
             double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(double2)));
@@ -655,9 +679,10 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         int itmax = 0;
         double worst = 0.0;
         for (int j = 0; j < na; ++j) {
+            const int itj = its[j] < 0 ? -its[j] - 1 : its[j];
             rr[rows[j]] = dots[j];
-            it_row[rows[j]] += its[j];
-            itmax = std::max(itmax, its[j]);
+            it_row[rows[j]] += itj;
+            itmax = std::max(itmax, itj);
             worst = std::max(worst, std::sqrt(dots[j] / bb[rows[j]]));
         }
         st.refine_steps = std::max(st.refine_steps, step + 1);

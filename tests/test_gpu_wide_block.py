@@ -56,3 +56,21 @@ def test_wide_block_pdep_eigs(oracle_wide):
     res = np.linalg.norm(A - lam[:, None] * basis[sel], axis=1)
     print("oracle residuals", res)
     assert res.max() <= 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_wide_block_bf16x3_chi0_parity(oracle_wide):
+    """The BF16x3 path with more than 64 bands (four waves along the bands in the
+    coefficient GEMM with the fused residual step) against the oracle's
+    sum-over-states chi0bar, on the oracle's orbitals, to the mixed-precision bar."""
+    V, m, gs = oracle_wide
+    from paper_1501_03141_amd import pdep
+    phi = inputs.trial_block(m.miller[m.nz], 6, 219)
+    want = R.chi0bar_apply(m, gs, phi, method="sos")
+    with pdep.Context(W.L, W.n, W.ecut, V, W.n_v, precision=pdep.PDEP_MIXED_BF16X3, cg_tol=1e-10, psi=gs.C,
+                      eps=gs.eps, gap_min=1e-4) as c:
+        got, st = c.chi0_apply(phi)
+    err = np.max(np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1))
+    print("bf16x3 N_v 86", st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= 1e-8
