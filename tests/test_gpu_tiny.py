@@ -290,3 +290,24 @@ def test_lane_quad_grids_parity(grid, cell, ecut, mode):
     print(grid, mode, "npw", m.miller.shape[0], st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= (1e-10 if mode == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_odd_band_count_parity(mode):
+    """N_v = 5: an odd number of bands, so the paired right-hand-side and density passes
+    end every perturbation with a band transformed alone."""
+    from paper_1501_03141_amd import pdep
+    Wo = inputs.Workload("tiny_odd", W.L, W.n, W.ecut, 4, 5, 8, 1e-10, 1517)
+    V = inputs.vloc(Wo)
+    m = R.make_model(Wo.L, Wo.n, Wo.ecut, V)
+    gs = R.ground_state(m, Wo.n_v, full=True)
+    phi = inputs.trial_block(m.miller[m.nz], 3, 223)
+    want = R.chi0bar_apply(m, gs, phi)
+    prec = pdep.PDEP_FP64 if mode == "fp64" else pdep.PDEP_MIXED_BF16X3
+    with pdep.Context(Wo.L, Wo.n, Wo.ecut, V, Wo.n_v, precision=prec, cg_tol=1e-10, psi=gs.C, eps=gs.eps,
+                      gap_min=1e-6) as c:
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print("N_v 5", mode, "gap", gs.gap, st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)
