@@ -311,3 +311,26 @@ def test_odd_band_count_parity(mode):
     print("N_v 5", mode, "gap", gs.gap, st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= (1e-10 if mode == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_unequal_xy_grid_parity(mode):
+    """A 24 x 32 x 16 grid (10 x 13.3 x 6.7 bohr): NX != NY, so every slab pass (H, density,
+    right-hand sides) takes the LDS Stockham kernels instead of the register and lane-quad
+    ones."""
+    from paper_1501_03141_amd import pdep
+    Wu = inputs.Workload("xy_unequal", (10.0, 40.0 / 3.0, 20.0 / 3.0), (24, 32, 16), 5.0, 3, 4, 6, 1e-10, 1519)
+    V = inputs.vloc(Wu)
+    m = R.make_model(Wu.L, Wu.n, Wu.ecut, V, naive=False)
+    gs = R.ground_state(m, Wu.n_v, full=True)
+    phi = inputs.trial_block(m.miller[m.nz], 3, 227)
+    want = R.chi0bar_apply(m, gs, phi)
+    prec = pdep.PDEP_FP64 if mode == "fp64" else pdep.PDEP_MIXED_BF16X3
+    with pdep.Context(Wu.L, Wu.n, Wu.ecut, V, Wu.n_v, precision=prec, cg_tol=1e-10, psi=gs.C, eps=gs.eps,
+                      gap_min=1e-6) as c:
+        assert np.array_equal(c.miller(), m.miller)
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print("24x32x16", mode, "npw", m.miller.shape[0], "gap", gs.gap, st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)
