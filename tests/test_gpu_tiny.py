@@ -334,3 +334,24 @@ def test_unequal_xy_grid_parity(mode):
     print("24x32x16", mode, "npw", m.miller.shape[0], "gap", gs.gap, st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= (1e-10 if mode == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_runtime_sizes_parity(mode):
+    """A 36 x 36 x 18 grid: line lengths with no compiled form, so the slab, stick and
+    density passes all run their run-time-size kernels."""
+    from paper_1501_03141_amd import pdep
+    Wr = inputs.Workload("runtime_sizes", (15.0, 15.0, 7.5), (36, 36, 18), 5.0, 3, 4, 6, 1e-10, 1521)
+    V = inputs.vloc(Wr)
+    m = R.make_model(Wr.L, Wr.n, Wr.ecut, V, naive=False)
+    gs = R.ground_state(m, Wr.n_v, full=True)
+    phi = inputs.trial_block(m.miller[m.nz], 3, 229)
+    want = R.chi0bar_apply(m, gs, phi)
+    prec = pdep.PDEP_FP64 if mode == "fp64" else pdep.PDEP_MIXED_BF16X3
+    with pdep.Context(Wr.L, Wr.n, Wr.ecut, V, Wr.n_v, precision=prec, cg_tol=1e-10, psi=gs.C, eps=gs.eps,
+                      gap_min=1e-6) as c:
+        got, st = c.chi0_apply(phi)
+    err = _relerr(got, want)
+    print("36x36x18", mode, "npw", m.miller.shape[0], "gap", gs.gap, st, "relerr", err)
+    assert st["n_notconv"] == 0
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)
