@@ -72,7 +72,10 @@ typedef enum {
     PDEP_MIXED_BF16X3 = 2 /* as PDEP_MIXED_FP32, but the inner P_c GEMMs split each FP32
                              operand into two bfloat16 parts and sum three bf16 products
                              with FP32 accumulation (about 16 significant bits); the FP64
-                             refinement restores the requested tolerance */
+                             refinement restores the requested tolerance.  If an inner
+                             solve diverges with these products (its residual grows
+                             100-fold), its result is dropped and the remaining
+                             refinement steps of the block use FP32 products */
 } pdep_precision;
 
 #define PDEP_DEVICE_PTRS 1u
