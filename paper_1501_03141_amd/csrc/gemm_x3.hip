@@ -724,11 +724,11 @@ void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, 
     if (N <= 0 || K <= 0) return;
     PDEP_REQUIRE(lda % 4 == 0 && lds % 4 == 0, PDEP_EINVAL,
                  "gemm_update_x3_real: leading dimensions must be multiples of 4");
-    PDEP_REQUIRE((N + 127) / 128 <= 65535, PDEP_EINVAL, "gemm_update_x3_real: N too large");
-    dim3 grid((K + 63) / 64, (N + 127) / 128);
+    PDEP_REQUIRE((N + 63) / 64 <= 65535, PDEP_EINVAL, "gemm_update_x3_real: N too large");
+    dim3 grid((K + 63) / 64, (N + 63) / 64);
     ProfScope prof_(K_GEMM_UPDATE, s, (double)M * K * sizeof(float2) + (double)N * M * sizeof(float) +
                     (double)N * K * sizeof(float2) * (beta != 0.0 ? 2.0 : 1.0), 4.0 * (double)M * N * K);
-    hipLaunchKernelGGL(k_gemm_update_x3r<false>, grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha,
+    hipLaunchKernelGGL((k_gemm_update_x3r<false, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, (float)alpha,
                        (float)beta, Y, ldy, DirUpdate{});
     PDEP_HIP(hipGetLastError());
 }
