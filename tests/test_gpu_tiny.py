@@ -355,3 +355,45 @@ def test_runtime_sizes_parity(mode):
     print("36x36x18", mode, "npw", m.miller.shape[0], "gap", gs.gap, st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= (1e-10 if mode == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_free_electron_golden(mode):
+    """V = 0 with one occupied plane wave: the library's chi0bar on cosine-wave
+    perturbations equals the closed-form eigenvalues stored in tests/golden."""
+    import os
+    from paper_1501_03141_amd import pdep
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "free_electron_chi0bar.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    golden = [(tuple(int(x) for x in r[:3]), float(r[3])) for r in rows]
+    V0 = np.zeros(W.n)
+    m = R.make_model(W.L, W.n, W.ecut, V0)
+    # the exact occupied orbital: the G = 0 plane wave (a computed one would carry its
+    # eigensolver residual into the projector)
+    psi = np.zeros((1, m.miller.shape[0]), dtype=complex)
+    psi[0, int(np.where(~np.any(m.miller != 0, axis=1))[0][0])] = 1.0
+    prec = pdep.PDEP_FP64 if mode == "fp64" else pdep.PDEP_MIXED_BF16X3
+    with pdep.Context(W.L, W.n, W.ecut, V0, 1, precision=prec, cg_tol=1e-12 if mode == "fp64" else 1e-10,
+                      psi=psi, eps=np.zeros(1)) as c:
+        sp = c.miller()
+        assert np.array_equal(sp, m.miller)
+        sp = sp[np.any(sp != 0, axis=1)]
+        index = {tuple(int(x) for x in g): i for i, g in enumerate(sp)}
+        # one cosine wave per listed +-G pair (each pair once)
+        seen, phis, lams = set(), [], []
+        for g, lam in golden:
+            if g in seen:
+                continue
+            seen.add(g)
+            seen.add(tuple(-x for x in g))
+            phi = np.zeros(sp.shape[0], dtype=complex)
+            phi[index[g]] = 1.0
+            phi[index[tuple(-x for x in g)]] = 1.0
+            phis.append(phi)
+            lams.append(lam)
+        phis = np.array(phis)
+        got, st = c.chi0_apply(phis)
+    err = np.max(np.abs(got - np.array(lams)[:, None] * phis)) / np.max(np.abs(lams))
+    print("free electron", mode, len(lams), "pairs", st, "max rel err", err)
+    assert st["n_notconv"] == 0
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)

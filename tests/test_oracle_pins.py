@@ -6,6 +6,7 @@ transform, a wrong Coulomb scaling, a wrong projector) fails at least one of the
 mutation tests at the end plant such mistakes and check that they are caught.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -332,3 +333,26 @@ def test_mutation_missing_projector_caught(tiny):
     bad = R.density_response(m, gs, np.array(sigma_free))
     good = R.chi0_real(m, gs, dV, method="sos")
     assert np.max(np.abs(bad - good)) > 1e-2 * np.max(np.abs(good))
+
+
+def _golden_free_electron():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "free_electron_chi0bar.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return [(tuple(int(x) for x in r[:3]), float(r[3])) for r in rows]
+
+
+def test_free_electron_golden_fixture():
+    """The oracle's chi0bar of the free-electron model reproduces the closed-form values
+    stored in tests/golden (plane-wave perturbations at the listed Miller indices)."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    gs = R.ground_state(m, 1, full=True)
+    golden = _golden_free_electron()
+    assert len(golden) >= 18
+    sp = m.miller[m.nz]
+    index = {tuple(int(x) for x in g): i for i, g in enumerate(sp)}
+    for (g, lam) in golden[:8]:
+        phi = np.zeros((1, sp.shape[0]), dtype=complex)
+        phi[0, index[g]] = 1.0
+        phi[0, index[tuple(-x for x in g)]] = 1.0     # Hermitian symmetric (a cosine wave)
+        out = R.chi0bar_apply(m, gs, phi)
+        assert np.max(np.abs(out - lam * phi)) <= 1e-12 * abs(lam)
