@@ -99,7 +99,9 @@ typedef struct {
     int cg_maxit;         /* iteration cap of each CG solve */
     double inner_tol;     /* mixed: relative reduction asked of each FP32 inner solve */
     int refine_maxit;     /* mixed: cap on FP64 refinement steps */
-    int precond;          /* 1: diagonal kinetic preconditioner 1/max(1, 1/2|G|^2 - e_v), 0: none */
+    int precond;          /* 1: diagonal kinetic preconditioner 1/max(1/2|G|^2 - e_v, 0.1 Ha)
+                             followed by P_c (the CG of Sec. 2.3 is "preconditioned" without a
+                             named preconditioner; it changes iteration counts only), 0: none */
     double gap_min;       /* setup fails with PDEP_EGAP below this HOMO-LUMO gap (Ha) */
     double gs_tol;        /* ground state: residual norm target ||H c - e c|| */
     int gs_maxit;         /* ground state: Davidson iteration cap */
@@ -136,6 +138,9 @@ typedef struct {
     double ms;                    /* wall time of the call on the device stream */
     int fft_chunk;                /* rows per launch of the transform chain of the inner solves
                                      (chosen by timing on the first large application) */
+    int n_fp32_fallback_rows;     /* PDEP_MIXED_BF16X3: systems that ran an inner solve with FP32
+                                     projection products after a BF16x3 inner solve diverged
+                                     (0 when the BF16x3 products held throughout) */
 } pdep_apply_stats;
 
 typedef struct {
@@ -151,11 +156,18 @@ typedef struct {
     double max_residual;          /* of the reported pairs */
     long long cg_iter_total;
     double ms;
+    int n_notconv;                /* Sternheimer systems that missed cg_tol, summed over every
+                                     chi0bar application; > 0 makes pdep_eigs return
+                                     PDEP_ENOTCONV (outputs still filled) */
 } pdep_eig_stats;
 
 typedef struct pdep_ctx pdep_ctx;
 
-/* Build the basis tables, upload V_loc and obtain the occupied orbitals.
+/* Build the basis tables, upload V_loc and obtain the occupied orbitals: the N_v
+ * lowest solutions of the Kohn-Sham equation of Sec. 2 with a local potential only,
+ * H = 1/2|G|^2 + V_loc on the plane-wave sphere of Sec. 2.1 (the ground-state input of
+ * the G0W0 scheme, Fig. scheme_overview).  The gap test follows the integer occupations
+ * of Sec. 2.1 (chi0 exists only for a positive HOMO-LUMO gap).
  * vloc: N_g doubles (host), real potential in Ha.  psi_in: NULL, or N_v x N_pw
  * complex (host) orthonormal occupied coefficients in S order with eps_in their
  * N_v energies; when NULL the library finds the N_v lowest eigenpairs of H with an
@@ -169,13 +181,17 @@ typedef struct pdep_ctx pdep_ctx;
 int pdep_setup(const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
                const double* psi_in, const double* eps_in, pdep_ctx** out);
 
+/* Sizes and ground-state figures of the context (host struct, caller-owned). */
 int pdep_get_info(pdep_ctx* ctx, pdep_info* info);
 
-/* Miller indices of S, 3 * N_pw int32 (host), lexicographic (mx, my, mz). */
-int pdep_get_gvectors(pdep_ctx* ctx, int32_t* miller);
+/* The plane-wave basis S of Sec. 2.1 (1/2|G|^2 <= ecut): *n_pw (may be NULL) receives
+ * N_pw; miller (may be NULL: size query) receives 3 * N_pw int32 Miller indices (host),
+ * lexicographic (mx, my, mz), mz fastest.  PDEP_EINVAL if both are NULL. */
+int pdep_get_gvectors(pdep_ctx* ctx, int* n_pw, int32_t* miller);
 
-/* Occupied energies (N_v doubles) and coefficients (N_v x N_pw complex, real in r:
- * the basis pdep_setup keeps), host.  Either pointer may be NULL. */
+/* The occupied Kohn-Sham states in use (Sec. 2; the psi_v and e_v of Eq. stern):
+ * energies (N_v doubles) and coefficients (N_v x N_pw complex, real in r: the basis
+ * pdep_setup keeps), host, caller-allocated.  Either pointer may be NULL. */
 int pdep_get_orbitals(pdep_ctx* ctx, double* eps, double* psi);
 
 /* chi0bar applied to n_pert potentials (Eq. chiisamatrixinpdep with V_pert = phi~):

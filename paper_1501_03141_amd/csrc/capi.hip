@@ -224,11 +224,12 @@ int pdep_get_info(pdep_ctx* ctx, pdep_info* info) {
     API_END
 }
 
-int pdep_get_gvectors(pdep_ctx* ctx, int32_t* miller) {
+int pdep_get_gvectors(pdep_ctx* ctx, int* n_pw, int32_t* miller) {
     API_BEGIN
     check_ctx(ctx);
-    PDEP_REQUIRE(miller != nullptr, PDEP_EINVAL, "null output");
-    std::memcpy(miller, ctx->c.basis.miller.data(), ctx->c.basis.miller.size() * sizeof(int32_t));
+    PDEP_REQUIRE(n_pw != nullptr || miller != nullptr, PDEP_EINVAL, "null n_pw and miller");
+    if (n_pw) *n_pw = ctx->c.basis.npw;
+    if (miller) std::memcpy(miller, ctx->c.basis.miller.data(), ctx->c.basis.miller.size() * sizeof(int32_t));
     API_END
 }
 
@@ -288,6 +289,7 @@ int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_a
         st->max_rel_residual = as.max_rel_residual;
         st->ms = ms;
         st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
+        st->n_fp32_fallback_rows = as.n_fp32_fallback;
     }
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
@@ -338,6 +340,7 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
         st->max_rel_residual = as.max_rel_residual;
         st->ms = ms;
         st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
+        st->n_fp32_fallback_rows = as.n_fp32_fallback;
     }
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
@@ -401,8 +404,12 @@ int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, cons
         st->max_residual = r.max_residual;
         st->cg_iter_total = r.cg_iter_total;
         st->ms = ms;
+        st->n_notconv = r.n_notconv;
     }
     if (!r.converged) return fail(PDEP_ENOTCONV, "PDEP Davidson did not reach tol");
+    if (r.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(r.n_notconv) +
+                                       " Sternheimer systems of the chi0bar applications missed cg_tol");
     API_END
 }
 

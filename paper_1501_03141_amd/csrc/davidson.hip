@@ -402,7 +402,14 @@ void ground_state(Ctx& c) {
             fprintf(stderr, "[pdep] ground state it %d: subspace %d, max residual %.2e\n", it, m, maxres), fflush(stderr);
         if (maxres <= tol) { conv = true; break; }
         // expansion vectors: preconditioned residuals of unconverged pairs
-        const int nt = (int)unconv.size();
+        int nt = (int)unconv.size();
+        if (m + nt > mmax) {          // restart from the Ritz vectors
+            PDEP_HIP(hipMemcpyAsync(V, X, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            PDEP_HIP(hipMemcpyAsync(AV, AX, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            m = k;
+        }
+        nt = std::min(nt, mmax - m);  // V and AV hold mmax columns
+        if (nt <= 0) break;
         double2* T = static_cast<double2*>(ws.get(D_T, (size_t)nt * ld * sizeof(double2)));
         std::vector<double> th_sel(nt);
         for (int j = 0; j < nt; ++j) {
@@ -412,11 +419,6 @@ void ground_state(Ctx& c) {
         }
         PDEP_HIP(hipMemcpyAsync(dtheta, th_sel.data(), nt * sizeof(double), hipMemcpyHostToDevice, s));
         precond_h(nt, npw, T, ld, b.d_kin64.as<double>(), dtheta, s);
-        if (m + nt > mmax) {          // restart from the Ritz vectors
-            PDEP_HIP(hipMemcpyAsync(V, X, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            PDEP_HIP(hipMemcpyAsync(AV, AX, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            m = k;
-        }
         const int kept = orthonormalise(c, ws, sv, V, m, T, nt, ld, false);
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -533,9 +535,13 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     Solver sv(c);
     Workspace ws(c);
     EigResult res;
-    const int nb = std::min(npw - 1, npdep + std::max(0, eo.n_buffer));
     PDEP_REQUIRE(npdep >= 1 && npdep < npw - 1, PDEP_EINVAL, "n_pdep must be between 1 and N_pw' - 1");
-    const int mmax = std::min(npw - 1, std::max(eo.max_subspace > 0 ? eo.max_subspace : 4 * npdep, nb + npdep));
+    const int nb = std::min(npw - 1, npdep + std::max(0, eo.n_buffer));
+    // After a restart the search space holds the nb Ritz vectors and grows by at most nb
+    // residuals, so it needs room for 2 nb columns.
+    PDEP_REQUIRE(eo.max_subspace <= 0 || eo.max_subspace >= 2 * nb, PDEP_EINVAL,
+                 "max_subspace must be 0 or at least 2 (n_pdep + n_buffer)");
+    const int mmax = pdep_subspace_max(npw, npdep, eo);
     double2* V = static_cast<double2*>(ws.get(D_V, (size_t)mmax * ld * sizeof(double2)));
     double2* AV = static_cast<double2*>(ws.get(D_AV, (size_t)mmax * ld * sizeof(double2)));
     double2* X = static_cast<double2*>(ws.get(D_X, (size_t)nb * ld * sizeof(double2)));
@@ -611,16 +617,19 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
                     theta[0]), fflush(stderr);
         if (maxres <= eo.tol) { res.converged = true; break; }
         if (it == eo.maxit) break;
-        const int nt = (int)unconv.size();
-        double2* T = static_cast<double2*>(ws.get(D_T, (size_t)nt * ld * sizeof(double2)));
-        for (int j = 0; j < nt; ++j)
-            PDEP_HIP(hipMemcpyAsync(T + (size_t)j * ld, R + (size_t)unconv[j] * ld, ld * sizeof(double2),
-                                    hipMemcpyDeviceToDevice, s));
+        int nt = (int)unconv.size();
         if (m + nt > mmax) {
             PDEP_HIP(hipMemcpyAsync(V, X, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
             PDEP_HIP(hipMemcpyAsync(AV, AX, (size_t)k * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
             m = k;
         }
+        // never more columns than V and AV hold (only short of 2 nb when N_pw' caps mmax)
+        nt = std::min(nt, mmax - m);
+        if (nt <= 0) break;
+        double2* T = static_cast<double2*>(ws.get(D_T, (size_t)nt * ld * sizeof(double2)));
+        for (int j = 0; j < nt; ++j)
+            PDEP_HIP(hipMemcpyAsync(T + (size_t)j * ld, R + (size_t)unconv[j] * ld, ld * sizeof(double2),
+                                    hipMemcpyDeviceToDevice, s));
         const int kept = orthonormalise(c, ws, sv, V, m, T, nt, ld, true);
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -632,6 +641,7 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     res.iterations = std::min(it, eo.maxit);
     res.max_residual = maxres;
     res.cg_iter_total = st.cg_iter_total;
+    res.n_notconv = st.n_notconv;
     for (int j = 0; j < npdep; ++j) lam_out[j] = theta[j];
     if (basis_out_dev)
         PDEP_HIP(hipMemcpyAsync(basis_out_dev, X, (size_t)npdep * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -385,6 +386,7 @@ int half_len(int npw);
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
 struct ApplyStats {
     int n_rhs = 0, cg_iter_max = 0, refine_steps = 0, n_notconv = 0;
+    int n_fp32_fallback = 0;              // BF16x3 mode: systems re-solved with FP32 projection products
     long long cg_iter_total = 0, op_applications = 0;
     double max_rel_residual = 0.0;
 };
@@ -411,10 +413,19 @@ void ground_state(Ctx& c);
 void realify_orbitals(Ctx& c);
 struct EigResult {
     int iterations = 0, columns = 0;
+    int n_notconv = 0;                    // Sternheimer systems that missed cg_tol (all chi0 applications)
     double max_residual = 0.0;
     long long cg_iter_total = 0;
     bool converged = false;
 };
+// Columns of the PDEP Davidson search space: max_subspace (default 4 n_pdep), but never
+// fewer than twice the block (n_pdep + n_buffer), which a restart needs, nor more than
+// N_pw - 1.
+inline int pdep_subspace_max(int npw, int npdep, const pdep_eig_opts& eo) {
+    const int nb = std::min(npw - 1, npdep + std::max(0, eo.n_buffer));
+    const int want = eo.max_subspace > 0 ? eo.max_subspace : 4 * npdep;
+    return std::min(npw - 1, std::max(want, 2 * nb));
+}
 EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_dev, const pdep_eig_opts& eo,
                         double* lam_out, double2* basis_out_dev);
 

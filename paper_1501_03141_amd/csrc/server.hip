@@ -192,7 +192,7 @@ size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, c
     const size_t gs = 2 * mg * ld * 16 + 3 * nbg * ld * 16 + mg * sticks_row + mg * mg * 16 * 2;
     // PDEP Davidson and one chi0 tile
     const size_t nb = (size_t)n_pdep + (size_t)std::max(0, eo.n_buffer);
-    const size_t mp = std::max<size_t>(eo.max_subspace > 0 ? (size_t)eo.max_subspace : 4 * (size_t)n_pdep, nb + n_pdep);
+    const size_t mp = (size_t)pdep_subspace_max(b.npw, n_pdep, eo);
     const size_t dav = 2 * mp * ld * 16 + 4 * nb * ld * 16 + mp * mp * 16 * 2 + ((size_t)64 << 20);
     const size_t inner = o.precision != PDEP_FP64 ? 8 : 16;
     const size_t row = ld * 16 * 5 + ld * inner * 11 + sticks_row + nv * 16 + 256;
@@ -245,6 +245,8 @@ int pdep_submit(pdep_server* S, const pdep_job* job, uint64_t* ticket) {
         PDEP_REQUIRE(job->n_pdep >= 1, PDEP_EINVAL, "n_pdep must be >= 1");
         PDEP_REQUIRE(job->eig.tol > 0 && job->eig.maxit >= 1 && job->eig.n_buffer >= 0, PDEP_EINVAL,
                      "bad eig options");
+        PDEP_REQUIRE(job->eig.max_subspace <= 0 || job->eig.max_subspace >= 2 * (job->n_pdep + job->eig.n_buffer),
+                     PDEP_EINVAL, "max_subspace must be 0 or at least 2 (n_pdep + n_buffer)");
         j->est = pdep::job_hbm_estimate(job->cell, job->opts, job->n_pdep, job->eig, &j->chi0_budget);
         const size_t ng = (size_t)job->cell.n[0] * job->cell.n[1] * job->cell.n[2];
         j->vloc.assign(job->vloc, job->vloc + ng);

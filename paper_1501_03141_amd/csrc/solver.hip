@@ -22,7 +22,8 @@
 //   beta = <r,z>_new/<r,z>;  p = z + beta p;  stop when ||r||^2 <= thr2
 // with A = P_c (H - e_v) applied as stick pass -> slab pass (V_loc) -> stick pass with
 // the kinetic/shift epilogue -> P_c GEMM pair, and K the diagonal kinetic preconditioner
-// 1/max(1, 1/2|G|^2 - e_v) (the paper does not fix K; it only changes iteration counts).
+// 1/max(1/2|G|^2 - e_v, kPrecondFloor) with a floor of 0.1 Ha (the paper does not fix K;
+// it only changes iteration counts).
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -595,7 +596,8 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     std::vector<int> rows;
     // BF16x3 projection products in the inner solves until a row diverges with them
     bool x3 = c.opts.precision == PDEP_MIXED_BF16X3;
-    std::vector<double> hs(3 * (size_t)n);
+    // rows that ran an inner solve with FP32 products after such a divergence
+    std::vector<char> fp32_row(c.opts.precision == PDEP_MIXED_BF16X3 ? n : 0, 0);
     for (int step = 0;; ++step) {
         rows.clear();
         for (int i = 0; i < n; ++i)
@@ -635,6 +637,8 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
             float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(float2)));
             launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
             c.pc_x3 = x3;
+            if (!fp32_row.empty() && !x3)
+                for (int i : rows) fp32_row[i] = 1;
             cg_inner<float>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
             // a diverged row (iterations reported negative) keeps its x: its solution is
             // dropped, and the remaining steps use FP32 products
@@ -690,6 +694,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
             fprintf(stderr, "[pdep] refinement step %d: %d systems, inner CG %d iterations, worst FP64 residual %.2e\n",
                     step + 1, na, itmax, worst), fflush(stderr);
     }
+    for (char f : fp32_row) st.n_fp32_fallback += f;
     for (int i = 0; i < n; ++i) {
         st.cg_iter_total += it_row[i];
         st.cg_iter_max = std::max(st.cg_iter_max, it_row[i]);

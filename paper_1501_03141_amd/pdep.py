@@ -70,7 +70,8 @@ class Info(C.Structure):
 class ApplyStats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("cg_iter_max", C.c_int), ("cg_iter_total", C.c_longlong),
                 ("op_applications", C.c_longlong), ("refine_steps", C.c_int), ("n_notconv", C.c_int),
-                ("max_rel_residual", C.c_double), ("ms", C.c_double), ("fft_chunk", C.c_int)]
+                ("max_rel_residual", C.c_double), ("ms", C.c_double), ("fft_chunk", C.c_int),
+                ("n_fp32_fallback_rows", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,7 +83,7 @@ class EigOpts(C.Structure):
 
 class EigStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("chi0_columns", C.c_int), ("max_residual", C.c_double),
-                ("cg_iter_total", C.c_longlong), ("ms", C.c_double)]
+                ("cg_iter_total", C.c_longlong), ("ms", C.c_double), ("n_notconv", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -144,7 +145,7 @@ def load(path: str = LIB_PATH):
     lib.pdep_last_error.restype = C.c_char_p
     lib.pdep_setup.argtypes = [C.POINTER(Cell), P, C.POINTER(Opts), P, P, C.POINTER(C.c_void_p)]
     lib.pdep_get_info.argtypes = [P, C.POINTER(Info)]
-    lib.pdep_get_gvectors.argtypes = [P, P]
+    lib.pdep_get_gvectors.argtypes = [P, C.POINTER(C.c_int), P]
     lib.pdep_get_orbitals.argtypes = [P, P, P]
     lib.chi0_apply.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.chi0_apply_raw.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
@@ -298,8 +299,10 @@ class Context:
 
     # --------------------------------------------------------------------------------
     def miller(self) -> np.ndarray:
-        m = np.empty((self.n_pw, 3), dtype=np.int32)
-        _check(self._lib.pdep_get_gvectors(self._h, m.ctypes.data))
+        n = C.c_int()
+        _check(self._lib.pdep_get_gvectors(self._h, C.byref(n), None))
+        m = np.empty((n.value, 3), dtype=np.int32)
+        _check(self._lib.pdep_get_gvectors(self._h, None, m.ctypes.data))
         return m
 
     def orbitals(self):

@@ -9,6 +9,7 @@ import pytest
 
 from oracle import response as R
 from paper_1501_03141_amd import inputs
+from parity import relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -33,8 +34,7 @@ def _ctx(V, gs=None, **kw):
     return pdep.Context(W.L, W.n, W.ecut, V, W.n_v, **kw)
 
 
-def _relerr(a, b):
-    return np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1))
+_relerr = relerr
 
 
 def test_miller_list_identical(oracle_tiny):
@@ -161,6 +161,36 @@ def test_pdep_eigs_seeded_block(oracle_tiny):
         eps, _, st = c.eigs(W.n_pdep, phi0=phi0, tol=1e-10, maxit=100)
     want = np.sort(1.0 - lam)[::-1]
     assert np.max(np.abs(eps - want)) <= 1e-10 * want.max()
+
+
+@pytest.mark.parametrize("n_pdep,n_buffer", [(2, 6), (4, 8)])
+def test_pdep_eigs_buffer_wider_than_block(oracle_tiny, n_pdep, n_buffer):
+    """More buffer vectors than wanted pairs: after a restart the search space holds the
+    n_pdep + n_buffer Ritz vectors and their residuals, and the library sizes it for
+    that; the wanted eigenvalues are still the exact lowest ones."""
+    V, m, gs, lam, Phi = oracle_tiny
+    with _ctx(V, gs) as c:
+        eps, _, st = c.eigs(n_pdep, seed=9, tol=1e-10, maxit=100, n_buffer=n_buffer)
+        with pytest.raises(Exception) as e:
+            c.eigs(n_pdep, seed=9, tol=1e-10, maxit=5, n_buffer=n_buffer,
+                   max_subspace=2 * (n_pdep + n_buffer) - 1)
+        assert getattr(e.value, "code", None) == -1
+    print("eig stats", st)
+    want = np.sort(1.0 - lam[:n_pdep])[::-1]
+    assert np.max(np.abs(eps - want) / want) <= 1e-10
+
+
+def test_pdep_eigs_reports_unconverged_solves(oracle_tiny):
+    """Sternheimer solves capped below the tolerance make pdep_eigs return
+    PDEP_ENOTCONV (outputs and the count of such systems still filled)."""
+    V, m, gs, lam, Phi = oracle_tiny
+    from paper_1501_03141_amd import pdep
+    with _ctx(V, gs, cg_maxit=2, refine_maxit=1) as c:
+        with pytest.raises(pdep.PdepError) as e:
+            c.eigs(4, seed=7, tol=1e-10, maxit=2)
+        assert e.value.code == pdep.PDEP_ENOTCONV
+        eps, _, st = c.eigs(4, seed=7, tol=1e-10, maxit=2, allow_notconv=True)
+    assert st["n_notconv"] > 0 and np.all(np.isfinite(eps))
 
 
 @pytest.mark.parametrize("mode", ["mixed_fp32", "bf16x3"])

@@ -8,6 +8,7 @@ import pytest
 
 from oracle import response as R
 from paper_1501_03141_amd import inputs
+from parity import relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +71,7 @@ def test_wide_block_bf16x3_chi0_parity(oracle_wide):
     with pdep.Context(W.L, W.n, W.ecut, V, W.n_v, precision=pdep.PDEP_MIXED_BF16X3, cg_tol=1e-10, psi=gs.C,
                       eps=gs.eps, gap_min=1e-4) as c:
         got, st = c.chi0_apply(phi)
-    err = np.max(np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1))
+    err = relerr(got, want)
     print("bf16x3 N_v 86", st, "relerr", err)
     assert st["n_notconv"] == 0
     assert err <= 1e-8

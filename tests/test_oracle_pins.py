@@ -251,6 +251,71 @@ def test_pdep_eigenpairs(tiny, tiny_pdep):
     assert np.allclose(Phi.conj() @ Phi.T, np.eye(len(lam)), atol=1e-12)
 
 
+def _ritz_pin_holds(model, gs, lam, Phi, seed=0):
+    """Rayleigh-Ritz on an invariant subspace returns its eigenvalues exactly, whatever
+    basis of it is given: the exact eigenvectors themselves, and a non-orthonormal real
+    mixture of them (rows rescaled, mixed by a random well-conditioned matrix, which
+    keeps Hermitian symmetry)."""
+    rng = np.random.default_rng(seed)
+    k = Phi.shape[0]
+    A = np.eye(k) + 0.3 * rng.standard_normal((k, k))
+    X = (A @ Phi) * rng.uniform(0.5, 3.0, size=(k, 1))
+    ok = True
+    for Y in (Phi, X):
+        th = np.sort(R.rayleigh_ritz(model, gs, Y))
+        ok = ok and np.max(np.abs(th - np.sort(lam))) <= 1e-11 * np.max(np.abs(lam))
+    return bool(ok)
+
+
+def test_rayleigh_ritz_on_eigenspace_gives_eigenvalues(tiny, tiny_pdep):
+    """Pin of the Ritz values: the span of the exact lowest eigenvectors of the full
+    chi0bar matrix (eigh of the dense matrix, a library routine) reproduces their
+    eigenvalues, also from a non-orthonormal basis of that span."""
+    m, gs = tiny
+    lam, Phi, _ = tiny_pdep
+    assert _ritz_pin_holds(m, gs, lam, Phi)
+
+
+def test_rayleigh_ritz_free_electron_closed_form():
+    """V = 0, one occupied state: chi0bar is diagonal in the real plane-wave basis with
+    lambda_G = -32 pi / (Omega |G|^4), so Ritz values on the span of a few real basis
+    vectors (mixed non-orthonormally) are those closed-form values."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    gs = R.ground_state(m, 1, full=True)
+    Bm = R.real_basis(m)
+    G2 = 2 * m.kin[m.nz]
+    lam_b = np.real(np.array([-32 * math.pi / (m.volume * (np.abs(b) ** 2 @ G2) ** 2) for b in Bm]))
+    pick = np.array([0, 7, 40, 41, 200])
+    rng = np.random.default_rng(5)
+    X = (np.eye(5) + 0.4 * rng.standard_normal((5, 5))) @ Bm[pick]
+    th = np.sort(R.rayleigh_ritz(m, gs, X))
+    assert np.max(np.abs(th - np.sort(lam_b[pick]))) <= 1e-12 * np.max(np.abs(lam_b[pick]))
+
+
+def test_mutation_rayleigh_ritz_sign_caught(tiny, tiny_pdep, monkeypatch):
+    """A sign error in the projected matrix (M = -X^H chi0bar X) breaks the Ritz pin."""
+    m, gs = tiny
+    lam, Phi, _ = tiny_pdep
+    real_apply = R.chi0bar_apply
+    monkeypatch.setattr(R, "chi0bar_apply", lambda model, gs_, phi, method="direct": -real_apply(model, gs_, phi,
+                                                                                                   method))
+    assert not _ritz_pin_holds(m, gs, lam, Phi)
+
+
+def test_mutation_rayleigh_ritz_overlap_caught(tiny, tiny_pdep, monkeypatch):
+    """Dropping the overlap X^H X (a plain eigenproblem of the projected matrix) breaks
+    the Ritz pin on the non-orthonormal basis."""
+    m, gs = tiny
+    lam, Phi, _ = tiny_pdep
+
+    real_eigh = R.sla.eigh
+
+    def eigh_no_overlap(M, S=None, **kw):
+        return real_eigh(M, **kw)
+    monkeypatch.setattr(R.sla, "eigh", eigh_no_overlap)
+    assert not _ritz_pin_holds(m, gs, lam, Phi)
+
+
 def test_rayleigh_ritz_interlacing(tiny, tiny_pdep):
     """Ritz values of any subspace are bounded below by the exact eigenvalues
     (Courant-Fischer); a random block gives a strict bound."""

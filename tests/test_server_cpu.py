@@ -138,3 +138,25 @@ def test_destroy_with_queued_jobs():
     for k in range(5):
         _submit(s, k)
     s.close()
+
+
+def test_subspace_size_rule():
+    """The PDEP search space needs room for 2 (n_pdep + n_buffer) columns after a
+    restart: a smaller explicit max_subspace is rejected at submission, and the HBM
+    estimate grows with the buffer vectors beyond the default 4 n_pdep columns."""
+    with pdep.Server(max_running=1, fake=True, fake_ms_per_gb=0.0) as s:
+        with pytest.raises(pdep.PdepError) as e:
+            _submit(s, 1, n_pdep=4, n_buffer=8, max_subspace=23)
+        assert e.value.code == pdep.PDEP_EINVAL
+        est = []
+        for kw in (dict(n_buffer=0), dict(n_buffer=8), dict(n_buffer=8, max_subspace=24)):
+            t = _submit(s, 2, n_pdep=4, **kw)
+            assert s.wait(t, 10000) == pdep.JOB_DONE
+            est.append(s.poll(t)[1]["hbm_estimate"])
+    # 16 columns by default; 24 = 2 (4 + 8) with the buffer, explicit or not
+    assert est[1] > est[0] and est[1] == est[2]
+
+
+def test_gvectors_needs_an_output():
+    lib = pdep.load()
+    assert lib.pdep_get_gvectors(None, None, None) == pdep.PDEP_EINVAL
