@@ -17,8 +17,15 @@ Conventions (Hartree units, orthorhombic cell of edges L, grid n, N_g = prod(n))
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
+
+# threads of the batched FFTs (pocketfft through scipy.fft, run over the batch): the
+# ORACLE_FFT_WORKERS or OMP_NUM_THREADS setting, else every CPU
+FFT_WORKERS = (int(os.environ.get("ORACLE_FFT_WORKERS", "0") or 0)
+               or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
 
 
 def sphere(L, ecut):
@@ -81,10 +88,10 @@ def hamiltonian_naive(E, kin, vloc_flat):
     return H
 
 
-# --- FFT route (numpy pocketfft); pinned equal to the naive DFT by the tests -------------
+# --- FFT route (pocketfft via scipy.fft); pinned equal to the naive DFT by the tests -----
 
 def inv_fft(n, idx, c):
-    """Sphere -> grid with numpy's FFT: N_g * ifftn of the scattered coefficients.
+    """Sphere -> grid with a library FFT: N_g * ifftn of the scattered coefficients.
     c is [N_pw] or [k, N_pw]; returns grid(s) of shape n or [k, *n]."""
     n = tuple(int(x) for x in n)
     c = np.asarray(c)
@@ -92,18 +99,18 @@ def inv_fft(n, idx, c):
     cc = c if batch else c[None, :]
     g = np.zeros((cc.shape[0], int(np.prod(n))), dtype=np.complex128)
     g[:, idx] = cc
-    out = np.fft.ifftn(g.reshape((cc.shape[0],) + n), axes=(1, 2, 3)) * float(np.prod(n))
+    out = sfft.ifftn(g.reshape((cc.shape[0],) + n), axes=(1, 2, 3), workers=FFT_WORKERS) * float(np.prod(n))
     return out if batch else out[0]
 
 
 def fwd_fft(n, idx, f):
-    """Grid -> sphere with numpy's FFT: fftn / N_g gathered at the sphere indices.
+    """Grid -> sphere with a library FFT: fftn / N_g gathered at the sphere indices.
     f has shape n or [k, *n]; returns [N_pw] or [k, N_pw]."""
     n = tuple(int(x) for x in n)
     f = np.asarray(f)
     batch = f.ndim == 4
     ff = f if batch else f[None]
-    F = np.fft.fftn(ff, axes=(1, 2, 3)).reshape(ff.shape[0], -1) / float(np.prod(n))
+    F = sfft.fftn(ff, axes=(1, 2, 3), workers=FFT_WORKERS).reshape(ff.shape[0], -1) / float(np.prod(n))
     out = F[:, idx]
     return out if batch else out[0]
 

@@ -38,3 +38,21 @@ def test_traffic_table_is_tied_to_its_source(tmp_path, monkeypatch):
     monkeypatch.setitem(bench.MEASURED_TRAFFIC, "slab_hv", dict(m, source=str(fake)))
     monkeypatch.setattr(bench, "ROOT", "/")
     assert bench.measured_traffic("slab_hv", "medium") is None
+
+
+def test_roofline_bound_is_the_larger_floor():
+    """The bound is the larger of the two algorithmic floors at published peaks: the FP32
+    slab pass of the medium step (0.2562 GB and 4.55 GFLOP per launch, 137.3 us) is
+    HBM-bound at 1.87 TB/s; the same bytes with 30x the flops would be ALU-bound."""
+    import bench
+    prof = {"slab_hv": {"ms": 137.3, "launches": 1000, "bytes": 0.2562e9 * 1000, "flops": 4.55e9 * 1000}}
+    name, r = bench.dominant_roofline(prof, "bf16")
+    assert name == "slab_hv" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["frac"] == pytest.approx(0.2562e9 / 137.3e-6 / 8e12, rel=1e-3)
+    prof["slab_hv"]["flops"] *= 30
+    _, r = bench.dominant_roofline(prof, "bf16")
+    assert r["bound"] == "alu" and r["peak"] == 157.3
+    # a matrix-core class in BF16x3 mode is priced at a third of the bf16 peak
+    prof = {"gemm_ahb": {"ms": 1.0, "launches": 1, "bytes": 1e3, "flops": 1e12}}
+    _, r = bench.dominant_roofline(prof, "bf16")
+    assert r["bound"] == "mfma" and r["peak"] == pytest.approx(2500.0 / 3, rel=1e-3)
