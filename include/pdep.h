@@ -204,6 +204,22 @@ int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_a
  * dv_r (n_pert x N_g doubles) given directly on the grid, no Coulomb scaling. */
 int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, pdep_apply_stats* st);
 
+/* chi0_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it).  Same
+ * arguments, results, statistics and errors as chi0_apply, but the work space comes
+ * from a fixed 256 MiB array in the library's device code (each device the library
+ * runs on holds its own copy until the process ends) instead of pdep_opts.alloc, no
+ * routine that allocates device memory is called (the FP64 projection update runs on
+ * the library's own matrix-core kernel), no events are created (st->ms is host wall
+ * time; pdep_profile_* does not time these calls) and the transform-chain block is not
+ * tuned here (a block tuned by an earlier chi0_apply is used).  The perturbations run in
+ * as many passes as the array needs; PDEP_ENOMEM if the work space of one perturbation
+ * (about N_v x (11 N_pw x 16 + 2 N_sticks n_z x 16) bytes) exceeds it.  All calls on a
+ * device share that device's array and its last contents (the library initialises
+ * what it reads); two such calls that overlapped on one device would race, so the
+ * library serialises them within the process. */
+int chi0_apply_noalloc(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st);
+
 /* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
  * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
  * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own

@@ -3,6 +3,7 @@
 // in the kernels of fft.hip / linalg.hip driven by solver.hip and davidson.hip.
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "pdep_internal.h"
@@ -51,6 +52,37 @@ struct Timer {
 };
 
 enum CapiSlot { C_IN = pdep::WS_CAPI_IN, C_OUT = pdep::WS_CAPI_OUT, C_STAGE = pdep::WS_CAPI_STAGE };
+
+}  // namespace
+
+// ------------------------------------------------------- no-allocation scratch ---
+// Fixed device memory of chi0_apply_noalloc: every device the library runs on holds
+// its own copy for the life of the process.  In host code `scratch` only names the
+// variable; its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_call_mu[kMaxDevices];   // one no-allocation call per device at a time
+
+// Device address of device dev's copy of `scratch` (dev must be the current device the
+// first time).
+char* scratch_address(int dev) {
+    PDEP_REQUIRE(dev >= 0 && dev < kMaxDevices, PDEP_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        PDEP_REQUIRE(e == hipSuccess && p != nullptr, PDEP_EDEVICE,
+                     std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<char*>(p);
+    }
+    return g_scratch_addr[dev];
+}
 
 void check_ctx(pdep_ctx* ctx) { PDEP_REQUIRE(ctx != nullptr, PDEP_EINVAL, "null context"); }
 
@@ -163,6 +195,7 @@ int pdep::setup_context(const pdep_cell* cell, const double* vloc, const pdep_op
     PDEP_REQUIRE(all_finite(vloc, b.ng), PDEP_EINVAL, "V_loc contains NaN or Inf");
     PDEP_REQUIRE(opts->n_v + 1 < b.npw, PDEP_EINVAL, "n_v too large for the basis");
     PDEP_HIP(hipGetDevice(&c.device));
+    (void)scratch_address(c.device);   // resolved once per device, with it current
     pdep::upload_basis(c.basis, &c.al, c.stream);
     c.nv = opts->n_v;
     // the slab passes read V in z-major order [iz][ix][iy]
@@ -246,6 +279,112 @@ int pdep_get_orbitals(pdep_ctx* ctx, double* eps, double* psi) {
     API_END
 }
 
+}  // extern "C"
+
+namespace {
+
+void fill_apply_stats(const Ctx& c, const pdep::ApplyStats& as, double ms, pdep_apply_stats* st) {
+    if (!st) return;
+    st->n_rhs = as.n_rhs;
+    st->cg_iter_max = as.cg_iter_max;
+    st->cg_iter_total = as.cg_iter_total;
+    st->op_applications = as.op_applications;
+    st->refine_steps = as.refine_steps;
+    st->n_notconv = as.n_notconv;
+    st->max_rel_residual = as.max_rel_residual;
+    st->ms = ms;
+    st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
+    st->n_fp32_fallback_rows = as.n_fp32_fallback;
+}
+
+// Context state that a no-allocation call changes, restored on every exit.
+struct NoallocGuard {
+    Ctx& c;
+    int rhs_tile;
+    size_t split;
+    NoallocGuard(Ctx& cc, pdep::Arena* a, size_t split_elems) : c(cc), rhs_tile(cc.opts.rhs_tile), split(cc.split_elems) {
+        c.arena = a;
+        c.split_elems = split_elems;
+    }
+    ~NoallocGuard() {
+        c.arena = nullptr;
+        c.opts.rhs_tile = rhs_tile;
+        c.split_elems = split;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int chi0_apply_noalloc(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    PDEP_REQUIRE(n_pert >= 0, PDEP_EINVAL, "n_pert must be >= 0");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (n_pert == 0) { g_err.clear(); return PDEP_OK; }
+    PDEP_REQUIRE(phi && out, PDEP_EINVAL, "null phi/out");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    if (!dev) PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pert * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+    char* base = scratch_address(c.device);
+    std::lock_guard<std::mutex> call_lk(g_scratch_call_mu[c.device]);
+    pdep::ProfSuspend no_events;
+    const auto t0 = std::chrono::steady_clock::now();
+    pdep::Arena arena;
+    arena.base = base;
+    arena.cap = kScratchBytes;
+    NoallocGuard guard(c, &arena, (size_t)1 << 20);
+    // perturbations per pass: staging rows (in and out, plus host staging) and the chi0
+    // work of one tile must fit the scratch
+    const size_t stage_pp = (size_t)2 * ld * sizeof(double2) + (dev ? 0 : (size_t)n1 * sizeof(double2)) + 1024;
+    int chunk = 0;
+    for (int p = n_pert; p >= 1; p = p > 8 ? p - (p + 7) / 8 : p - 1)
+        if ((size_t)p * stage_pp + pdep::chi0_work_bytes(c, p) <= kScratchBytes) {
+            chunk = p;
+            break;
+        }
+    PDEP_REQUIRE(chunk >= 1, PDEP_ENOMEM,
+                 "one perturbation needs " + std::to_string((stage_pp + pdep::chi0_work_bytes(c, 1)) >> 20) +
+                     " MiB of work space, beyond the " + std::to_string(kScratchBytes >> 20) +
+                     " MiB no-allocation scratch (N_v = " + std::to_string(c.nv) + ", N_pw = " +
+                     std::to_string(npw) + "): use chi0_apply");
+    c.opts.rhs_tile = chunk * c.nv;   // each pass is a single tile
+    pdep::ApplyStats as;
+    for (int p0 = 0; p0 < n_pert; p0 += chunk) {
+        const int np = std::min(chunk, n_pert - p0);
+        arena.reset();
+        double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)np * ld * sizeof(double2)));
+        double2* out_s = static_cast<double2*>(c.ws(C_OUT, (size_t)np * ld * sizeof(double2)));
+        const double2* src = reinterpret_cast<const double2*>(phi) + (size_t)p0 * n1;
+        double2* dst = reinterpret_cast<double2*>(out) + (size_t)p0 * n1;
+        if (dev) {
+            pdep::launch_expand_s1(np, npw, g0, src, n1, in_s, ld, s);
+        } else {
+            double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)np * n1 * sizeof(double2)));
+            PDEP_HIP(hipMemcpyAsync(stage, src, (size_t)np * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+            pdep::launch_expand_s1(np, npw, g0, stage, n1, in_s, ld, s);
+        }
+        pdep::chi0bar_sphere(c, np, in_s, out_s, as);
+        if (dev) {
+            pdep::launch_compact_s1(np, npw, g0, out_s, ld, dst, n1, s);
+        } else {
+            double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)np * n1 * sizeof(double2)));
+            pdep::launch_compact_s1(np, npw, g0, out_s, ld, stage, n1, s);
+            PDEP_HIP(hipMemcpyAsync(dst, stage, (size_t)np * n1 * sizeof(double2), hipMemcpyDeviceToHost, s));
+        }
+        PDEP_HIP(hipStreamSynchronize(s));   // the next pass reuses the scratch
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    fill_apply_stats(c, as, ms, st);
+    if (as.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
+    API_END
+}
+
 int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st) {
     API_BEGIN
     check_ctx(ctx);
@@ -279,18 +418,7 @@ int chi0_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_a
         PDEP_HIP(hipMemcpyAsync(out, stage, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyDeviceToHost, s));
     }
     const double ms = tm.stop();
-    if (st) {
-        st->n_rhs = as.n_rhs;
-        st->cg_iter_max = as.cg_iter_max;
-        st->cg_iter_total = as.cg_iter_total;
-        st->op_applications = as.op_applications;
-        st->refine_steps = as.refine_steps;
-        st->n_notconv = as.n_notconv;
-        st->max_rel_residual = as.max_rel_residual;
-        st->ms = ms;
-        st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
-        st->n_fp32_fallback_rows = as.n_fp32_fallback;
-    }
+    fill_apply_stats(c, as, ms, st);
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
     API_END
@@ -330,18 +458,7 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
         PDEP_HIP(hipMemcpyAsync(dn_r, stage, bytes, hipMemcpyDeviceToHost, s));
     }
     const double ms = tm.stop();
-    if (st) {
-        st->n_rhs = as.n_rhs;
-        st->cg_iter_max = as.cg_iter_max;
-        st->cg_iter_total = as.cg_iter_total;
-        st->op_applications = as.op_applications;
-        st->refine_steps = as.refine_steps;
-        st->n_notconv = as.n_notconv;
-        st->max_rel_residual = as.max_rel_residual;
-        st->ms = ms;
-        st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
-        st->n_fp32_fallback_rows = as.n_fp32_fallback;
-    }
+    fill_apply_stats(c, as, ms, st);
     if (as.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
     API_END

@@ -100,6 +100,15 @@ class ProfScope {
     bool active_ = false;
 };
 
+// While one exists on a thread, the launches of that thread are not timed (the
+// no-allocation entry point creates no events).
+struct ProfSuspend {
+    ProfSuspend();
+    ~ProfSuspend();
+    ProfSuspend(const ProfSuspend&) = delete;
+    ProfSuspend& operator=(const ProfSuspend&) = delete;
+};
+
 // ---------------------------------------------------------------- FFT geometry ---
 // Radix plan of one axis: n = prod(rad[0..nst)), radices in {2,3,4,8}.
 struct AxisPlan {
@@ -345,6 +354,34 @@ enum WsSlot : int {
     WS_COUNT = 36
 };
 
+// Work space carved from a fixed device region instead of the allocator (the
+// no-allocation entry point): each work-space slot keeps its region while requests fit
+// it and otherwise takes a new one behind the last; exhausting the region throws
+// PDEP_ENOMEM.  Contents are not kept when a slot moves (as with Buf::ensure).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    char* p[WS_COUNT] = {};
+    size_t n[WS_COUNT] = {};
+    void reset() {
+        used = 0;
+        for (int i = 0; i < WS_COUNT; ++i) { p[i] = nullptr; n[i] = 0; }
+    }
+    void* get(int i, size_t bytes) {
+        if (p[i] && n[i] >= bytes) return p[i];
+        const size_t off = (used + 255) / 256 * 256;
+        if (off > cap || bytes > cap - off)
+            throw Error(PDEP_ENOMEM, "no-allocation scratch of " + std::to_string(cap >> 20) +
+                                         " MiB exhausted (work-space slot " + std::to_string(i) + " needs " +
+                                         std::to_string(bytes) + " bytes, " + std::to_string(cap - std::min(off, cap)) +
+                                         " left)");
+        p[i] = base + off;
+        n[i] = bytes;
+        used = off + bytes;
+        return p[i];
+    }
+};
+
 struct Ctx {
     Ctx() = default;
     Ctx(const Ctx&) = delete;
@@ -373,7 +410,18 @@ struct Ctx {
     // refinement step: rows that diverge with them are solved again with FP32 products)
     bool pc_x3 = false;
     Buf w[WS_COUNT];
-    void* ws(int i, size_t bytes) { w[i].ensure(&al, bytes); return w[i].get(); }
+    // set for the duration of a no-allocation call: work space comes from it, the
+    // projection update avoids library GEMMs, and the chain block is not timed
+    Arena* arena = nullptr;
+    // complex elements of the split-K partial-product buffers of the projection GEMMs
+    size_t split_elems = (size_t)8 << 20;
+    void* ws(int i, size_t bytes) {
+        if (arena) return arena->get(i, bytes);
+        w[i].ensure(&al, bytes);
+        return w[i].get();
+    }
+    // the current region of work-space slot i (as last returned by ws)
+    void* ws_current(int i) const { return arena ? static_cast<void*>(arena->p[i]) : w[i].get(); }
     // rows per launch of the transform chain for FP32 / FP64 rows (0: not tuned yet)
     int fft_chunk32 = 0, fft_chunk64 = 0;
 };
@@ -398,6 +446,9 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
 void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st);
 // chi0bar on S (device, FP64, G0 entry ignored/zero): phi [npert][npw] -> out [npert][npw]
 void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st);
+// upper bound of the device work space chi0bar_sphere takes for npert perturbations in
+// one tile (opts.rhs_tile >= npert * N_v)
+size_t chi0_work_bytes(const Ctx& c, int npert);
 
 // capi.hip: pdep_setup with an optional caller-owned rocblas_handle (server workers)
 int setup_context(const pdep_cell* cell, const double* vloc, const pdep_opts* opts, const double* psi_in,

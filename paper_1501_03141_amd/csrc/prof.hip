@@ -70,10 +70,17 @@ const char* kNames[K_COUNT] = {"sphere_to_sticks", "slab_hv",    "sticks_to_sphe
 
 }  // namespace
 
+namespace {
+thread_local int g_suspended = 0;   // ProfSuspend scopes open on this thread
+}
+
+ProfSuspend::ProfSuspend() { ++g_suspended; }
+ProfSuspend::~ProfSuspend() { --g_suspended; }
+
 ProfScope::ProfScope(int kid, hipStream_t s, double bytes, double flops)
     : kid_(kid), s_(s), bytes_(bytes), flops_(flops) {
     Profiler& p = prof();
-    if (!p.on || !((p.mask >> kid) & 1u)) return;
+    if (!p.on || !((p.mask >> kid) & 1u) || g_suspended > 0) return;
     std::lock_guard<std::mutex> g(p.mu);
     a_ = p.ev();
     b_ = p.ev();

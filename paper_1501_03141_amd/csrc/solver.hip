@@ -108,7 +108,7 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv, nh = half_len(npw);
     const long lds = coef_ld(nv);
     cplx<T>* St = reinterpret_cast<cplx<T>*>(S);
-    const size_t split_elems = (size_t)8 << 20;    // split-K partial products (complex elements)
+    const size_t split_elems = c.split_elems;    // split-K partial products (complex elements)
     cplx<T>* work = static_cast<cplx<T>*>(c.ws(W_SPLIT, split_elems * sizeof(cplx<T>)));
     if constexpr (sizeof(T) == sizeof(double)) {
         // Real coefficients over half spheres.  S = Re(Psi_w^H Y) by the split-K MFMA GEMM
@@ -118,6 +118,12 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
         if (nrows <= 0) return;
         launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
                            true);
+        if (c.arena) {
+            // no library calls (rocBLAS may allocate device memory): the MFMA update
+            launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream,
+                                  true);
+            return;
+        }
         // the real parts, contiguous, in the split-K buffer (free once the GEMM is done),
         // in blocks of rows that fit it
         double* Sr = reinterpret_cast<double*>(work);
@@ -232,7 +238,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
     }
     int& tuned = fft_chunk_of<T>(c);
     if (tuned == 0) tuned = fft_chunk_env(sizeof(T) == sizeof(double));
-    if (tuned == 0 && nrows >= kTuneRows) {
+    if (tuned == 0 && nrows >= kTuneRows && !c.arena) {   // timing needs events (no-allocation calls skip it)
         const int rule = fft_chunk_rule<T>(c);
         std::vector<int> cand;
         for (int v : {rule / 2, (3 * rule) / 4, rule, (3 * rule) / 2, 2 * rule, nrows}) {
@@ -488,7 +494,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                 float* alpha = beta + n;
                 if constexpr (sizeof(T) == sizeof(float)) {
                     float* Sr = reinterpret_cast<float*>(S);
-                    float* wr = static_cast<float*>(c.ws(W_SPLIT, ((size_t)8 << 20) * sizeof(float2)));
+                    float* wr = static_cast<float*>(c.ws(W_SPLIT, c.split_elems * sizeof(float2)));
                     const long lp = sphere_ld(c.basis.npw), lds = coef_ld(nv);
                     if (nv <= 128) {
                         // r -= alpha q and its inner products inside the coefficient GEMM
@@ -506,13 +512,13 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                         cs.beta = beta;
                         cs.count = sc.n_active;   // cleared here for the check below
                         launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
-                                                (size_t)16 << 20, s, kin, sh, kPrecondFloor, cs, nblk);
+                                                2 * c.split_elems, s, kin, sh, kPrecondFloor, cs, nblk);
                     } else {
                         launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active,
                                            kin, sh, ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta,
                                            alpha);
                         launch_gemm_ahb_x3_real(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
-                                                (size_t)16 << 20, s, kin, sh, kPrecondFloor);
+                                                2 * c.split_elems, s, kin, sh, kPrecondFloor);
                     }
                     launch_cg_direction_x3(nv, ncur, npw, psi_of<T>(c), lp, Sr, lds, r, ld, kin, sh, kPrecondFloor,
                                            beta, alpha, xout, sc.s_id[0], sc.active, p, ld, s);
@@ -550,7 +556,7 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     return it;
 }
 
-template <typename T> cplx<T>* cg_solution(Ctx& c) { return c.w[W_XOUT].as<cplx<T>>(); }
+template <typename T> cplx<T>* cg_solution(Ctx& c) { return static_cast<cplx<T>*>(c.ws_current(W_XOUT)); }
 
 }  // namespace
 
@@ -710,6 +716,21 @@ size_t row_bytes(const Ctx& c, long ld) {
     return (size_t)ld * sizeof(double2) * 5 + (size_t)ld * inner * 6 + sticks_row_bytes(c) +
            (size_t)c.nv * sizeof(double2) + 128;
 }
+
+}  // namespace
+
+// Device work space of chi0bar_sphere on npert perturbations run as one tile (an upper
+// bound): the per-row bound above for every Sternheimer system, the potential and
+// density grids, the split-K buffer and the smaller sticks block of the perturbation
+// preparation that precedes the tile's.
+size_t chi0_work_bytes(const Ctx& c, int npert) {
+    const long ld = sphere_ld(c.basis.npw);
+    const size_t per_pert = (size_t)c.nv * (row_bytes(c, ld) + 1024) + 2 * (size_t)c.basis.ng * sizeof(double);
+    return (size_t)npert * per_pert + c.split_elems * sizeof(double2) +
+           (size_t)std::min(npert, 256) * sticks_row_bytes(c) + ((size_t)1 << 20);
+}
+
+namespace {
 
 int perturbation_tile(Ctx& c, int npert, long ld) {
     if (c.opts.rhs_tile > 0)

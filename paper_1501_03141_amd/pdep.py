@@ -149,6 +149,7 @@ def load(path: str = LIB_PATH):
     lib.pdep_get_orbitals.argtypes = [P, P, P]
     lib.chi0_apply.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.chi0_apply_raw.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
+    lib.chi0_apply_noalloc.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.pdep_eigs.argtypes = [P, C.c_int, C.c_uint64, P, C.POINTER(EigOpts), D, P, C.POINTER(EigStats)]
     lib.pdep_destroy.argtypes = [P]
     lib.pdep_profile_enable.argtypes = [C.c_int]
@@ -169,7 +170,7 @@ def load(path: str = LIB_PATH):
                  "pdep_server_destroy"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
-                 "chi0_apply_raw", "pdep_eigs", "pdep_destroy"):
+                 "chi0_apply_raw", "chi0_apply_noalloc", "pdep_eigs", "pdep_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -342,6 +343,19 @@ class Context:
         o, keep_o = self._ptr(out, np.complex128, shape, out=True)
         st = ApplyStats()
         _check(self._lib.chi0_apply(self._h, n_pert, p, o, C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        return (keep_o if not self.device_ptrs else out), st.as_dict()
+
+    def chi0_apply_noalloc(self, phi, out=None, allow_notconv=False):
+        """chi0_apply through the entry point that allocates no device memory."""
+        n_pert = int(phi.shape[0])
+        shape = (n_pert, self.n_pw - 1)
+        p, keep = self._ptr(phi, np.complex128, shape)
+        if out is None:
+            out = self._new(np.complex128, shape)
+        o, keep_o = self._ptr(out, np.complex128, shape, out=True)
+        st = ApplyStats()
+        _check(self._lib.chi0_apply_noalloc(self._h, n_pert, p, o, C.byref(st)),
                allow=(PDEP_ENOTCONV,) if allow_notconv else ())
         return (keep_o if not self.device_ptrs else out), st.as_dict()
 
