@@ -15,7 +15,10 @@ point, doubly occupied bands):
   symmetrised form of Eq. symmoperator);
 * sum-over-states (Adler-Wiser at omega = 0, q = 0 body, Eq. AdlerWiser) as a second,
   independent route to the same response;
-* PDEP eigenpairs = lowest eigenpairs of chi0bar (Eq. eigendecompzerofreq).
+* PDEP eigenpairs = lowest eigenpairs of chi0bar (Eq. eigendecompzerofreq);
+* the reducible chibar = (1 - chi0bar)^-1 chi0bar (Eq. linearalgebrachichi0) and, as a
+  second route, the self-consistent DFPT loop with the Hartree response (Eqs. LF and
+  LFHartree, Fig. pdepscheme right panel); eps^-1 = 1 + chibar (Eq. epsilonandchi).
 
 Modules:
   planewave  -- sphere, grid, naive DFT, dense H

@@ -298,3 +298,58 @@ def subspace_iteration(model: Model, gs: GroundState, X0: np.ndarray, n_iter: in
         Lc = np.linalg.cholesky(S)
         X = np.linalg.solve(Lc, X)
     return lam_old, n_iter
+
+
+# --- reducible polarizability (RPA, Hartree term only) -------------------------------------
+
+def chibar_from_chi0bar(M: np.ndarray) -> np.ndarray:
+    """The reducible symmetrised polarizability from the irreducible one by linear algebra
+    (Eq. linearalgebrachichi0): chibar = (1 - chi0bar)^{-1} chi0bar, M a square matrix of
+    chi0bar in any orthonormal basis."""
+    return np.linalg.solve(np.eye(M.shape[0]) - M, M)
+
+
+def hartree_potential(model: Model, dnG: np.ndarray) -> np.ndarray:
+    """Linear change of the Hartree potential (Eq. LFHartree) in G space on S':
+    dV_H(G) = 4 pi dn(G) / |G|^2 (Hartree units, e^2 = 1)."""
+    return model.coul[None, :] ** 2 * dnG
+
+
+def chibar_apply_scf(model: Model, gs: GroundState, phi: np.ndarray, tol: float = 1e-12,
+                     maxit: int = 500, mixing: float = 0.4):
+    """Reducible chibar on a block phi [k, N_pw'] by the self-consistent DFPT loop of
+    Fig. pdepscheme (right panel): the Sternheimer perturbation is the applied potential
+    phi~ plus the linear change of the Hartree potential of the density response (the
+    Hartree term of Eq. LF, Eq. LFHartree; RPA), dV_H(G) = 4 pi dn(G)/|G|^2, taken on S'
+    like the potentials themselves.  Each pass solves the Sternheimer equations for the
+    current total perturbation, forms dn (Eq. deltani) and its Hartree potential, and
+    mixes it linearly into the next perturbation; at self-consistency sqrt(4 pi)/|G|
+    dn(G) on S' is chibar phi (Eq. chiisamatrixinpdep with the screened response).  A
+    pass multiplies the error by 1 - mixing (1 - lambda) on each eigenvector of chi0bar,
+    so the loop converges for mixing < 2 / eps_max (eps_max = 1 - lambda_min).  Returns
+    (chibar phi [k, N_pw'], passes)."""
+    phi = np.atleast_2d(phi)
+    coul = model.coul[None, :]                     # sqrt(4 pi)/|G| on S'
+    vH = np.zeros_like(phi, dtype=np.complex128)   # Hartree potential on S'
+    out = None
+    for it in range(1, maxit + 1):
+        pert = phi * coul + vH                     # phi~ + dV_H
+        full = np.zeros((phi.shape[0], model.n_pw), dtype=np.complex128)
+        full[:, model.nz] = pert
+        dV = np.real(model.inv(full))
+        dn = np.stack([chi0_real(model, gs, dV[i]) for i in range(phi.shape[0])])
+        dnG = model.fwd(dn.astype(np.complex128))[:, model.nz]
+        vH_new = hartree_potential(model, dnG)
+        new = coul * dnG
+        if out is not None and np.max(np.linalg.norm(new - out, axis=1) / np.linalg.norm(new, axis=1)) <= tol:
+            return new, it
+        out = new
+        vH = (1.0 - mixing) * vH + mixing * vH_new
+    return out, maxit
+
+
+def eps_inverse_eigenvalues(lam: np.ndarray) -> np.ndarray:
+    """Eigenvalues of the inverse dielectric matrix from those of chi0bar: chibar has the
+    eigenvalues lambda / (1 - lambda) on the same eigenvectors (Eq. linearalgebrachichi0)
+    and eps^-1 = 1 + chibar (Eq. epsilonandchi), hence 1 / (1 - lambda)."""
+    return 1.0 / (1.0 - np.asarray(lam))

@@ -421,3 +421,74 @@ def test_free_electron_golden_fixture():
         phi[0, index[tuple(-x for x in g)]] = 1.0     # Hermitian symmetric (a cosine wave)
         out = R.chi0bar_apply(m, gs, phi)
         assert np.max(np.abs(out - lam * phi)) <= 1e-12 * abs(lam)
+
+
+# --- reducible polarizability (Hartree-only self-consistency) -----------------------------
+
+def _reducible_by_linear_algebra(m, M, phi):
+    """chibar phi from the dense chi0bar matrix M in the real basis (Eq. linearalgebrachichi0)."""
+    Bm = R.real_basis(m)
+    a = np.real(Bm.conj() @ phi.T)                 # coordinates of the rows of phi
+    return (R.chibar_from_chi0bar(M) @ a).T @ Bm
+
+
+def test_scf_loop_equals_linear_algebra(tiny, tiny_pdep):
+    """Two routes to the reducible chibar: the self-consistent DFPT loop with the Hartree
+    response (Sternheimer solves for phi~ + dV_H until self-consistent) and the linear
+    algebra (1 - chi0bar)^-1 chi0bar on the full chi0bar matrix."""
+    m, gs = tiny
+    _, _, M = tiny_pdep
+    phi = inputs.trial_block(m.miller[m.nz], 2, 21)
+    got, passes = R.chibar_apply_scf(m, gs, phi, tol=1e-13)
+    want = _reducible_by_linear_algebra(m, M, phi)
+    print("scf passes", passes)
+    assert np.max(np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)) <= 1e-11
+
+
+def test_reducible_free_electron_closed_form():
+    """V = 0, one occupied state: chi0bar is diagonal with lambda_G = -32 pi/(Omega |G|^4),
+    so chibar = lambda/(1 - lambda) = -32 pi / (Omega |G|^4 + 32 pi) on each plane-wave
+    cosine; the self-consistent loop (with mixing 0.5) reproduces it."""
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, np.zeros(TINY.n))
+    gs = R.ground_state(m, 1, full=True)
+    sp = m.miller[m.nz]
+    index = {tuple(int(x) for x in g): i for i, g in enumerate(sp)}
+    G2 = 2 * m.kin[m.nz]
+    for g in [(1, 0, 0), (0, 1, 1), (2, -1, 0)]:
+        k = index[g]
+        phi = np.zeros((1, sp.shape[0]), dtype=complex)
+        phi[0, k] = 1.0
+        phi[0, index[tuple(-x for x in g)]] = 1.0
+        mu = -32 * math.pi / (m.volume * G2[k] ** 2 + 32 * math.pi)
+        out, _ = R.chibar_apply_scf(m, gs, phi, tol=1e-14, mixing=0.5)
+        assert np.max(np.abs(out - mu * phi)) <= 1e-12 * abs(mu)
+
+
+def test_eps_inverse_eigenvalues(tiny, tiny_pdep):
+    """The eigenvalues of eps^-1 = 1 + chibar (Eq. epsilonandchi), from the dense chibar,
+    are 1/(1 - lambda) of the chi0bar eigenvalues; all lie in (0, 1]."""
+    _, _, M = tiny_pdep
+    mu = np.linalg.eigvalsh(0.5 * (R.chibar_from_chi0bar(M) + R.chibar_from_chi0bar(M).T))
+    lam = np.linalg.eigvalsh(M)
+    assert np.max(np.abs(np.sort(1.0 + mu) - np.sort(R.eps_inverse_eigenvalues(lam)))) <= 1e-12
+    assert np.all(R.eps_inverse_eigenvalues(lam) > 0) and np.all(R.eps_inverse_eigenvalues(lam) <= 1 + 1e-12)
+
+
+want_of = _reducible_by_linear_algebra
+
+
+@pytest.mark.parametrize("bad", ["sign", "no4pi"])
+def test_mutation_hartree_term_caught(tiny, tiny_pdep, monkeypatch, bad):
+    """A Hartree response with the wrong sign, or without the 4 pi / |G|^2 kernel, breaks
+    the agreement of the self-consistent loop with the linear algebra."""
+    m, gs = tiny
+    _, _, M = tiny_pdep
+    real = R.hartree_potential
+    wrong = {"sign": lambda model, dnG: -real(model, dnG),
+             "no4pi": lambda model, dnG: dnG}[bad]
+    monkeypatch.setattr(R, "hartree_potential", wrong)
+    phi = inputs.trial_block(m.miller[m.nz], 1, 22)
+    with np.errstate(all="ignore"):
+        got, _ = R.chibar_apply_scf(m, gs, phi, tol=1e-12, maxit=200, mixing=0.4)
+        err = np.max(np.linalg.norm(got - want_of(m, M, phi), axis=1) / np.linalg.norm(want_of(m, M, phi), axis=1))
+    assert not err <= 1e-3          # a diverged loop (inf / nan) also fails the pin
