@@ -144,10 +144,16 @@ typedef struct {
 } pdep_apply_stats;
 
 typedef struct {
-    double tol;           /* converged when every wanted residual ||chi0bar x - l x|| <= tol */
+    double tol;           /* converged when every wanted residual ||A x - l x|| <= tol */
     int maxit;            /* Davidson iteration cap */
-    int max_subspace;     /* restart size (columns); 0 = 4 * n_pdep */
+    int max_subspace;     /* restart size (columns); 0 = 4 * n_pdep; else >= 2 (n_pdep + n_buffer) */
     int n_buffer;         /* extra unreported vectors carried for faster convergence */
+    int reducible;        /* 0: A = chi0bar (Fig. pdepscheme, left panel); 1: A = the reducible
+                             chibar, each application made self-consistent with the Hartree
+                             response as in chibar_apply (right panel) */
+    double scr_tol;       /* reducible: self-consistency tolerance of each application
+                             (0: tol / 10) */
+    int scr_maxit;        /* reducible: cap on self-consistency passes (0: 200) */
 } pdep_eig_opts;
 
 typedef struct {
@@ -157,9 +163,21 @@ typedef struct {
     long long cg_iter_total;
     double ms;
     int n_notconv;                /* Sternheimer systems that missed cg_tol, summed over every
-                                     chi0bar application; > 0 makes pdep_eigs return
-                                     PDEP_ENOTCONV (outputs still filled) */
+                                     chi0bar application, plus (reducible) columns whose
+                                     self-consistency missed scr_tol; > 0 makes pdep_eigs
+                                     return PDEP_ENOTCONV (outputs still filled) */
+    int scr_passes;               /* reducible: self-consistency passes, summed */
 } pdep_eig_stats;
+
+typedef struct {
+    int passes;                   /* self-consistency passes (chi0bar applications to the block) */
+    long long chi0_columns;       /* chi0bar columns computed */
+    int n_notconv;                /* columns that missed tol within maxit passes */
+    double max_rel_residual;      /* max over columns of ||phi - (1 - chi0bar) y|| / ||phi|| */
+    long long cg_iter_total;      /* Sternheimer CG iterations, summed */
+    int cg_notconv;               /* Sternheimer systems that missed cg_tol */
+    double ms;
+} pdep_chibar_stats;
 
 typedef struct pdep_ctx pdep_ctx;
 
@@ -220,13 +238,33 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
  * library serialises them within the process. */
 int chi0_apply_noalloc(pdep_ctx* ctx, int n_pert, const double* phi, double* out, pdep_apply_stats* st);
 
+/* The reducible symmetrised polarizability chibar = (1 - chi0bar)^-1 chi0bar of the RPA
+ * (Eq. linearalgebrachichi0) applied to n_pert potentials phi (n_pert x N_pw' complex,
+ * Hermitian-symmetric rows on S'; out: same shape), without a PDEP basis: the
+ * Sternheimer perturbation of each column is phi~ plus the Hartree potential of the
+ * density response it induces (Eq. LF with the Hartree term only, Eq. LFHartree,
+ * dV_H(G) = 4 pi dn(G)/|G|^2 on S'), made self-consistent (Fig. pdepscheme, right
+ * panel) by conjugate gradients on (1 - chi0bar) y = phi, chibar phi = y - phi, until
+ * ||phi - (1 - chi0bar) y|| <= tol ||phi|| (tol > 0; every pass is one chi0bar
+ * application to the unconverged columns, with the context's precision and cg_tol,
+ * which should lie well below tol).  The inverse dielectric matrix is
+ * eps^-1 = 1 + chibar (Eq. epsilonandchi).  PDEP_ENOTCONV if a column misses tol within
+ * maxit passes or a Sternheimer solve misses cg_tol (outputs and stats still filled).
+ * st may be NULL. */
+int chibar_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, double tol, int maxit,
+                 pdep_chibar_stats* st);
+
 /* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
  * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
  * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own
  * SplitMix64 + Box-Muller generator) or n_pdep x N_pw' complex Hermitian-symmetric
  * start vectors.  eps_out: n_pdep dielectric eigenvalues 1 - lambda_i, descending.
  * basis_out: NULL or n_pdep x N_pw' complex eigenvectors in the same order.
- * eo may be NULL (tol 1e-9, maxit 60, restart 4 n_pdep, no buffer). */
+ * eo may be NULL (tol 1e-9, maxit 60, restart 4 n_pdep, no buffer, chi0bar).
+ * With eo->reducible the iteration diagonalises chibar instead (Fig. pdepscheme, right
+ * panel); it has the same eigenvectors, eigenvalues mu_i = lambda_i / (1 - lambda_i)
+ * (Eq. linearalgebrachichi0), and eps_out receives the same dielectric eigenvalues,
+ * 1 / (1 + mu_i); the eigenvalues of eps^-1 are 1 / eps_i. */
 int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0,
               const pdep_eig_opts* eo, double* eps_out, double* basis_out, pdep_eig_stats* st);
 

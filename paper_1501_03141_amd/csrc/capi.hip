@@ -464,6 +464,57 @@ int chi0_apply_raw(pdep_ctx* ctx, int n_pert, const double* dv_r, double* dn_r, 
     API_END
 }
 
+int chibar_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, double tol, int maxit,
+                 pdep_chibar_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    PDEP_REQUIRE(n_pert >= 0, PDEP_EINVAL, "n_pert must be >= 0");
+    PDEP_REQUIRE(tol > 0 && tol < 1 && maxit >= 1, PDEP_EINVAL, "bad self-consistency tolerance / cap");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (n_pert == 0) { g_err.clear(); return PDEP_OK; }
+    PDEP_REQUIRE(phi && out, PDEP_EINVAL, "null phi/out");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)n_pert * ld * sizeof(double2)));
+    double2* out_s = static_cast<double2*>(c.ws(C_OUT, (size_t)n_pert * ld * sizeof(double2)));
+    if (dev) {
+        pdep::launch_expand_s1(n_pert, npw, g0, reinterpret_cast<const double2*>(phi), n1, in_s, ld, s);
+    } else {
+        PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pert * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+        pdep::launch_expand_s1(n_pert, npw, g0, stage, n1, in_s, ld, s);
+    }
+    pdep::ApplyStats as;
+    const pdep::ScreenResult r = pdep::chibar_sphere(c, n_pert, in_s, out_s, tol, maxit, as);
+    if (dev) {
+        pdep::launch_compact_s1(n_pert, npw, g0, out_s, ld, reinterpret_cast<double2*>(out), n1, s);
+    } else {
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        pdep::launch_compact_s1(n_pert, npw, g0, out_s, ld, stage, n1, s);
+        PDEP_HIP(hipMemcpyAsync(out, stage, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    const double ms = tm.stop();
+    if (st) {
+        st->passes = r.passes;
+        st->chi0_columns = r.chi0_columns;
+        st->n_notconv = r.n_notconv;
+        st->max_rel_residual = r.max_rel_residual;
+        st->cg_iter_total = as.cg_iter_total;
+        st->cg_notconv = as.n_notconv;
+        st->ms = ms;
+    }
+    if (r.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(r.n_notconv) + " columns missed the self-consistency tolerance");
+    if (as.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(as.n_notconv) + " Sternheimer systems missed cg_tol");
+    API_END
+}
+
 int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, const pdep_eig_opts* eo_in,
               double* eps_out, double* basis_out, pdep_eig_stats* st) {
     API_BEGIN
@@ -473,12 +524,13 @@ int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, cons
     const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
     PDEP_REQUIRE(n_pdep >= 1 && n_pdep < n1, PDEP_EINVAL, "n_pdep out of range");
     pdep_eig_opts eo;
+    std::memset(&eo, 0, sizeof(eo));
     eo.tol = 1e-9;
     eo.maxit = 60;
-    eo.max_subspace = 0;
-    eo.n_buffer = 0;
     if (eo_in) eo = *eo_in;
-    PDEP_REQUIRE(eo.tol > 0 && eo.maxit >= 1 && eo.n_buffer >= 0, PDEP_EINVAL, "bad eig options");
+    PDEP_REQUIRE(eo.tol > 0 && eo.maxit >= 1 && eo.n_buffer >= 0 && eo.scr_tol >= 0 && eo.scr_maxit >= 0 &&
+                     (eo.reducible == 0 || eo.reducible == 1),
+                 PDEP_EINVAL, "bad eig options");
     if (st) std::memset(st, 0, sizeof(*st));
     const long ld = pdep::sphere_ld(npw);
     const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
@@ -502,7 +554,8 @@ int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, cons
     std::vector<double> lam(n_pdep);
     pdep::EigResult r = pdep::pdep_davidson(c, n_pdep, seed, phi0 ? phi0_s.as<double2>() : nullptr, eo, lam.data(),
                                             basis_out ? basis_s.as<double2>() : nullptr);
-    for (int i = 0; i < n_pdep; ++i) eps_out[i] = 1.0 - lam[i];
+    // chi0bar: eps = 1 - lambda; chibar: eps^-1 = 1 + mu
+    for (int i = 0; i < n_pdep; ++i) eps_out[i] = eo.reducible ? 1.0 / (1.0 + lam[i]) : 1.0 - lam[i];
     if (basis_out) {
         if (dev) {
             pdep::launch_compact_s1(n_pdep, npw, g0, basis_s.as<double2>(), ld, reinterpret_cast<double2*>(basis_out),
@@ -521,12 +574,16 @@ int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, cons
         st->max_residual = r.max_residual;
         st->cg_iter_total = r.cg_iter_total;
         st->ms = ms;
-        st->n_notconv = r.n_notconv;
+        st->n_notconv = r.n_notconv + r.scr_notconv;
+        st->scr_passes = r.scr_passes;
     }
     if (!r.converged) return fail(PDEP_ENOTCONV, "PDEP Davidson did not reach tol");
     if (r.n_notconv > 0)
         return fail(PDEP_ENOTCONV, std::to_string(r.n_notconv) +
                                        " Sternheimer systems of the chi0bar applications missed cg_tol");
+    if (r.scr_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(r.scr_notconv) +
+                                       " chibar applications missed the self-consistency tolerance");
     API_END
 }
 

@@ -584,9 +584,21 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
     int m = orthonormalise(c, ws, sv, nullptr, 0, V, nb, ld, true);
     PDEP_REQUIRE(m == nb, PDEP_EINVAL, "start vectors are linearly dependent");
     ApplyStats st;
-    chi0bar_sphere(c, m, V, AV, st);
+    // the operator: chi0bar, or the reducible chibar made self-consistent per application
+    const double scr_tol = eo.scr_tol > 0.0 ? eo.scr_tol : 0.1 * eo.tol;
+    const int scr_maxit = eo.scr_maxit > 0 ? eo.scr_maxit : 200;
+    auto apply = [&](int n, const double2* X, double2* AX) {
+        if (eo.reducible) {
+            const ScreenResult r = chibar_sphere(c, n, X, AX, scr_tol, scr_maxit, st);
+            res.scr_passes += r.passes;
+            res.scr_notconv += r.n_notconv;
+            return (int)r.chi0_columns;
+        }
+        chi0bar_sphere(c, n, X, AX, st);
+        return n;
+    };
+    res.columns += apply(m, V, AV);
     check_finite_rows(c, ws, AV, m, ld, "chi0bar applied to the start block");
-    res.columns += m;
     std::vector<double> theta;
     double maxres = 0.0;
     int it;
@@ -633,9 +645,8 @@ EigResult pdep_davidson(Ctx& c, int npdep, uint64_t seed, const double2* phi0_de
         const int kept = orthonormalise(c, ws, sv, V, m, T, nt, ld, true);
         if (kept == 0) break;
         PDEP_HIP(hipMemcpyAsync(V + (size_t)m * ld, T, (size_t)kept * ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        chi0bar_sphere(c, kept, V + (size_t)m * ld, AV + (size_t)m * ld, st);
+        res.columns += apply(kept, V + (size_t)m * ld, AV + (size_t)m * ld);
         check_finite_rows(c, ws, AV + (size_t)m * ld, kept, ld, "chi0bar applied to the expansion vectors");
-        res.columns += kept;
         m += kept;
     }
     res.iterations = std::min(it, eo.maxit);

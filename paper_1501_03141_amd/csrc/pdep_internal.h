@@ -351,7 +351,8 @@ enum WsSlot : int {
     WS_SOLVER_END = 28,
     WS_CAPI_IN = 28, WS_CAPI_OUT = 29, WS_CAPI_STAGE = 30,
     WS_SETUP_STICKS = 31, WS_DAV_THETA = 32, WS_DAV_C = 33, WS_DAV_DOTS = 34,
-    WS_COUNT = 36
+    WS_SCR_Y = 35,            // screening.hip: 35 .. 41
+    WS_COUNT = 42
 };
 
 // Work space carved from a fixed device region instead of the allocator (the
@@ -458,6 +459,17 @@ int setup_context(const pdep_cell* cell, const double* vloc, const pdep_opts* op
 size_t job_hbm_estimate(const pdep_cell& cell, const pdep_opts& o, int n_pdep, const pdep_eig_opts& eo,
                         size_t* chi0_budget);
 
+// screening.hip: chibar = (1 - chi0bar)^-1 chi0bar on n potentials on S (device, FP64,
+// rows of stride sphere_ld(npw), G = 0 entry zero), self-consistent to tol ||phi||
+struct ScreenResult {
+    int passes = 0;               // chi0bar applications to the block (self-consistency passes)
+    long long chi0_columns = 0;   // chi0bar columns computed
+    int n_notconv = 0;            // columns that missed tol within maxit passes
+    double max_rel_residual = 0.0;
+};
+ScreenResult chibar_sphere(Ctx& c, int n, const double2* phi, double2* out, double tol, int maxit,
+                           ApplyStats& st);
+
 // davidson.hip
 void ground_state(Ctx& c);
 // orbitals -> Hermitian-symmetric (real in r) Ritz vectors of the same subspace
@@ -465,6 +477,7 @@ void realify_orbitals(Ctx& c);
 struct EigResult {
     int iterations = 0, columns = 0;
     int n_notconv = 0;                    // Sternheimer systems that missed cg_tol (all chi0 applications)
+    int scr_passes = 0, scr_notconv = 0;  // reducible: self-consistency passes, columns that missed scr_tol
     double max_residual = 0.0;
     long long cg_iter_total = 0;
     bool converged = false;

@@ -243,8 +243,9 @@ int pdep_submit(pdep_server* S, const pdep_job* job, uint64_t* ticket) {
         PDEP_REQUIRE(job->vloc != nullptr, PDEP_EINVAL, "null vloc");
         PDEP_REQUIRE(job->opts.n_v >= 1, PDEP_EINVAL, "n_v must be >= 1");
         PDEP_REQUIRE(job->n_pdep >= 1, PDEP_EINVAL, "n_pdep must be >= 1");
-        PDEP_REQUIRE(job->eig.tol > 0 && job->eig.maxit >= 1 && job->eig.n_buffer >= 0, PDEP_EINVAL,
-                     "bad eig options");
+        PDEP_REQUIRE(job->eig.tol > 0 && job->eig.maxit >= 1 && job->eig.n_buffer >= 0 && job->eig.scr_tol >= 0 &&
+                         job->eig.scr_maxit >= 0 && (job->eig.reducible == 0 || job->eig.reducible == 1),
+                     PDEP_EINVAL, "bad eig options");
         PDEP_REQUIRE(job->eig.max_subspace <= 0 || job->eig.max_subspace >= 2 * (job->n_pdep + job->eig.n_buffer),
                      PDEP_EINVAL, "max_subspace must be 0 or at least 2 (n_pdep + n_buffer)");
         j->est = pdep::job_hbm_estimate(job->cell, job->opts, job->n_pdep, job->eig, &j->chi0_budget);

@@ -78,12 +78,23 @@ class ApplyStats(C.Structure):
 
 
 class EigOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("max_subspace", C.c_int), ("n_buffer", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("max_subspace", C.c_int), ("n_buffer", C.c_int),
+                ("reducible", C.c_int), ("scr_tol", C.c_double), ("scr_maxit", C.c_int)]
 
 
 class EigStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("chi0_columns", C.c_int), ("max_residual", C.c_double),
-                ("cg_iter_total", C.c_longlong), ("ms", C.c_double), ("n_notconv", C.c_int)]
+                ("cg_iter_total", C.c_longlong), ("ms", C.c_double), ("n_notconv", C.c_int),
+                ("scr_passes", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ChibarStats(C.Structure):
+    _fields_ = [("passes", C.c_int), ("chi0_columns", C.c_longlong), ("n_notconv", C.c_int),
+                ("max_rel_residual", C.c_double), ("cg_iter_total", C.c_longlong), ("cg_notconv", C.c_int),
+                ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -151,6 +162,7 @@ def load(path: str = LIB_PATH):
     lib.chi0_apply_raw.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.chi0_apply_noalloc.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.pdep_eigs.argtypes = [P, C.c_int, C.c_uint64, P, C.POINTER(EigOpts), D, P, C.POINTER(EigStats)]
+    lib.chibar_apply.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(ChibarStats)]
     lib.pdep_destroy.argtypes = [P]
     lib.pdep_profile_enable.argtypes = [C.c_int]
     lib.pdep_profile_enable.restype = C.c_int
@@ -170,7 +182,7 @@ def load(path: str = LIB_PATH):
                  "pdep_server_destroy"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
-                 "chi0_apply_raw", "chi0_apply_noalloc", "pdep_eigs", "pdep_destroy"):
+                 "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_eigs", "pdep_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -371,9 +383,24 @@ class Context:
                allow=(PDEP_ENOTCONV,) if allow_notconv else ())
         return (keep_o if not self.device_ptrs else out), st.as_dict()
 
+    def chibar_apply(self, phi, tol=1e-9, maxit=200, out=None, allow_notconv=False):
+        """The reducible chibar (Hartree-only self-consistent response) applied to the rows
+        of phi [n_pert, N_pw - 1]; returns (result, stats)."""
+        n_pert = int(phi.shape[0])
+        shape = (n_pert, self.n_pw - 1)
+        p, keep = self._ptr(phi, np.complex128, shape)
+        if out is None:
+            out = self._new(np.complex128, shape)
+        o, keep_o = self._ptr(out, np.complex128, shape, out=True)
+        st = ChibarStats()
+        _check(self._lib.chibar_apply(self._h, n_pert, p, o, float(tol), int(maxit), C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        return (keep_o if not self.device_ptrs else out), st.as_dict()
+
     def eigs(self, n_pdep, seed=0, phi0=None, tol=1e-9, maxit=60, max_subspace=0, n_buffer=0,
-             want_basis=False, allow_notconv=False):
-        """PDEP: (eps descending [n_pdep], basis [n_pdep, N_pw-1] or None, stats)."""
+             want_basis=False, allow_notconv=False, reducible=False, scr_tol=0.0, scr_maxit=0):
+        """PDEP: (eps descending [n_pdep], basis [n_pdep, N_pw-1] or None, stats).  With
+        reducible=True the Davidson iteration runs on chibar; eps is the same quantity."""
         eps = np.empty(n_pdep, dtype=np.float64)
         p0 = None
         keep = None
@@ -384,7 +411,8 @@ class Context:
         keep_b = None
         if basis is not None:
             bptr, keep_b = self._ptr(basis, np.complex128, (n_pdep, self.n_pw - 1), out=True)
-        eo = EigOpts(float(tol), int(maxit), int(max_subspace), int(n_buffer))
+        eo = EigOpts(float(tol), int(maxit), int(max_subspace), int(n_buffer), 1 if reducible else 0,
+                     float(scr_tol), int(scr_maxit))
         st = EigStats()
         _check(self._lib.pdep_eigs(self._h, int(n_pdep), C.c_uint64(int(seed)), p0, C.byref(eo),
                                    eps.ctypes.data_as(C.POINTER(C.c_double)), bptr, C.byref(st)),
@@ -435,7 +463,7 @@ class Server:
         v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
         job = Job(Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut)),
                   v.ctypes.data, o, int(n_pdep), C.c_uint64(int(seed)),
-                  EigOpts(float(eig_tol), int(eig_maxit), int(max_subspace), int(n_buffer)))
+                  EigOpts(float(eig_tol), int(eig_maxit), int(max_subspace), int(n_buffer), 0, 0.0, 0))
         t = C.c_uint64()
         _check(self._lib.pdep_submit(self._h, C.byref(job), C.byref(t)))
         self._keep[t.value] = int(n_pdep)
