@@ -261,6 +261,7 @@ def main():
                     help="mixed mode of the timed steps (the other one is timed once beside it)")
     ap.add_argument("--no-other-mode", action="store_true")
     ap.add_argument("--no-eigs", action="store_true", help="skip the end-to-end PDEP Davidson")
+    ap.add_argument("--no-graphs", action="store_true", help="skip the HIP-graph replay of the inner CG")
     ap.add_argument("--serving-jobs", type=int, default=48, help="0 disables the serving phase")
     ap.add_argument("--serving-max-running", type=int, default=4)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -350,6 +351,21 @@ def main():
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes/launch"
         roof["traffic_over_algorithmic"] = round(roof["traffic"] / max(roof["algorithmic_bytes_per_launch"], 1), 3)
+    # ---- the same steps with the inner CG replayed as HIP graphs, beside eager steps
+    # without kernel events (graph mode is off while the profiler times launches)
+    graphs = None
+    if not args.no_graphs:
+        ms_e, _, _ = run_steps(ctx_main, out, 2, 0, False)
+        ctx_g = make_context(w, V, modes[main_mode], psi=psi, eps=eps_occ, cg_graphs=True)
+        out_g = torch.empty_like(phi)
+        ms_g, sts_g, _ = run_steps(ctx_g, out_g, 2, 1, False)
+        graphs = {"ms_per_step_graphs": round(ms_g, 2), "ms_per_step_eager_no_events": round(ms_e, 2),
+                  "value_graphs": round(w.n_pdep / (ms_g / 1e3), 3),
+                  "graph_launches": sts_g[-1]["graph_launches"], "graph_captures": sts_g[-1]["graph_captures"],
+                  "graph_updates": sts_g[-1]["graph_updates"],
+                  "identical_to_eager": bool(torch.equal(out_g, out))}
+        log("graph mode", graphs)
+        ctx_g.close()
     if args.copy_probe_mib > 0:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -462,6 +478,7 @@ def main():
         "n_notconv": stats[-1]["n_notconv"],
         "fp64": fp64,
         "other_mixed_mode": other,
+        "cg_graphs": graphs,
         "cg_iter_max": stats[-1]["cg_iter_max"],
         "cg_iter_mean": round(stats[-1]["cg_iter_total"] / max(stats[-1]["n_rhs"], 1), 2),
         "refine_steps": stats[-1]["refine_steps"],

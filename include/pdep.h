@@ -43,6 +43,15 @@
  * Errors: every call returns a pdep_status; on error pdep_last_error() gives a
  * message for the calling thread.  PDEP_ENOTCONV still fills outputs and stats.
  * A context must not be used by two threads at once.
+ *
+ * Launch shapes: the first application with at least 1024 Sternheimer systems times the
+ * candidate shapes of the transform chain (rows per launch) and of the BF16x3
+ * coefficient GEMMs (split-K target, column tiles) on its own data and keeps the
+ * fastest for the context; results do not depend on them beyond rounding.  With the
+ * environment variable PDEP_TUNE_CACHE=<file>, the chosen shapes are also written to
+ * that JSON file (one object per grid, N_pw, N_v and precision) and read back by later
+ * contexts of the same problem, which then skip the timing runs.  PDEP_FFT_CHUNK=<fp32
+ * rows>[:<fp64 rows>] fixes the chain shape.
  */
 #ifndef PDEP_H
 #define PDEP_H
@@ -79,6 +88,10 @@ typedef enum {
 } pdep_precision;
 
 #define PDEP_DEVICE_PTRS 1u
+#define PDEP_CG_GRAPHS 2u     /* replay the batched inner CG iterations as HIP graphs: every
+                                 block of iterations between two reads of the active-row count
+                                 is captured once per row count and relaunched (eager when the
+                                 kernel profiler is on); results are identical to eager mode */
 
 typedef struct {
     void* (*alloc)(size_t bytes, void* ctx);
@@ -109,7 +122,7 @@ typedef struct {
     int rhs_tile;         /* Sternheimer systems per batched CG tile; 0 = automatic */
     void* stream;         /* hipStream_t; NULL = default stream */
     pdep_allocator alloc; /* device allocator; alloc == NULL: hipMalloc / hipFree */
-    uint32_t flags;       /* PDEP_DEVICE_PTRS */
+    uint32_t flags;       /* PDEP_DEVICE_PTRS | PDEP_CG_GRAPHS */
 } pdep_opts;
 
 /* Fill *o with defaults: FP64, cg_tol 1e-10, cg_maxit 2000, inner_tol 1e-5,
@@ -141,6 +154,9 @@ typedef struct {
     int n_fp32_fallback_rows;     /* PDEP_MIXED_BF16X3: systems that ran an inner solve with FP32
                                      projection products after a BF16x3 inner solve diverged
                                      (0 when the BF16x3 products held throughout) */
+    long long graph_launches;     /* PDEP_CG_GRAPHS: CG iteration blocks replayed as graphs */
+    long long graph_captures;     /* PDEP_CG_GRAPHS: graphs captured (one per row count and phase) */
+    long long graph_updates;      /* PDEP_CG_GRAPHS: captures applied to an executable graph in place */
 } pdep_apply_stats;
 
 typedef struct {

@@ -128,6 +128,7 @@ void finish_setup(Ctx& c) {
     double mx = 0.0;
     for (double x : r2) mx = std::max(mx, std::sqrt(std::max(x, 0.0)));
     c.gs_residual = mx;
+    pdep::tune_cache_load(c);
 }
 
 }  // namespace
@@ -295,6 +296,9 @@ void fill_apply_stats(const Ctx& c, const pdep::ApplyStats& as, double ms, pdep_
     st->ms = ms;
     st->fft_chunk = c.opts.precision == PDEP_FP64 ? c.fft_chunk64 : c.fft_chunk32;
     st->n_fp32_fallback_rows = as.n_fp32_fallback;
+    st->graph_launches = as.graph_launches;
+    st->graph_captures = as.graph_captures;
+    st->graph_updates = as.graph_updates;
 }
 
 // Context state that a no-allocation call changes, restored on every exit.

@@ -329,6 +329,11 @@ void check_finite_rows(Ctx& c, Workspace& ws, const double2* X, int nrows, long 
 
 Ctx::~Ctx() {
     if (own_blas && blas) rocblas_destroy_handle(static_cast<rocblas_handle>(blas));
+    if (graph_stream) {
+        (void)hipStreamSynchronize(graph_stream);
+        (void)hipStreamDestroy(graph_stream);
+    }
+    if (graph_event) (void)hipEventDestroy(graph_event);
 }
 
 // ------------------------------------------------------------------ ground state ---

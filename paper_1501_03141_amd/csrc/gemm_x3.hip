@@ -611,14 +611,14 @@ template <bool REAL>
 int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, void* S, long lds,
                 void* work, size_t work_elems, hipStream_t s, bool real_out, const float* kin = nullptr,
                 const double* shift = nullptr, float kfloor = 0.f, const CgStepFuse* cs = nullptr,
-                int max_parts = 0) {
+                int max_parts = 0, GemmShape shape = {}) {
     if (M <= 0 || N <= 0) return 0;
     PDEP_REQUIRE(lda % 4 == 0 && ldb % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3: leading dimensions must be multiples of 4");
     const int WM = M <= 32 ? 1 : (M <= 64 ? 2 : 4);
     // eight column tiles per wave when all four waves run along m and are mostly full;
     // the fused CG step keeps four (three waves per SIMD instead of two: its extra r and
     // q traffic needs the latency hiding more than the shared B tile; 5-12% faster)
-    const int CT = (M > 96 && !cs) ? 8 : 4;
+    const int CT = (M > 96 && !cs) ? (shape.col_tiles == 4 ? 4 : 8) : 4;
     const int BMC = 32 * WM, BN = 16 * CT * (4 / WM);
     PDEP_REQUIRE((N + BN - 1) / BN <= 65535, PDEP_EINVAL, "gemm_ahb_x3: N too large");
     dim3 grid((M + BMC - 1) / BMC, (N + BN - 1) / BN);
@@ -630,7 +630,7 @@ int gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const float2* B,
     // traffic: measured best at 512 for N_v = 128 and 512); 1024 for the fused step
     int splits = 1;
     const long tiles = (long)grid.x * grid.y;
-    const long target = cs ? 1024 : 512;
+    const long target = shape.splitk_target > 0 ? shape.splitk_target : (cs ? 1024 : 512);
     if (work && tiles < target) {
         splits = (int)std::min<long>((target + tiles - 1) / tiles, std::max(1, K / 256));
         if (cs) splits = std::min(splits, max_parts);
@@ -703,20 +703,21 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
 
 void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
                              long lds, float* work, size_t work_elems, hipStream_t s, const float* kin,
-                             const double* shift, double kfloor) {
+                             const double* shift, double kfloor, GemmShape shape) {
     PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_real: lds must be a multiple of 4");
     PDEP_REQUIRE(!kin || (shift && kfloor > 0), PDEP_EINVAL, "gemm_ahb_x3_real: preconditioner needs shifts");
-    gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor);
+    gemm_ahb_x3<true>(M, N, K, A, lda, B, ldb, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor, nullptr,
+                      0, shape);
 }
 
 int launch_gemm_ahb_x3_step(int M, int N, int K, const float2* A, long lda, float2* r, long ldr, float* S, long lds,
                             float* work, size_t work_elems, hipStream_t s, const float* kin, const double* shift,
-                            double kfloor, const CgStepFuse& cs, int max_parts) {
+                            double kfloor, const CgStepFuse& cs, int max_parts, GemmShape shape) {
     PDEP_REQUIRE(lds % 4 == 0, PDEP_EINVAL, "gemm_ahb_x3_step: lds must be a multiple of 4");
     PDEP_REQUIRE(kin && shift && kfloor > 0, PDEP_EINVAL, "gemm_ahb_x3_step: the step needs the preconditioner");
     PDEP_REQUIRE(M <= 128, PDEP_EINVAL, "gemm_ahb_x3_step: at most 128 coefficient rows");
     return gemm_ahb_x3<true>(M, N, K, A, lda, r, ldr, S, lds, work, work_elems, s, true, kin, shift, (float)kfloor,
-                             &cs, max_parts);
+                             &cs, max_parts, shape);
 }
 
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,

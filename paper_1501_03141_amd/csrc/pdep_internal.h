@@ -100,6 +100,8 @@ class ProfScope {
     bool active_ = false;
 };
 
+// True while launches of this thread are being timed (pdep_profile_enable).
+bool profiling_on();
 // While one exists on a thread, the launches of that thread are not timed (the
 // no-allocation entry point creates no events).
 struct ProfSuspend {
@@ -226,12 +228,19 @@ void launch_gemm_ahb_x3(int M, int N, int K, const float2* A, long lda, const fl
                         long lds, float2* work, size_t work_elems, hipStream_t s, bool real_out = false);
 void launch_gemm_update_x3(int M, int N, int K, const float2* A, long lda, const float2* S, long lds, double alpha,
                            double beta, float2* Y, long ldy, hipStream_t s);
+// Launch shape of the BF16x3 coefficient GEMMs (0 = the built-in rule): split K until
+// about splitk_target workgroups; col_tiles 4 or 8 column tiles per wave (plain GEMM with
+// more than 96 coefficient rows only).
+struct GemmShape {
+    int splitk_target = 0;
+    int col_tiles = 0;
+};
 // Real-coefficient BF16x3 pair (S real, float [N][lds], lds multiple of 4):
 //   S[n][m] = Re sum_k conj(A[m][k]) B[n][k];   Y[n][k] = beta Y + alpha sum_m S[n][m] A[m][k]
 // kin non-null: B[n][k] is taken times the CG preconditioner 1 / max(kin[k] - shift[n], kfloor)
 void launch_gemm_ahb_x3_real(int M, int N, int K, const float2* A, long lda, const float2* B, long ldb, float* S,
                              long lds, float* work, size_t work_elems, hipStream_t s, const float* kin = nullptr,
-                             const double* shift = nullptr, double kfloor = 0.0);
+                             const double* shift = nullptr, double kfloor = 0.0, GemmShape shape = {});
 void launch_gemm_update_x3_real(int M, int N, int K, const float2* A, long lda, const float* S, long lds,
                                 double alpha, double beta, float2* Y, long ldy, hipStream_t s);
 // The residual update of a preconditioned CG step, for the rows of launch_gemm_ahb_x3_step.
@@ -255,7 +264,7 @@ struct CgStepFuse {
 // (<= max_parts).
 int launch_gemm_ahb_x3_step(int M, int N, int K, const float2* A, long lda, float2* r, long ldr, float* S, long lds,
                             float* work, size_t work_elems, hipStream_t s, const float* kin, const double* shift,
-                            double kfloor, const CgStepFuse& cs, int max_parts);
+                            double kfloor, const CgStepFuse& cs, int max_parts, GemmShape shape = {});
 // CG direction update with the projected preconditioned residual formed in the GEMM:
 // for active rows n, x[xrow[n]] += alpha[n] p[n] (the old p; xrow null: row n) and
 // p[n] <- K r[n] - sum_m S[n][m] A[m] + beta[n] p[n], where S = Re(A^H K r) comes from
@@ -425,9 +434,21 @@ struct Ctx {
     void* ws_current(int i) const { return arena ? static_cast<void*>(arena->p[i]) : w[i].get(); }
     // rows per launch of the transform chain for FP32 / FP64 rows (0: not tuned yet)
     int fft_chunk32 = 0, fft_chunk64 = 0;
+    // launch shapes of the BF16x3 coefficient GEMMs: the fused CG step and the plain one
+    // (splitk_target 0: not tuned yet)
+    GemmShape step_shape, ahb_shape;
+    bool capturing = false;               // a HIP graph is being captured (no tuning runs)
+    // PDEP_CG_GRAPHS: the stream the inner CG is captured on, and the event that orders it
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_event = nullptr;
 };
 
 // solver.hip
+// Tuned launch parameters shared across processes: with PDEP_TUNE_CACHE=<file> set, the
+// values tuned for a problem (grid, N_pw, N_v, precision) are read at set-up and written
+// back (one JSON object per problem) when a tuning run picks new ones.
+void tune_cache_load(Ctx& c);
+void tune_cache_store(const Ctx& c);
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
 // entries of a half-sphere row (k <= (npw - 1) / 2, the centre G = 0 last)
@@ -436,6 +457,8 @@ template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, dou
 struct ApplyStats {
     int n_rhs = 0, cg_iter_max = 0, refine_steps = 0, n_notconv = 0;
     int n_fp32_fallback = 0;              // BF16x3 mode: systems re-solved with FP32 projection products
+    long long graph_captures = 0, graph_launches = 0;   // PDEP_CG_GRAPHS: CG blocks captured / replayed
+    long long graph_updates = 0;          // captures that updated an executable graph in place
     long long cg_iter_total = 0, op_applications = 0;
     double max_rel_residual = 0.0;
 };

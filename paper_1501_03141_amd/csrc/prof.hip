@@ -74,6 +74,8 @@ namespace {
 thread_local int g_suspended = 0;   // ProfSuspend scopes open on this thread
 }
 
+bool profiling_on() { return prof().on && g_suspended == 0; }
+
 ProfSuspend::ProfSuspend() { ++g_suspended; }
 ProfSuspend::~ProfSuspend() { --g_suspended; }
 

@@ -31,6 +31,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unistd.h>
 #include <utility>
 #include <vector>
 #include "pdep_internal.h"
@@ -103,6 +108,115 @@ rocblas_handle ctx_blas(Ctx& c) {
 
 }  // namespace
 
+// Rows from which a first application tunes launch shapes by timing them on its data.
+constexpr int kTuneRows = 1024;
+
+namespace {
+
+// Device time (ms) of f() on stream s: run twice, the second run timed.
+template <class F> float time_twice(hipStream_t s, F&& f) {
+    hipEvent_t e0, e1;
+    PDEP_HIP(hipEventCreate(&e0));
+    PDEP_HIP(hipEventCreate(&e1));
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+        PDEP_HIP(hipEventRecord(e0, s));
+        f();
+        PDEP_HIP(hipEventRecord(e1, s));
+        PDEP_HIP(hipEventSynchronize(e1));
+        PDEP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+std::string tune_key(const Ctx& c) {
+    const char* prec = c.opts.precision == PDEP_FP64 ? "fp64" : (c.opts.precision == PDEP_MIXED_FP32 ? "fp32" : "bf16x3");
+    return std::to_string(c.basis.n[0]) + "x" + std::to_string(c.basis.n[1]) + "x" + std::to_string(c.basis.n[2]) +
+           " npw " + std::to_string(c.basis.npw) + " nv " + std::to_string(c.nv) + " " + prec;
+}
+
+// The cache file: one line per problem, {"<key>": {"<name>": <int>, ...}}, inside one
+// JSON object.
+using TuneMap = std::map<std::string, std::map<std::string, long>>;
+std::mutex g_tune_mu;
+
+TuneMap tune_read(const char* path) {
+    TuneMap m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"');
+        if (a == std::string::npos) continue;
+        const size_t b = line.find('"', a + 1);
+        const size_t brace = line.find('{', b == std::string::npos ? 0 : b);
+        if (b == std::string::npos || brace == std::string::npos) continue;
+        auto& entry = m[line.substr(a + 1, b - a - 1)];
+        size_t q = brace;
+        while ((q = line.find('"', q + 1)) != std::string::npos) {
+            const size_t q2 = line.find('"', q + 1);
+            const size_t colon = q2 == std::string::npos ? q2 : line.find(':', q2);
+            if (colon == std::string::npos) break;
+            entry[line.substr(q + 1, q2 - q - 1)] = std::strtol(line.c_str() + colon + 1, nullptr, 10);
+            q = line.find_first_of(",}", colon);
+            if (q == std::string::npos || line[q] == '}') break;
+        }
+    }
+    return m;
+}
+
+}  // namespace
+
+void tune_cache_load(Ctx& c) {
+    const char* path = std::getenv("PDEP_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneMap m = tune_read(path);
+    const auto it = m.find(tune_key(c));
+    if (it == m.end()) return;
+    auto get = [&](const char* k) {
+        const auto f = it->second.find(k);
+        return f == it->second.end() ? 0 : (int)f->second;
+    };
+    c.fft_chunk32 = get("chain_rows_fp32");
+    c.fft_chunk64 = get("chain_rows_fp64");
+    c.step_shape.splitk_target = get("step_splitk_target");
+    c.ahb_shape.splitk_target = get("coef_splitk_target");
+    c.ahb_shape.col_tiles = get("coef_col_tiles");
+    if (verbose()) fprintf(stderr, "[pdep] tuned shapes of %s read from %s\n", tune_key(c).c_str(), path);
+}
+
+void tune_cache_store(const Ctx& c) {
+    const char* path = std::getenv("PDEP_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneMap m = tune_read(path);
+    auto& e = m[tune_key(c)];
+    auto put = [&](const char* k, int v) {
+        if (v > 0) e[k] = v;
+    };
+    put("chain_rows_fp32", c.fft_chunk32);
+    put("chain_rows_fp64", c.fft_chunk64);
+    put("step_splitk_target", c.step_shape.splitk_target);
+    put("coef_splitk_target", c.ahb_shape.splitk_target);
+    put("coef_col_tiles", c.ahb_shape.col_tiles);
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream f(tmp);
+        f << "{\n";
+        size_t i = 0;
+        for (const auto& kv : m) {
+            f << "  \"" << kv.first << "\": {";
+            size_t j = 0;
+            for (const auto& nv : kv.second) f << (j++ ? ", " : "") << "\"" << nv.first << "\": " << nv.second;
+            f << "}" << (++i < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    if (std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+
 template <typename T>
 void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     const int npw = c.basis.npw, nv = c.nv, nh = half_len(npw);
@@ -150,7 +264,27 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
         if (c.pc_x3) {
             float* Sr = reinterpret_cast<float*>(S);
             float* wr = reinterpret_cast<float*>(work);
-            launch_gemm_ahb_x3_real(nv, nrows, nh, pw, lp, Y, ld, Sr, lds, wr, 2 * split_elems, c.stream);
+            if (c.ahb_shape.splitk_target == 0 && nrows >= kTuneRows && !c.arena && !c.capturing) {
+                // the coefficient GEMM only reads Y: time its launch shapes on the live rows
+                float best = 0.f;
+                for (const GemmShape g : {GemmShape{512, 8}, GemmShape{1024, 8}, GemmShape{256, 8}, GemmShape{512, 4},
+                                          GemmShape{1024, 4}}) {
+                    const float ms = time_twice(c.stream, [&] {
+                        launch_gemm_ahb_x3_real(nv, nrows, nh, pw, lp, Y, ld, Sr, lds, wr, 2 * split_elems, c.stream,
+                                                nullptr, nullptr, 0.0, g);
+                    });
+                    if (verbose())
+                        fprintf(stderr, "[pdep] coefficient GEMM, %d rows, split-K target %d, %d column tiles: %.3f ms\n",
+                                nrows, g.splitk_target, g.col_tiles, ms);
+                    if (c.ahb_shape.splitk_target == 0 || ms < best) {
+                        best = ms;
+                        c.ahb_shape = g;
+                    }
+                }
+                tune_cache_store(c);
+            }
+            launch_gemm_ahb_x3_real(nv, nrows, nh, pw, lp, Y, ld, Sr, lds, wr, 2 * split_elems, c.stream, nullptr,
+                                    nullptr, 0.0, c.ahb_shape);
             launch_gemm_update_x3_real(nv, nrows, nh, psi_of<T>(c), lp, Sr, lds, -1.0, 1.0, Y, ld, c.stream);
         } else {
             launch_gemm_ahb<T>(nv, nrows, nh, pw, lp, Y, ld, St, lds, work, split_elems, c.stream, true);
@@ -168,7 +302,6 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
 // not depend on the choice.  PDEP_FFT_CHUNK=<fp32 rows>[:<fp64 rows>] in the environment
 // fixes the sizes instead (for profiling runs that must launch the shapes of a tuned run).
 constexpr double kChunkCacheBytes = 150e6;   // about half of the 256 MB last-level cache
-constexpr int kTuneRows = 1024;
 
 int fft_chunk_env(bool fp64) {
     static const std::pair<int, int> v = [] {
@@ -184,6 +317,8 @@ int fft_chunk_env(bool fp64) {
 }
 
 template <typename T> int& fft_chunk_of(Ctx& c) { return sizeof(T) == sizeof(float) ? c.fft_chunk32 : c.fft_chunk64; }
+
+
 
 template <typename T> int fft_chunk_rule(const Ctx& c) {
     const FftDims& d = c.basis.dims;
@@ -267,6 +402,7 @@ void apply_op(Ctx& c, const cplx<T>* p, cplx<T>* q, long ld, int nrows, const do
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (verbose()) fprintf(stderr, "[pdep] transform chain block size %d rows\n", tuned), fflush(stderr);
+        tune_cache_store(c);
     }
     chain(tuned > 0 ? tuned : nrows);
     if (project) project_c<T>(c, q, ld, nrows, S);
@@ -380,6 +516,33 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     // half-sphere rows (entries k <= c of vectors real in r)
     constexpr bool half = true;
     const int npw = half_len(c.basis.npw), nv = c.nv;
+    // Graph mode runs the solve on the context's own capture stream (a stream that is not
+    // the legacy default stream can be captured), ordered after the caller's stream by an
+    // event at entry and before it at exit.
+    const bool use_graph = (c.opts.flags & PDEP_CG_GRAPHS) != 0 && !c.arena;   // instantiation may allocate
+    struct StreamSwitch {
+        Ctx& c;
+        hipStream_t orig = nullptr;
+        bool on = false;
+        StreamSwitch(Ctx& cc, bool enable) : c(cc) {
+            if (!enable) return;
+            if (!c.graph_stream) {
+                PDEP_HIP(hipStreamCreateWithFlags(&c.graph_stream, hipStreamNonBlocking));
+                PDEP_HIP(hipEventCreateWithFlags(&c.graph_event, hipEventDisableTiming));
+            }
+            orig = c.stream;
+            PDEP_HIP(hipEventRecord(c.graph_event, orig));
+            PDEP_HIP(hipStreamWaitEvent(c.graph_stream, c.graph_event, 0));
+            c.stream = c.graph_stream;
+            on = true;
+        }
+        ~StreamSwitch() {
+            if (!on) return;
+            (void)hipEventRecord(c.graph_event, c.graph_stream);
+            (void)hipStreamWaitEvent(orig, c.graph_event, 0);
+            c.stream = orig;
+        }
+    } stream_switch(c, use_graph);
     hipStream_t s = c.stream;
     const size_t vbytes = (size_t)n * ld * sizeof(cplx<T>);
     cplx<T>* x = static_cast<cplx<T>*>(c.ws(W_CX, vbytes));
@@ -440,6 +603,19 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
     // the host reads the active count every `poll` iterations (compaction, exit): 2 beats 4
     // on the medium block (fewer iterations on rows that have converged, 278 -> 272 ms)
     const int poll = 2;
+    // graph mode: one executable graph per phase of the 8-iteration re-projection cycle,
+    // for the current slot count (destroyed when compaction changes it, and at exit)
+    int graph_ncur = -1;
+    hipGraphExec_t graph_exec[8 / poll] = {};
+    bool graph_valid[8 / poll] = {};
+    struct GraphsGuard {
+        hipGraphExec_t* e;
+        int n;
+        ~GraphsGuard() {
+            for (int i = 0; i < n; ++i)
+                if (e[i]) (void)hipGraphExecDestroy(e[i]);
+        }
+    } graphs_guard{graph_exec, 8 / poll};
     while (h_active > 0 && it < maxit) {
         if (h_active < ncur && (10 * h_active < 9 * ncur)) {
             // compact: retire converged slots, then fill the holes they leave below the new
@@ -474,7 +650,10 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
         const int nstep = std::min(poll, maxit - it);
         double* rz = sc.s_rz[0];
         double* sh = sc.s_shift[0];
-        for (int k = 0; k < nstep; ++k) {
+        // one CG iteration on the ncur live slots (reproject: r is projected again after
+        // it; last: the final iteration of the block)
+        auto iteration = [&](bool reproject, bool last) {
+
             // With the preconditioner z = P_c K r is projected every iteration, so p stays in
             // range(P_c) and q = (H - shift) p needs no projection: <p, q> and the update of
             // x are unchanged by it.  What q adds to r outside range(P_c) is rounding (the
@@ -511,8 +690,29 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                         cs.rr = sc.rr;
                         cs.beta = beta;
                         cs.count = sc.n_active;   // cleared here for the check below
-                        launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, r, ld, Sr, lds, wr,
-                                                2 * c.split_elems, s, kin, sh, kPrecondFloor, cs, nblk);
+                        auto step = [&](float2* rr_in, GemmShape g) {
+                            launch_gemm_ahb_x3_step(nv, ncur, npw, c.psi32w.as<float2>(), lp, rr_in, ld, Sr, lds, wr,
+                                                    2 * c.split_elems, s, kin, sh, kPrecondFloor, cs, nblk, g);
+                        };
+                        if (c.step_shape.splitk_target == 0 && ncur >= kTuneRows && !c.arena && !c.capturing) {
+                            // time the split-K targets on a copy of r (z is not used in this mode);
+                            // every other output of the trial runs is written again by the real step
+                            PDEP_HIP(hipMemcpyAsync(z, r, (size_t)ncur * ld * sizeof(cplx<T>), hipMemcpyDeviceToDevice,
+                                                    s));
+                            float best = 0.f;
+                            for (int t : {512, 1024, 2048}) {
+                                const float ms = time_twice(s, [&] { step(z, GemmShape{t, 0}); });
+                                if (verbose())
+                                    fprintf(stderr, "[pdep] fused CG step, %d rows, split-K target %d: %.3f ms\n",
+                                            ncur, t, ms);
+                                if (c.step_shape.splitk_target == 0 || ms < best) {
+                                    best = ms;
+                                    c.step_shape.splitk_target = t;
+                                }
+                            }
+                            tune_cache_store(c);
+                        }
+                        step(r, c.step_shape);
                     } else {
                         launch_cg_step1<T>(ncur, npw, nullptr, r, nullptr, p, q, ld, rz, pq_part, npq, sc.active,
                                            kin, sh, ncur, pre, s, rz_part, rr_part, sc.rz_new, sc.rr, half, beta,
@@ -524,14 +724,14 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
                                            beta, alpha, xout, sc.s_id[0], sc.active, p, ld, s);
                 }
                 // r is re-projected every 8 iterations
-                if ((it + k + 1) % 8 == 0) project_c<T>(c, r, ld, ncur, S);
+                if (reproject) project_c<T>(c, r, ld, ncur, S);
             } else if (pre) {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, false, true, sticks, S, pq_part);
                 st.op_applications++;
                 launch_cg_step1<T>(ncur, npw, x, r, z, p, q, ld, rz, pq_part, npq, sc.active, kin, sh, ncur, pre, s,
                                    rz_part, rr_part, sc.rz_new, sc.rr, half);
                 project_c<T>(c, z, ld, ncur, S);
-                if (k == nstep - 1) project_c<T>(c, r, ld, ncur, S);
+                if (last) project_c<T>(c, r, ld, ncur, S);
             } else {
                 apply_op<T>(c, p, q, ld, ncur, sh, ncur, true, true, sticks, S);
                 st.op_applications++;
@@ -543,6 +743,66 @@ int cg_inner(Ctx& c, int n, const cplx<T>* b, long ld, CgScalars& sc, int maxit,
             if (!(pre && fused && nv <= 128)) launch_fill_zero(sc.n_active, sizeof(int), s);
             launch_cg_check(ncur, sc.rr, sc.s_thr2[0], sc.active, sc.s_iters[0], rz, sc.rz_new, sc.n_active, 1,
                             s, rr_max);
+        };
+        auto block = [&](int it0, int n) {
+            for (int k = 0; k < n; ++k) iteration((it0 + k + 1) % 8 == 0, k == n - 1);
+        };
+        // The kernels of a block of `poll` iterations can be captured once per slot count
+        // and replayed as a HIP graph (the host still reads the active count after each
+        // block).  The first block of a solve runs eagerly: it sizes every work buffer and
+        // tunes the transform chain, which must not happen under capture.  The graph holds
+        // kernels only (the counter is cleared by a kernel, not a memset).
+        const bool graph_ok = use_graph && nstep == poll && it > 0 && !profiling_on();
+        if (graph_ok) {
+            const int variant = (it % 8) / poll;   // which iteration of the 8 re-projects r
+            if (graph_ncur != ncur) {
+                for (auto& v : graph_valid) v = false;   // kept for an in-place update
+                graph_ncur = ncur;
+            }
+            hipGraphExec_t& ex = graph_exec[variant];
+            if (!graph_valid[variant]) {
+                hipGraph_t g = nullptr;
+                const long long ops = st.op_applications;   // counted at launch, not at capture
+                PDEP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    c.capturing = true;
+                    block(it, nstep);
+                    c.capturing = false;
+                    st.op_applications = ops;
+                } catch (...) {
+                    c.capturing = false;
+                    hipGraph_t dead = nullptr;
+                    (void)hipStreamEndCapture(s, &dead);
+                    if (dead) (void)hipGraphDestroy(dead);
+                    throw;
+                }
+                PDEP_HIP(hipStreamEndCapture(s, &g));
+                // a graph of the same shape (another row count) is updated in place; a new
+                // shape (the chain's block count changed) is instantiated
+                bool updated = false;
+                if (ex) {
+                    hipGraphNode_t bad = nullptr;
+                    hipGraphExecUpdateResult why;
+                    updated = hipGraphExecUpdate(ex, g, &bad, &why) == hipSuccess;
+                    if (!updated) {
+                        (void)hipGetLastError();
+                        (void)hipGraphExecDestroy(ex);
+                        ex = nullptr;
+                    }
+                }
+                hipError_t e = hipSuccess;
+                if (!updated) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                PDEP_HIP(e);
+                graph_valid[variant] = true;
+                ++st.graph_captures;
+                if (updated) ++st.graph_updates;
+            }
+            PDEP_HIP(hipGraphLaunch(ex, s));
+            ++st.graph_launches;
+            st.op_applications += nstep;
+        } else {
+            block(it, nstep);
         }
         it += nstep;
         PDEP_HIP(hipMemcpyAsync(&h_active, sc.n_active, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -31,6 +31,7 @@ PDEP_FP64 = 0
 PDEP_MIXED_FP32 = 1
 PDEP_MIXED_BF16X3 = 2
 PDEP_DEVICE_PTRS = 1
+PDEP_CG_GRAPHS = 2
 
 _NAMES = {0: "PDEP_OK", -1: "PDEP_EINVAL", -2: "PDEP_ENOMEM", -3: "PDEP_ENOTCONV", -4: "PDEP_EGAP",
           -5: "PDEP_EDEVICE", -6: "PDEP_EBUSY", -7: "PDEP_ENOTFOUND"}
@@ -71,7 +72,8 @@ class ApplyStats(C.Structure):
     _fields_ = [("n_rhs", C.c_int), ("cg_iter_max", C.c_int), ("cg_iter_total", C.c_longlong),
                 ("op_applications", C.c_longlong), ("refine_steps", C.c_int), ("n_notconv", C.c_int),
                 ("max_rel_residual", C.c_double), ("ms", C.c_double), ("fft_chunk", C.c_int),
-                ("n_fp32_fallback_rows", C.c_int)]
+                ("n_fp32_fallback_rows", C.c_int), ("graph_launches", C.c_longlong),
+                ("graph_captures", C.c_longlong), ("graph_updates", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -264,7 +266,8 @@ class Context:
 
     def __init__(self, L, n, ecut, vloc, n_v, precision=PDEP_FP64, cg_tol=1e-10, cg_maxit=2000,
                  inner_tol=1e-5, refine_maxit=8, precond=1, gap_min=1e-3, gs_tol=1e-10, gs_maxit=400,
-                 hbm_budget=0, rhs_tile=0, psi=None, eps=None, device_ptrs=False, use_torch=True):
+                 hbm_budget=0, rhs_tile=0, psi=None, eps=None, device_ptrs=False, use_torch=True,
+                 cg_graphs=False):
         self._lib = load()
         self._h = C.c_void_p()
         cell = Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut))
@@ -282,7 +285,7 @@ class Context:
         o.gs_maxit = int(gs_maxit)
         o.hbm_budget = int(hbm_budget)
         o.rhs_tile = int(rhs_tile)
-        o.flags = PDEP_DEVICE_PTRS if device_ptrs else 0
+        o.flags = (PDEP_DEVICE_PTRS if device_ptrs else 0) | (PDEP_CG_GRAPHS if cg_graphs else 0)
         self.device_ptrs = bool(device_ptrs)
         self._alloc = None
         if use_torch:
