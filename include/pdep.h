@@ -270,6 +270,30 @@ int chi0_apply_noalloc(pdep_ctx* ctx, int n_pert, const double* phi, double* out
 int chibar_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, double tol, int maxit,
                  pdep_chibar_stats* st);
 
+typedef struct {
+    int chains;                   /* Lanczos chains run (one per basis potential and band, zero
+                                     start vectors excluded) */
+    int max_length;               /* longest chain (n_lanczos unless a chain closed earlier) */
+    long long h_applications;     /* batched applications of the deflated Hamiltonian */
+    double ms;
+} pdep_lanczos_stats;
+
+/* The body of chi0bar at imaginary frequencies in the basis phi (n_pert x N_pw' complex,
+ * Hermitian-symmetric rows on S', e.g. the PDEP eigenvectors):
+ *   body[f][i][j] = -(4/Omega) sum_v Re <w_iv| A_v (A_v^2 + u_f^2)^-1 |w_jv>,
+ * w_jv = P_c Fwd(V_j u_v), V_j = Re Inv(sqrt(4 pi)/|G| phi_j), A_v = P_c (H - e_v) P_c:
+ * the Adler-Wiser form (Eq. AdlerWiser) of the body at omega = i u_f (Eq. finalB), equal to
+ * the static <phi_i| chi0bar phi_j> at u = 0.  Computed without empty states by one
+ * Lanczos chain of the deflated Hamiltonian P_c H P_c per (j, v), started at
+ * w_jv / ||w_jv|| and n_lanczos long (Sec. 2.4, Eqs. MCdef and MCfinal; the paper uses
+ * 40), so that every frequency costs only sums over the chains.  freq: n_freq values
+ * u_f >= 0 (Ha, host); body: n_freq x n_pert x n_pert doubles (host, caller-allocated),
+ * row i, column j (column j comes from the chains of phi_j).  Device memory: about
+ * 5 n_pert N_v rows of N_pw complex doubles plus n_lanczos N_v n_pert^2 complex doubles.
+ * phi follows PDEP_DEVICE_PTRS; freq and body are host arrays.  st may be NULL. */
+int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
+                      double* body, pdep_lanczos_stats* st);
+
 /* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
  * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
  * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own

@@ -519,6 +519,42 @@ int chibar_apply(pdep_ctx* ctx, int n_pert, const double* phi, double* out, doub
     API_END
 }
 
+int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
+                      double* body, pdep_lanczos_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    if (st) std::memset(st, 0, sizeof(*st));
+    PDEP_REQUIRE(n_pert >= 1 && n_lanczos >= 1 && n_freq >= 1, PDEP_EINVAL, "n_pert, n_lanczos and n_freq must be >= 1");
+    PDEP_REQUIRE(phi && freq && body, PDEP_EINVAL, "null phi/freq/body");
+    for (int f = 0; f < n_freq; ++f)
+        PDEP_REQUIRE(std::isfinite(freq[f]) && freq[f] >= 0.0, PDEP_EINVAL, "frequencies must be finite and >= 0");
+    PDEP_REQUIRE((long)n_pert * c.nv <= 65535L * 64, PDEP_EINVAL, "too many chains for one block");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)n_pert * ld * sizeof(double2)));
+    if (dev) {
+        pdep::launch_expand_s1(n_pert, npw, g0, reinterpret_cast<const double2*>(phi), n1, in_s, ld, s);
+    } else {
+        PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pert * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+        pdep::launch_expand_s1(n_pert, npw, g0, stage, n1, in_s, ld, s);
+    }
+    const pdep::LanczosResult r = pdep::body_lanczos(c, n_pert, in_s, n_lanczos, n_freq, freq, body);
+    const double ms = tm.stop();
+    if (st) {
+        st->chains = r.chains;
+        st->max_length = r.max_length;
+        st->h_applications = r.h_applications;
+        st->ms = ms;
+    }
+    API_END
+}
+
 int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, const pdep_eig_opts* eo_in,
               double* eps_out, double* basis_out, pdep_eig_stats* st) {
     API_BEGIN

@@ -361,7 +361,8 @@ enum WsSlot : int {
     WS_CAPI_IN = 28, WS_CAPI_OUT = 29, WS_CAPI_STAGE = 30,
     WS_SETUP_STICKS = 31, WS_DAV_THETA = 32, WS_DAV_C = 33, WS_DAV_DOTS = 34,
     WS_SCR_Y = 35,            // screening.hip: 35 .. 41
-    WS_COUNT = 42
+    WS_LZ_W = 42,             // lanczos.hip: 42 .. 49
+    WS_COUNT = 50
 };
 
 // Work space carved from a fixed device region instead of the allocator (the
@@ -470,6 +471,12 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
 void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st);
 // chi0bar on S (device, FP64, G0 entry ignored/zero): phi [npert][npw] -> out [npert][npw]
 void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st);
+// W [npert * N_v half-sphere FP64 rows, stride ld, row = i * N_v + v] <- P_c Fwd(V_i u_v)
+// with V_i = Re Inv(sqrt(4 pi)/|G| phi_i) (the Sternheimer right-hand sides up to sign);
+// phi: npert rows on S (stride sphere_ld(npw), G = 0 entry zero)
+void rhs_half_rows(Ctx& c, int npert, const double2* phi, double2* W, long ld);
+// z = P_c H P_c q on FP64 half-sphere rows (zero_shift: one device double 0.0)
+void apply_deflated_h64(Ctx& c, const double2* q, double2* z, long ld, int nrows, const double* zero_shift);
 // upper bound of the device work space chi0bar_sphere takes for npert perturbations in
 // one tile (opts.rhs_tile >= npert * N_v)
 size_t chi0_work_bytes(const Ctx& c, int npert);
@@ -492,6 +499,15 @@ struct ScreenResult {
 };
 ScreenResult chibar_sphere(Ctx& c, int n, const double2* phi, double2* out, double tol, int maxit,
                            ApplyStats& st);
+
+// lanczos.hip: the body of chi0bar at imaginary frequencies u (host array) in the basis
+// phi (npert rows on S, device) by deflated Lanczos chains; body (host) [nfreq][npert][npert]
+struct LanczosResult {
+    int chains = 0, max_length = 0;
+    long long h_applications = 0;
+};
+LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int n_lanczos, int nfreq, const double* u,
+                           double* body);
 
 // davidson.hip
 void ground_state(Ctx& c);

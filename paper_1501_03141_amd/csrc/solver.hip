@@ -1066,6 +1066,28 @@ void chi0_grid(Ctx& c, int npert, const double* dv, double* dn, ApplyStats& st) 
     chi0_core(c, npert, dv, dn, nullptr, 0, st);
 }
 
+void rhs_half_rows(Ctx& c, int npert, const double2* phi, double2* W, long ld) {
+    const Basis& b = c.basis;
+    const int nv = c.nv, nrow = npert * nv;
+    hipStream_t s = c.stream;
+    double* Vr = static_cast<double*>(c.ws(W_VR, (size_t)npert * b.ng * sizeof(double)));
+    double2* sticks = static_cast<double2*>(c.ws(W_STICKS, (size_t)std::max(npert, nrow) * sticks_row_bytes(c)));
+    // V_i = Re Inv(sqrt(4 pi)/|G| phi_i), then P_c Fwd(V_i u_v) for the band pairs
+    launch_sphere_to_sticks<double>(b.dims, b.tables, phi, sphere_ld(b.npw), npert, b.d_coul.as<double>(), sticks, s);
+    launch_slab_inv_store<double>(b.dims, b.tables, sticks, npert, nullptr, Vr, s);
+    const int nvp = pair_count(nv, nv);
+    launch_slab_fwd_product<double>(b.dims, b.tables, Vr, c.upair.as<double2>(), nvp, npert * nvp, sticks, s);
+    launch_sticks_to_sphere_pair<double>(b.dims, b.tables, sticks, nrow, W, ld, EPI_SCALE, 1.0, nullptr, 0, nullptr,
+                                         nullptr, 0, s, nullptr, nv);
+    project_c<double>(c, W, ld, nrow, static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow))));
+}
+
+void apply_deflated_h64(Ctx& c, const double2* q, double2* z, long ld, int nrows, const double* zero_shift) {
+    apply_op<double>(c, q, z, ld, nrows, zero_shift, 1, true, true,
+                     c.ws(W_STICKS, (size_t)nrows * sticks_row_bytes(c)),
+                     static_cast<double2*>(c.ws(W_S, coef_bytes(c.nv, nrows))));
+}
+
 void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplyStats& st) {
     const Basis& b = c.basis;
     const long ld = sphere_ld(b.npw);

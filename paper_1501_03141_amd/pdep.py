@@ -102,6 +102,14 @@ class ChibarStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LanczosStats(C.Structure):
+    _fields_ = [("chains", C.c_int), ("max_length", C.c_int), ("h_applications", C.c_longlong),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("max_running", C.c_int), ("hbm_budget", C.c_size_t), ("queue_capacity", C.c_int),
                 ("flags", C.c_uint32), ("fake_ms_per_gb", C.c_double)]
@@ -165,6 +173,7 @@ def load(path: str = LIB_PATH):
     lib.chi0_apply_noalloc.argtypes = [P, C.c_int, P, P, C.POINTER(ApplyStats)]
     lib.pdep_eigs.argtypes = [P, C.c_int, C.c_uint64, P, C.POINTER(EigOpts), D, P, C.POINTER(EigStats)]
     lib.chibar_apply.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(ChibarStats)]
+    lib.pdep_body_lanczos.argtypes = [P, C.c_int, P, C.c_int, C.c_int, D, D, C.POINTER(LanczosStats)]
     lib.pdep_destroy.argtypes = [P]
     lib.pdep_profile_enable.argtypes = [C.c_int]
     lib.pdep_profile_enable.restype = C.c_int
@@ -184,7 +193,8 @@ def load(path: str = LIB_PATH):
                  "pdep_server_destroy"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
-                 "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_eigs", "pdep_destroy"):
+                 "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_body_lanczos", "pdep_eigs",
+                 "pdep_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -399,6 +409,19 @@ class Context:
         _check(self._lib.chibar_apply(self._h, n_pert, p, o, float(tol), int(maxit), C.byref(st)),
                allow=(PDEP_ENOTCONV,) if allow_notconv else ())
         return (keep_o if not self.device_ptrs else out), st.as_dict()
+
+    def body_lanczos(self, phi, freq, n_lanczos=40):
+        """The body of chi0bar at the imaginary frequencies freq in the basis phi
+        [n_pert, N_pw - 1] by deflated Lanczos chains: (body [n_freq, n_pert, n_pert], stats)."""
+        n_pert = int(phi.shape[0])
+        p, keep = self._ptr(phi, np.complex128, (n_pert, self.n_pw - 1))
+        f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).ravel())
+        body = np.empty((f.size, n_pert, n_pert), dtype=np.float64)
+        st = LanczosStats()
+        _check(self._lib.pdep_body_lanczos(self._h, n_pert, p, int(n_lanczos), int(f.size),
+                                           f.ctypes.data_as(C.POINTER(C.c_double)),
+                                           body.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)))
+        return body, st.as_dict()
 
     def eigs(self, n_pdep, seed=0, phi0=None, tol=1e-9, maxit=60, max_subspace=0, n_buffer=0,
              want_basis=False, allow_notconv=False, reducible=False, scr_tol=0.0, scr_maxit=0):
