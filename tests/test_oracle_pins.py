@@ -566,3 +566,115 @@ def test_mutation_lanczos_start_norm_caught(tiny, monkeypatch):
     a = LZ.body_sos(m, gs, phi, [0.5])
     b = LZ.body_lanczos(m, gs, phi, [0.5], n_lanczos=m.n_pw)
     assert np.max(np.abs(a - b)) > 1e-3 * np.max(np.abs(a))
+
+
+# --- head and wings (q -> 0) and Eq. Bfinal -----------------------------------------------
+
+from oracle import headwings as HW  # noqa: E402
+
+
+def test_head_wings_sum_over_states_equals_resolvent(tiny):
+    """Two routes to F, U and B at imaginary frequencies: the sum over empty states with
+    dipole elements through the commutator, and the Sternheimer dipole vectors of
+    Eq. commu with the resolvent applied by a dense solve."""
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 3, 41)
+    u = [0.0, 0.7, 5.0]
+    a = HW.head_wings_body_sos(m, gs, phi, u)
+    b = HW.head_wings_body_resolvent(m, gs, phi, u)
+    for x, y in zip(a, b):
+        assert np.max(np.abs(x - y)) <= 1e-10 * np.max(np.abs(x))
+    # the body is the one of the Lanczos module's sum over states
+    assert np.max(np.abs(a[2] - LZ.body_sos(m, gs, phi, u))) <= 1e-12 * np.max(np.abs(a[2]))
+    for f in range(3):
+        assert np.max(np.abs(a[0][f] - a[0][f].T)) <= 1e-12 * np.max(np.abs(a[0][f]))
+        assert np.linalg.eigvalsh(a[0][f]).max() < 0
+
+
+def test_head_isotropic_for_a_centred_well():
+    """One spherical well at the centre of a cubic cell: the system has the cube's point
+    symmetry, so F_ab(iu) = f delta_ab."""
+    n = TINY.n
+    x = [np.arange(n[d]) * TINY.L[d] / n[d] for d in range(3)]
+    X, Y, Z = np.meshgrid(*x, indexing="ij")
+    c = TINY.L[0] / 2
+    V = -2.0 * np.exp(-((X - c) ** 2 + (Y - c) ** 2 + (Z - c) ** 2) / (2 * 1.2 ** 2))
+    m = R.make_model(TINY.L, TINY.n, TINY.ecut, V)
+    gs = R.ground_state(m, 1, full=True)
+    F, _, _ = HW.head_wings_body_sos(m, gs, inputs.trial_block(m.miller[m.nz], 1, 42), [0.0, 1.0])
+    for f in range(2):
+        d = np.diag(F[f])
+        assert np.max(np.abs(F[f] - np.diag(d))) <= 1e-10 * np.abs(d).max()
+        assert np.max(np.abs(d - d.mean())) <= 1e-10 * np.abs(d).max()
+
+
+def test_head_large_frequency_decay(tiny):
+    """u^2 F(iu) -> -(16 pi / Omega) sum_v <xi^a_v| A_v |xi^b_v> as u -> infinity."""
+    m, gs = tiny
+    X = HW.dipole_vectors(m, gs)
+    lim = np.zeros((3, 3))
+    for v in range(gs.C.shape[0]):
+        AX = (gs.H @ X[:, v, :].T).T - gs.eps[v] * X[:, v, :]
+        lim += np.real(X[:, v, :].conj() @ AX.T)
+    lim *= -16.0 * math.pi / m.volume
+    F, _, _ = HW.head_wings_body_sos(m, gs, inputs.trial_block(m.miller[m.nz], 1, 43), [1e4])
+    assert np.max(np.abs(F[0] * 1e8 - lim)) <= 1e-6 * np.max(np.abs(lim))
+
+
+def test_bz_integral_of_the_cube():
+    """For a cube of edge L: int_{|q_a| <= pi/L} d^3q / q^2 = (pi/L) C with
+    C = 24 int_0^1 atan(1/sqrt(1 + a^2)) / sqrt(1 + a^2) da (reduce to one face)."""
+    from scipy import integrate
+    Cc, _ = integrate.quad(lambda a: math.atan(1 / math.sqrt(1 + a * a)) / math.sqrt(1 + a * a), 0, 1,
+                           epsabs=1e-14)
+    want = (math.pi / 10.0) * 24 * Cc * 4 * math.pi / (2 * math.pi) ** 3
+    assert abs(HW.bz_coulomb_integral((10.0, 10.0, 10.0)) - want) <= 1e-9 * want
+    # an orthorhombic box, against the integral in spherical coordinates of the distance
+    # to the box surface (radial integral of q^2 / q^2), to that quadrature's accuracy
+    h = np.pi / np.array([10.0, 10.0, 20.0])
+
+    def radial(th, ph):
+        d = np.abs([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        return min(h[i] / d[i] for i in range(3) if d[i] > 0) * math.sin(th)
+    sph, _ = integrate.dblquad(radial, 0, math.pi / 2, 0, math.pi / 2, epsabs=1e-12)
+    want2 = 8 * sph * 4 * math.pi / (2 * math.pi) ** 3
+    assert abs(HW.bz_coulomb_integral((10.0, 10.0, 20.0)) - want2) <= 1e-6 * want2
+
+
+def test_bfinal_reduces_and_matches_the_block_inverse():
+    """Eq. Bfinal: without wings Lambda = (1 - B)^-1 B (Eq. linearalgebrachichi0); with
+    wings along one direction only (and the head along it) it is the body of the inverse
+    of the bordered matrix [[1 - f, -w^T], [-w, 1 - B]] minus 1, w = U_x / sqrt 3,
+    f = F_xx / 3 (Schur complement), and k is that matrix's Schur pivot."""
+    rng = np.random.default_rng(7)
+    n = 5
+    A = rng.standard_normal((n, n))
+    B = -(A @ A.T) / n                       # negative definite body
+    F = np.diag([-0.8, 0.0, 0.0])
+    U = np.zeros((3, n))
+    lam0, _, _ = HW.lambda_xi(F * 0, U, B, (10.0, 10.0, 10.0))
+    assert np.max(np.abs(lam0 - np.linalg.solve(np.eye(n) - B, B))) <= 1e-13
+    U[0] = 0.3 * rng.standard_normal(n)
+    lam, xi, k = HW.lambda_xi(F, U, B, (10.0, 10.0, 10.0))
+    w = U[0] / math.sqrt(3.0)
+    f = F[0, 0] / 3.0
+    Mbig = np.zeros((n + 1, n + 1))
+    Mbig[0, 0] = 1 - f
+    Mbig[0, 1:] = -w
+    Mbig[1:, 0] = -w
+    Mbig[1:, 1:] = np.eye(n) - B
+    inv = np.linalg.inv(Mbig)
+    assert np.max(np.abs(lam - (inv[1:, 1:] - np.eye(n)))) <= 1e-12
+    assert abs(k - 1.0 / inv[0, 0]) <= 1e-12
+
+
+def test_mutation_commutator_sign_caught(tiny, monkeypatch):
+    """A commutator of the wrong sign (+i G instead of -i G) flips the wings, which the
+    two-route agreement for U catches (the head, quadratic in g, would not)."""
+    m, gs = tiny
+    phi = inputs.trial_block(m.miller[m.nz], 2, 44)
+    good = HW.head_wings_body_sos(m, gs, phi, [0.5])[1]
+    real = HW.commutator_vectors
+    monkeypatch.setattr(HW, "commutator_vectors", lambda model, g: -real(model, g))
+    bad = HW.head_wings_body_resolvent(m, gs, phi, [0.5])[1]
+    assert np.max(np.abs(good - bad)) > 1e-3 * np.max(np.abs(good))
