@@ -294,6 +294,26 @@ typedef struct {
 int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
                       double* body, pdep_lanczos_stats* st);
 
+/* Head, wings and body of chi0bar at q -> 0 (Table limitqchi0) at the imaginary
+ * frequencies freq, in the basis phi (as pdep_body_lanczos), and the reducible
+ * quantities of Eq. Bfinal.  The dipole vectors xi^a_v = P_c r_a psi_v solve
+ * (H - e_v) xi = P_c [H, r_a] psi_v (Eq. commu; for the local potential here the
+ * commutator is -d/dr_a) with the context's precision and cg_tol; they join the
+ * Lanczos chains of pdep_body_lanczos as three more start vectors, so that, with
+ * f(A) = A (A^2 + u^2)^-1:
+ *   F[f][a][b]   = -(16 pi / Omega) sum_v <xi^a_v| f(A_v) |xi^b_v>                (Eq. finalF)
+ *   U[f][a][j]   = -(4 / Omega) sqrt(4 pi) sum_v <xi^a_v| f(A_v) |w_jv>          (Eq. finalU1)
+ *   B[f][i][j]   as pdep_body_lanczos                                             (Eq. finalB)
+ *   Lambda[f]    = (1 - B)^-1 B + (1/k) (1 - B)^-1 mu (1 - B)^-1,
+ *   Xi[f]        = (1 - k)/k * int_BZ d^3q / (2 pi)^3 4 pi / q^2                 (Eq. Bfinal)
+ * with k = 1 - Tr F / 3 - Tr[mu (1 - B)^-1], mu_ij = 1/3 sum_a U_ia U_aj (U_ia from the
+ * chains of the dipole vectors, Eq. finalU2) and the integral over the Brillouin zone of
+ * the Gamma-only cell, |q_a| <= pi / L_a.  All outputs are host arrays (caller-allocated,
+ * real); any of F, U, B, Lambda, Xi may be NULL.  PDEP_ENOTCONV if a dipole solve missed
+ * cg_tol (outputs still filled).  st may be NULL. */
+int pdep_head_wings(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
+                    double* F, double* U, double* B, double* Lambda, double* Xi, pdep_lanczos_stats* st);
+
 /* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
  * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
  * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "pdep_internal.h"
 
@@ -544,7 +545,7 @@ int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczo
         PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
         pdep::launch_expand_s1(n_pert, npw, g0, stage, n1, in_s, ld, s);
     }
-    const pdep::LanczosResult r = pdep::body_lanczos(c, n_pert, in_s, n_lanczos, n_freq, freq, body);
+    const pdep::LanczosResult r = pdep::body_lanczos(c, n_pert, in_s, 0, n_lanczos, n_freq, freq, body);
     const double ms = tm.stop();
     if (st) {
         st->chains = r.chains;
@@ -552,6 +553,51 @@ int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczo
         st->h_applications = r.h_applications;
         st->ms = ms;
     }
+    API_END
+}
+
+int pdep_head_wings(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
+                    double* F, double* U, double* B, double* Lambda, double* Xi, pdep_lanczos_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    if (st) std::memset(st, 0, sizeof(*st));
+    PDEP_REQUIRE(n_pert >= 1 && n_lanczos >= 1 && n_freq >= 1, PDEP_EINVAL, "n_pert, n_lanczos and n_freq must be >= 1");
+    PDEP_REQUIRE(phi && freq, PDEP_EINVAL, "null phi/freq");
+    for (int f = 0; f < n_freq; ++f)
+        PDEP_REQUIRE(std::isfinite(freq[f]) && freq[f] >= 0.0, PDEP_EINVAL, "frequencies must be finite and >= 0");
+    PDEP_REQUIRE((long)(n_pert + 3) * c.nv <= 65535L * 64, PDEP_EINVAL, "too many chains for one block");
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)n_pert * ld * sizeof(double2)));
+    if (dev) {
+        pdep::launch_expand_s1(n_pert, npw, g0, reinterpret_cast<const double2*>(phi), n1, in_s, ld, s);
+    } else {
+        PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pert * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pert * n1 * sizeof(double2)));
+        PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pert * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+        pdep::launch_expand_s1(n_pert, npw, g0, stage, n1, in_s, ld, s);
+    }
+    const size_t nb = (size_t)n_pert + 3, np = (size_t)n_pert;
+    std::vector<double> E((size_t)n_freq * nb * nb);
+    pdep::ApplyStats ds;
+    const pdep::LanczosResult r = pdep::body_lanczos(c, n_pert, in_s, 3, n_lanczos, n_freq, freq, E.data(), &ds);
+    for (int f = 0; f < n_freq; ++f)
+        pdep::bfinal(n_pert, E.data() + (size_t)f * nb * nb, c.basis.L, F ? F + 9 * (size_t)f : nullptr,
+                     U ? U + 3 * np * f : nullptr, B ? B + np * np * f : nullptr, Lambda ? Lambda + np * np * f : nullptr,
+                     Xi ? Xi + f : nullptr);
+    const double ms = tm.stop();
+    if (st) {
+        st->chains = r.chains;
+        st->max_length = r.max_length;
+        st->h_applications = r.h_applications;
+        st->ms = ms;
+    }
+    if (ds.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(ds.n_notconv) + " dipole-vector solves missed cg_tol");
     API_END
 }
 

@@ -28,7 +28,7 @@ namespace pdep {
 
 namespace {
 
-enum LzSlot { L_W = WS_LZ_W, L_WW, L_Q, L_QP, L_Z, L_O, L_SC, L_WORK };
+enum LzSlot { L_W = WS_LZ_W, L_WW, L_Q, L_QP, L_Z, L_O, L_SC, L_WORK, L_G, L_COEF };
 
 // z -= alpha q + beta qp (rows)
 __global__ void k_lz_orth(int K, long ld, const double* __restrict__ alpha, const double* __restrict__ beta,
@@ -55,6 +55,27 @@ __global__ void k_lz_next(int K, long ld, const double* __restrict__ inv, const 
 }
 
 dim3 grid_rows(int K, int n) { return dim3((unsigned)((K + 255) / 256), (unsigned)n); }
+
+// g[a * nv + v][k] = [H, r_a] psi_v = -i G_a(k) c_v(k) on the half sphere (a local
+// potential: the commutator is -d/dr_a); G: [3][K] Cartesian components
+__global__ void k_commutator_rows(int K, int nv, const double* __restrict__ G, const double2* __restrict__ psi,
+                                  long ldp, double2* __restrict__ g, long ld) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y, a = row / nv, v = row - a * nv;
+    if (k >= K) return;
+    const double ga = G[(long)a * K + k];
+    const double2 c = psi[(long)v * ldp + k];
+    g[(long)row * ld + k] = make_double2(ga * c.y, -ga * c.x);
+}
+
+// x[r] *= s
+__global__ void k_scale_rows(int K, long ld, double sc, double2* __restrict__ x) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const long o = (long)blockIdx.y * ld + k;
+    x[o].x *= sc;
+    x[o].y *= sc;
+}
 
 // x = Re y with (T - z) y = e_1 for the symmetric tridiagonal T (diagonal a[0..n),
 // off-diagonal b[0..n-1)) and z = e + i u: the first column of
@@ -90,9 +111,12 @@ void resolvent_column(int n, const double* a, const double* b, double e, double 
 
 }  // namespace
 
-LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int nl, int nfreq, const double* u, double* body) {
+LanczosResult body_lanczos(Ctx& c, int npert_in, const double2* phi, int ndir, int nl, int nfreq, const double* u,
+                           double* body, ApplyStats* dir_st) {
     LanczosResult res;
     const Basis& b = c.basis;
+    // start vectors: the npert_in potentials, then ndir (0 or 3) Cartesian directions
+    const int npert = npert_in + ndir;
     const int nv = c.nv, nh = half_len(b.npw), nrow = npert * nv;
     const long ld = sphere_ld(b.npw);
     hipStream_t s = c.stream;
@@ -109,7 +133,31 @@ LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int nl, int nf
     const size_t split_elems = (size_t)1 << 20;
     double2* work = static_cast<double2*>(c.ws(L_WORK, split_elems * sizeof(double2)));
 
-    rhs_half_rows(c, npert, phi, W, ld);
+    rhs_half_rows(c, npert_in, phi, W, ld);
+    if (ndir > 0) {
+        // the dipole vectors xi^a_v = P_c r_a psi_v: (H - e_v) xi = P_c [H, r_a] psi_v
+        // (Eq. commu), solved like the Sternheimer systems, scaled by sqrt(4 pi) (the
+        // Coulomb factor of the head potential) and appended as extra start vectors
+        const int nd = ndir * nv;
+        std::vector<double> G((size_t)3 * nh);
+        for (int k = 0; k < nh; ++k)
+            for (int a = 0; a < 3; ++a) G[(size_t)a * nh + k] = 2.0 * M_PI * b.miller[3 * (size_t)k + a] / b.L[a];
+        double* d_G = static_cast<double*>(c.ws(L_G, (size_t)3 * nh * sizeof(double) + 64));
+        PDEP_HIP(hipMemcpyAsync(d_G, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        double2* gb = Z;                                     // free until the chains start
+        double2* xd = W + (size_t)npert_in * nv * ld;
+        hipLaunchKernelGGL(k_commutator_rows, grid_rows(nh, nd), dim3(256), 0, s, nh, nv, d_G, c.psi64.as<double2>(),
+                           (long)b.npw, gb, ld);
+        PDEP_HIP(hipGetLastError());
+        project_c<double>(c, gb, ld, nd, static_cast<double2*>(c.ws(L_COEF, coef_bytes(nv, nd) + 64)));
+        PDEP_HIP(hipStreamSynchronize(s));
+        ApplyStats ds;
+        solve_rows(c, nd, gb, xd, ld, ds, nullptr);
+        project_c<double>(c, xd, ld, nd, static_cast<double2*>(c.ws(L_COEF, coef_bytes(nv, nd) + 64)));
+        hipLaunchKernelGGL(k_scale_rows, grid_rows(nh, nd), dim3(256), 0, s, nh, ld, std::sqrt(4.0 * M_PI), xd);
+        PDEP_HIP(hipGetLastError());
+        if (dir_st) *dir_st = ds;
+    }
     launch_fill_zero(d_zero, sizeof(double), s);
     launch_fill_zero(Qp, vb, s);
     launch_half_weights<double>(nrow, nh, W, ld, Ww, ld, s);
@@ -192,6 +240,137 @@ LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int nl, int nf
             }
         }
     return res;
+}
+
+namespace {
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on the roots of P_n
+// from the Chebyshev guesses, P_n by its three-term recurrence.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::abs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// In-place inverse of the n x n row-major matrix A (Gauss-Jordan, partial pivoting).
+void invert(int n, std::vector<double>& A) {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::abs(A[(size_t)r * n + col]) > std::abs(A[(size_t)piv * n + col])) piv = r;
+        PDEP_REQUIRE(A[(size_t)piv * n + col] != 0.0, PDEP_EDEVICE, "1 - B is singular");
+        if (piv != col)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
+                std::swap(I[(size_t)piv * n + j], I[(size_t)col * n + j]);
+            }
+        const double d = 1.0 / A[(size_t)col * n + col];
+        for (int j = 0; j < n; ++j) {
+            A[(size_t)col * n + j] *= d;
+            I[(size_t)col * n + j] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = A[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
+                I[(size_t)r * n + j] -= f * I[(size_t)col * n + j];
+            }
+        }
+    }
+    A.swap(I);
+}
+
+}  // namespace
+
+double bz_coulomb_integral(const double L[3]) {
+    // the box |q_a| <= h_a is six pyramids over its faces; on the face q_a = h_a the
+    // radial integral of q^2 / q^2 leaves h_a times the integral of 1 / (1 + s^2 + t^2)
+    // over |s| <= h_b / h_a, |t| <= h_c / h_a, whose t integral is closed:
+    // 2 atan(t_max / sqrt(1 + s^2)) / sqrt(1 + s^2)
+    std::vector<double> x, w;
+    gauss_legendre(64, x, w);
+    const double h[3] = {M_PI / L[0], M_PI / L[1], M_PI / L[2]};
+    double total = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double sb = h[(a + 1) % 3] / h[a], sc = h[(a + 2) % 3] / h[a];
+        double val = 0.0;
+        for (int i = 0; i < 64; ++i) {
+            const double s = sb * x[i], r = std::sqrt(1.0 + s * s);
+            val += sb * w[i] * 2.0 * std::atan(sc / r) / r;
+        }
+        total += 2.0 * h[a] * val;
+    }
+    return total * 4.0 * M_PI / (8.0 * M_PI * M_PI * M_PI);
+}
+
+void bfinal(int np, const double* E, const double L[3], double* F, double* U, double* B, double* Lam, double* Xi) {
+    const int nb = np + 3;
+    auto e = [&](int i, int j) { return E[(size_t)i * nb + j]; };
+    if (F)
+        for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb) F[a * 3 + bb] = e(np + a, np + bb);
+    if (U)
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < np; ++j) U[(size_t)a * np + j] = e(np + a, j);
+    if (B)
+        for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) B[(size_t)i * np + j] = e(i, j);
+    if (!Lam && !Xi) return;
+    // M = (1 - B)^-1, mu_ij = 1/3 sum_a U_ia U_aj (U_ia from the chains of the
+    // directions, U_aj from those of the potentials), f = Tr F / 3
+    std::vector<double> M((size_t)np * np), mu((size_t)np * np, 0.0);
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            M[(size_t)i * np + j] = (i == j ? 1.0 : 0.0) - e(i, j);
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a) acc += e(i, np + a) * e(np + a, j);
+            mu[(size_t)i * np + j] = acc / 3.0;
+        }
+    invert(np, M);
+    const double f = (e(np, np) + e(np + 1, np + 1) + e(np + 2, np + 2)) / 3.0;
+    double tr = 0.0;
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) tr += mu[(size_t)i * np + j] * M[(size_t)j * np + i];
+    const double k = 1.0 - f - tr;
+    if (Xi) *Xi = (1.0 - k) / k * bz_coulomb_integral(L);
+    if (!Lam) return;
+    // Lambda = M B + M mu M / k
+    std::vector<double> MB((size_t)np * np, 0.0), Mmu((size_t)np * np, 0.0);
+    for (int i = 0; i < np; ++i)
+        for (int l = 0; l < np; ++l) {
+            const double m = M[(size_t)i * np + l];
+            for (int j = 0; j < np; ++j) {
+                MB[(size_t)i * np + j] += m * e(l, j);
+                Mmu[(size_t)i * np + j] += m * mu[(size_t)l * np + j];
+            }
+        }
+    for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+            double acc = 0.0;
+            for (int l = 0; l < np; ++l) acc += Mmu[(size_t)i * np + l] * M[(size_t)l * np + j];
+            Lam[(size_t)i * np + j] = MB[(size_t)i * np + j] + acc / k;
+        }
 }
 
 }  // namespace pdep

@@ -361,8 +361,8 @@ enum WsSlot : int {
     WS_CAPI_IN = 28, WS_CAPI_OUT = 29, WS_CAPI_STAGE = 30,
     WS_SETUP_STICKS = 31, WS_DAV_THETA = 32, WS_DAV_C = 33, WS_DAV_DOTS = 34,
     WS_SCR_Y = 35,            // screening.hip: 35 .. 41
-    WS_LZ_W = 42,             // lanczos.hip: 42 .. 49
-    WS_COUNT = 50
+    WS_LZ_W = 42,             // lanczos.hip: 42 .. 51
+    WS_COUNT = 52
 };
 
 // Work space carved from a fixed device region instead of the allocator (the
@@ -452,6 +452,8 @@ void tune_cache_load(Ctx& c);
 void tune_cache_store(const Ctx& c);
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
+// bytes of the projection coefficients of nrows rows (either precision)
+size_t coef_bytes(int nv, int nrows);
 // entries of a half-sphere row (k <= (npw - 1) / 2, the centre G = 0 last)
 int half_len(int npw);
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
@@ -506,8 +508,20 @@ struct LanczosResult {
     int chains = 0, max_length = 0;
     long long h_applications = 0;
 };
-LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int n_lanczos, int nfreq, const double* u,
-                           double* body);
+// With ndir = 3 the three dipole vectors xi^a_v of Eq. commu join the start vectors
+// (after the npert potentials): body is then [nfreq][npert + 3][npert + 3] with the head
+// F in the last 3 x 3 block and the wings in the last rows / columns; dir_st (may be
+// null) receives the statistics of their Sternheimer solves.
+LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int ndir, int n_lanczos, int nfreq,
+                           const double* u, double* body, ApplyStats* dir_st = nullptr);
+
+// The integral of 4 pi / q^2 over the Brillouin zone of a Gamma-only orthorhombic cell,
+// |q_a| <= pi / L_a, divided by (2 pi)^3.
+double bz_coulomb_integral(const double L[3]);
+// Eq. Bfinal at one frequency from the extended matrix E [(np + 3) x (np + 3)] of
+// body_lanczos with the three directions: F (3 x 3), U (U_aj, 3 x np), B (np x np),
+// Lambda (np x np) and Xi (a scalar), each output may be null.
+void bfinal(int np, const double* E, const double L[3], double* F, double* U, double* B, double* Lam, double* Xi);
 
 // davidson.hip
 void ground_state(Ctx& c);

@@ -174,6 +174,7 @@ def load(path: str = LIB_PATH):
     lib.pdep_eigs.argtypes = [P, C.c_int, C.c_uint64, P, C.POINTER(EigOpts), D, P, C.POINTER(EigStats)]
     lib.chibar_apply.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(ChibarStats)]
     lib.pdep_body_lanczos.argtypes = [P, C.c_int, P, C.c_int, C.c_int, D, D, C.POINTER(LanczosStats)]
+    lib.pdep_head_wings.argtypes = [P, C.c_int, P, C.c_int, C.c_int, D, D, D, D, D, D, C.POINTER(LanczosStats)]
     lib.pdep_destroy.argtypes = [P]
     lib.pdep_profile_enable.argtypes = [C.c_int]
     lib.pdep_profile_enable.restype = C.c_int
@@ -193,8 +194,8 @@ def load(path: str = LIB_PATH):
                  "pdep_server_destroy"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
-                 "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_body_lanczos", "pdep_eigs",
-                 "pdep_destroy"):
+                 "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_body_lanczos", "pdep_head_wings",
+                 "pdep_eigs", "pdep_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -422,6 +423,22 @@ class Context:
                                            f.ctypes.data_as(C.POINTER(C.c_double)),
                                            body.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)))
         return body, st.as_dict()
+
+    def head_wings(self, phi, freq, n_lanczos=40, allow_notconv=False):
+        """Head F [nf, 3, 3], wings U [nf, 3, n], body B [nf, n, n], Lambda [nf, n, n]
+        and Xi [nf] at the imaginary frequencies freq (q -> 0), and the stats."""
+        n = int(phi.shape[0])
+        p, keep = self._ptr(phi, np.complex128, (n, self.n_pw - 1))
+        f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).ravel())
+        nf = f.size
+        out = dict(F=np.empty((nf, 3, 3)), U=np.empty((nf, 3, n)), B=np.empty((nf, n, n)),
+                   Lambda=np.empty((nf, n, n)), Xi=np.empty(nf))
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        st = LanczosStats()
+        _check(self._lib.pdep_head_wings(self._h, n, p, int(n_lanczos), nf, dp(f), dp(out["F"]), dp(out["U"]),
+                                         dp(out["B"]), dp(out["Lambda"]), dp(out["Xi"]), C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        return out, st.as_dict()
 
     def eigs(self, n_pdep, seed=0, phi0=None, tol=1e-9, maxit=60, max_subspace=0, n_buffer=0,
              want_basis=False, allow_notconv=False, reducible=False, scr_tol=0.0, scr_maxit=0):
