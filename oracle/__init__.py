@@ -18,11 +18,19 @@ point, doubly occupied bands):
 * PDEP eigenpairs = lowest eigenpairs of chi0bar (Eq. eigendecompzerofreq);
 * the reducible chibar = (1 - chi0bar)^-1 chi0bar (Eq. linearalgebrachichi0) and, as a
   second route, the self-consistent DFPT loop with the Hartree response (Eqs. LF and
-  LFHartree, Fig. pdepscheme right panel); eps^-1 = 1 + chibar (Eq. epsilonandchi).
+  LFHartree, Fig. pdepscheme right panel); eps^-1 = 1 + chibar (Eq. epsilonandchi);
+* the body, head and wings of chi0bar at imaginary frequencies (Eqs. AdlerWiser, finalF,
+  finalU1, finalB) by sums over states, by resolvent solves and by deflated Lanczos
+  chains (Sec. 2.4), and Lambda, Xi of Eq. Bfinal;
+* G0W0 for occupied states: exchange, the correlation self-energy by contour deformation
+  (Sec. 2.5) and the quasiparticle equation (Eqs. QPenergies, QPconZ).
 
 Modules:
   planewave  -- sphere, grid, naive DFT, dense H
   response   -- ground state, direct and sum-over-states Sternheimer, dn, chi0bar, PDEP
   matfree    -- matrix-free FFT + CG version of the same chain (used for CPU timing and
                 sampled checks at sizes where dense matrices do not fit)
+  lanczos    -- body of chi0bar at imaginary frequencies, sums over states and chains
+  headwings  -- head and wings at q -> 0, the Brillouin-zone Coulomb integral, Eq. Bfinal
+  gw         -- Sigma_X, Sigma_C by contour deformation, QP energies
 """
