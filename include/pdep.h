@@ -314,6 +314,73 @@ int pdep_body_lanczos(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczo
 int pdep_head_wings(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos, int n_freq, const double* freq,
                     double* F, double* U, double* B, double* Lambda, double* Xi, pdep_lanczos_stats* st);
 
+/* ------------------------------------------------------ G0W0 quasiparticle energies ---
+ * Options of pdep_qp_energies; a zero field takes the default in brackets. */
+typedef struct {
+    int n_lanczos;        /* chain length (Sec. 2.4) [40] */
+    int n_freq;           /* Gauss-Legendre nodes of the imaginary-axis integral [64] */
+    double omega0;        /* scale (Ha) of the node map u = omega0 t / (1 - t), t in (0, 1) [0.5] */
+    double eta;           /* broadening (Ha) of W_p at the real frequencies of the residues [1e-3] */
+    double e_fermi;       /* Fermi level (Ha); 0: midgap, which needs the context's own ground
+                           * state (caller orbitals leave the gap unknown: then it is required) */
+    double secant_tol;    /* stop when |E_k+1 - E_k| <= secant_tol (Ha) [1e-8] */
+    int secant_maxit;     /* [40] */
+    double dE;            /* step (Ha) of the central difference for Z [1e-3] */
+} pdep_qp_opts;
+
+/* Per state.  Energies in Ha. */
+typedef struct {
+    double eps_ks;        /* e_n */
+    double sigma_x;       /* <n|Sigma_X|n> */
+    double sigma_c_ks[2]; /* Re, Im <n|Sigma_C(e_n)|n> */
+    double z;             /* renormalisation 1 / (1 - d Re Sigma_C / dE) at e_n */
+    double e_lin;         /* linearised root (Eq. QPconZ) */
+    double e_qp;          /* secant root of Eq. QPenergies with Re Sigma_C */
+    double sigma_c_qp[2]; /* Re, Im <n|Sigma_C(e_qp)|n> */
+    int iterations;       /* secant iterations */
+    int converged;        /* 1 if |E_k+1 - E_k| reached secant_tol */
+} pdep_qp_result;
+
+typedef struct {
+    int chains;              /* Lanczos chains run */
+    int max_length;
+    long long h_applications;
+    int secant_iterations;   /* sum over states */
+    int residue_points;      /* real frequencies at which W_p was evaluated */
+    double ms;
+} pdep_qp_stats;
+
+/* G0W0 quasiparticle energies of the occupied states `states` (band indices 0 .. N_v - 1,
+ * n_states of them) with W_p in the basis phi (n_pdep x N_pw' complex, Hermitian-symmetric,
+ * orthonormal rows on S': normally the PDEP eigenvectors of pdep_eigs):
+ *   W_p(w) = Xi(w) + (1/Omega) sum_ij V_i Lambda_ij(w) V_j                     (Eq. Wchihb)
+ * with Lambda, Xi from the head, wings and body of pdep_head_wings (Eq. Bfinal), and
+ *   Sigma_X = -sum_{m occ} [I_BZ delta_mn + (4 pi / Omega) sum_{G in S'} |rho_mn(G)|^2 / |G|^2]
+ *   Sigma_C(E) = -(1/2 pi) int dw <n| G_KS(E + i w) W_p(i w) |n>
+ *                + sum_m f_m <n m| W_p(e_m - E) |m n>                 (Eqs. contourdeformationfinal, fcontour)
+ *   E_qp = e_n + Sigma_X + Re Sigma_C(E_qp) - vxc_n                                (Eq. QPenergies)
+ * rho_mn = Fwd(conj(u_m) u_n); I_BZ is the integral of 4 pi / q^2 over the Brillouin zone
+ * of the Gamma-only cell (as Xi uses).  G_KS is split by P_v and P_c (Eq. Glehmann): the
+ * occupied part is the explicit sum over the N_v orbitals (Eq. MVfinal), the empty part
+ * comes from the Lanczos chains of the deflated Hamiltonian started at P_c V_j u_n, which
+ * are the body's chains of band n (Eq. MCfinal; each chain's tridiagonal matrix is
+ * diagonalised).  The imaginary-axis integral is taken pole by pole: the Lorentzian of
+ * each pole with W_p(0) exactly, the rest on n_freq Gauss-Legendre nodes of
+ * u = omega0 t / (1 - t).  W_p at the residues' real frequencies carries the broadening
+ * eta (Eq. AdlerWiser), so Sigma_C is complex there.  The QP equation starts from the
+ * linearised root (Eq. QPconZ, Z by a central difference of step dE) and is solved by the
+ * secant method through e_n and e_lin.  vxc: n_states values <n|V_xc|n> (NULL: zero; the
+ * model Hamiltonian here has no exchange-correlation potential of its own).  Empty-state
+ * residues come from the chains' Ritz values when a QP energy rises above e_fermi.
+ * out: n_states results (host).  energies / sigma_c_e (both NULL or both set): n_e energies
+ * per state (host [n_states][n_e]) at which <n|Sigma_C(E)|n> is also returned (host
+ * [n_states][n_e][2], Re and Im).  phi follows PDEP_DEVICE_PTRS.  PDEP_ENOTCONV if a
+ * dipole solve missed cg_tol or a secant iteration did not converge (outputs still
+ * filled); PDEP_EINVAL for bad states or options.  opts and st may be NULL. */
+int pdep_qp_energies(pdep_ctx* ctx, int n_pdep, const double* phi, int n_states, const int* states,
+                     const double* vxc, const pdep_qp_opts* opts, pdep_qp_result* out, int n_e,
+                     const double* energies, double* sigma_c_e, pdep_qp_stats* st);
+
 /* PDEP eigenpairs: the n_pdep lowest (most screened) eigenvalues lambda_i of
  * chi0bar by block Davidson in FP64 (Sec. 2.3, Davidson iteration from a random
  * orthonormal start).  phi0: NULL (start drawn from `seed` by the library's own

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-SOURCES = ["basis.hip", "fft.hip", "linalg.hip", "gemm_x3.hip", "solver.hip", "davidson.hip", "screening.hip", "lanczos.hip", "capi.hip", "prof.hip", "server.hip"]
+SOURCES = ["basis.hip", "fft.hip", "linalg.hip", "gemm_x3.hip", "solver.hip", "davidson.hip", "screening.hip", "lanczos.hip", "gw.hip", "capi.hip", "prof.hip", "server.hip"]
 
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",

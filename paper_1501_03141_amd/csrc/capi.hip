@@ -601,6 +601,79 @@ int pdep_head_wings(pdep_ctx* ctx, int n_pert, const double* phi, int n_lanczos,
     API_END
 }
 
+int pdep_qp_energies(pdep_ctx* ctx, int n_pdep, const double* phi, int n_states, const int* states,
+                     const double* vxc, const pdep_qp_opts* opts, pdep_qp_result* out, int n_e,
+                     const double* energies, double* sigma_c_e, pdep_qp_stats* st) {
+    API_BEGIN
+    check_ctx(ctx);
+    Ctx& c = ctx->c;
+    if (st) std::memset(st, 0, sizeof(*st));
+    const int npw = c.basis.npw, n1 = npw - 1, g0 = c.basis.g0;
+    PDEP_REQUIRE(phi && states && out, PDEP_EINVAL, "null phi/states/out");
+    PDEP_REQUIRE(n_pdep >= 1 && n_pdep < n1, PDEP_EINVAL, "n_pdep out of range");
+    PDEP_REQUIRE(n_states >= 1 && n_states <= 64, PDEP_EINVAL, "n_states must be 1 .. 64");
+    for (int k = 0; k < n_states; ++k)
+        PDEP_REQUIRE(states[k] >= 0 && states[k] < c.nv, PDEP_EINVAL, "states must be occupied band indices");
+    PDEP_REQUIRE(n_e >= 0 && (n_e == 0 || (energies && sigma_c_e)), PDEP_EINVAL,
+                 "energies and sigma_c_e are needed for n_e > 0");
+    pdep_qp_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.n_lanczos == 0) o.n_lanczos = 40;
+    if (o.n_freq == 0) o.n_freq = 64;
+    if (o.omega0 == 0.0) o.omega0 = 0.5;
+    if (o.eta == 0.0) o.eta = 1e-3;
+    if (o.secant_tol == 0.0) o.secant_tol = 1e-8;
+    if (o.secant_maxit == 0) o.secant_maxit = 40;
+    if (o.dE == 0.0) o.dE = 1e-3;
+    PDEP_REQUIRE(o.n_lanczos >= 1 && o.n_freq >= 1 && o.n_freq <= 4096 && o.omega0 > 0.0 && o.eta > 0.0 &&
+                     o.secant_tol > 0.0 && o.secant_maxit >= 1 && o.dE > 0.0 && std::isfinite(o.e_fermi),
+                 PDEP_EINVAL, "bad qp options");
+    if (o.e_fermi == 0.0) {
+        PDEP_REQUIRE(c.gap > 0.0, PDEP_EINVAL,
+                     "e_fermi is required: the gap is unknown for orbitals given by the caller");
+        o.e_fermi = c.eps[c.nv - 1] + 0.5 * c.gap;
+    }
+    PDEP_REQUIRE(o.e_fermi > c.eps[c.nv - 1], PDEP_EINVAL, "e_fermi must lie above the highest occupied energy");
+    if (vxc)
+        for (int k = 0; k < n_states; ++k) PDEP_REQUIRE(std::isfinite(vxc[k]), PDEP_EINVAL, "vxc is not finite");
+    for (int k = 0; k < n_states * n_e; ++k)
+        PDEP_REQUIRE(std::isfinite(energies[k]), PDEP_EINVAL, "energies are not finite");
+    PDEP_REQUIRE((long)(n_pdep + 3) * c.nv <= 65535L * 64, PDEP_EINVAL, "too many chains for one block");
+    const long ld = pdep::sphere_ld(npw);
+    const bool dev = (c.opts.flags & PDEP_DEVICE_PTRS) != 0;
+    hipStream_t s = c.stream;
+    Timer tm(s);
+    double2* in_s = static_cast<double2*>(c.ws(C_IN, (size_t)n_pdep * ld * sizeof(double2)));
+    if (dev) {
+        pdep::launch_expand_s1(n_pdep, npw, g0, reinterpret_cast<const double2*>(phi), n1, in_s, ld, s);
+    } else {
+        PDEP_REQUIRE(all_finite(phi, (size_t)2 * n_pdep * n1), PDEP_EINVAL, "phi contains NaN or Inf");
+        double2* stage = static_cast<double2*>(c.ws(C_STAGE, (size_t)n_pdep * n1 * sizeof(double2)));
+        PDEP_HIP(hipMemcpyAsync(stage, phi, (size_t)n_pdep * n1 * sizeof(double2), hipMemcpyHostToDevice, s));
+        pdep::launch_expand_s1(n_pdep, npw, g0, stage, n1, in_s, ld, s);
+    }
+    pdep::ApplyStats ds;
+    const pdep::QpStats q =
+        pdep::qp_energies(c, n_pdep, in_s, n_states, states, vxc, o, out, n_e, energies, sigma_c_e, &ds);
+    const double ms = tm.stop();
+    int notconv = 0;
+    for (int k = 0; k < n_states; ++k) notconv += out[k].converged ? 0 : 1;
+    if (st) {
+        st->chains = q.chains;
+        st->max_length = q.max_length;
+        st->h_applications = q.h_applications;
+        st->secant_iterations = q.secant_iterations;
+        st->residue_points = q.residue_points;
+        st->ms = ms;
+    }
+    if (ds.n_notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(ds.n_notconv) + " dipole-vector solves missed cg_tol");
+    if (notconv > 0)
+        return fail(PDEP_ENOTCONV, std::to_string(notconv) + " quasiparticle equations did not converge");
+    API_END
+}
+
 int pdep_eigs(pdep_ctx* ctx, int n_pdep, uint64_t seed, const double* phi0, const pdep_eig_opts* eo_in,
               double* eps_out, double* basis_out, pdep_eig_stats* st) {
     API_BEGIN

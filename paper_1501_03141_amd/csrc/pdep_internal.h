@@ -361,8 +361,9 @@ enum WsSlot : int {
     WS_CAPI_IN = 28, WS_CAPI_OUT = 29, WS_CAPI_STAGE = 30,
     WS_SETUP_STICKS = 31, WS_DAV_THETA = 32, WS_DAV_C = 33, WS_DAV_DOTS = 34,
     WS_SCR_Y = 35,            // screening.hip: 35 .. 41
-    WS_LZ_W = 42,             // lanczos.hip: 42 .. 51
-    WS_COUNT = 52
+    WS_LZ_W = 42,             // lanczos.hip: 42 .. 56
+    WS_GW = 57,               // gw.hip: 57 .. 61
+    WS_COUNT = 62
 };
 
 // Work space carved from a fixed device region instead of the allocator (the
@@ -452,8 +453,9 @@ void tune_cache_load(Ctx& c);
 void tune_cache_store(const Ctx& c);
 // Leading dimension (elements) of stored sphere vectors.
 long sphere_ld(int npw);
-// bytes of the projection coefficients of nrows rows (either precision)
+// bytes of the projection coefficients of nrows rows (either precision), coef_ld(nv) per row
 size_t coef_bytes(int nv, int nrows);
+long coef_ld(int nv);
 // entries of a half-sphere row (k <= (npw - 1) / 2, the centre G = 0 last)
 int half_len(int npw);
 template <typename T> void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S);
@@ -477,6 +479,10 @@ void chi0bar_sphere(Ctx& c, int npert, const double2* phi, double2* out, ApplySt
 // with V_i = Re Inv(sqrt(4 pi)/|G| phi_i) (the Sternheimer right-hand sides up to sign);
 // phi: npert rows on S (stride sphere_ld(npw), G = 0 entry zero)
 void rhs_half_rows(Ctx& c, int npert, const double2* phi, double2* W, long ld);
+// The projection coefficients <c_m| Fwd(V_i u_v)> of the last rhs_half_rows call (device,
+// row i * nv + v, coef_ld(nv) complex entries per row with zero imaginary parts), valid
+// until the next projection through the solver's coefficient buffer.
+const double2* rhs_coefficients(Ctx& c);
 // z = P_c H P_c q on FP64 half-sphere rows (zero_shift: one device double 0.0)
 void apply_deflated_h64(Ctx& c, const double2* q, double2* z, long ld, int nrows, const double* zero_shift);
 // upper bound of the device work space chi0bar_sphere takes for npert perturbations in
@@ -502,19 +508,48 @@ struct ScreenResult {
 ScreenResult chibar_sphere(Ctx& c, int n, const double2* phi, double2* out, double tol, int maxit,
                            ApplyStats& st);
 
-// lanczos.hip: the body of chi0bar at imaginary frequencies u (host array) in the basis
-// phi (npert rows on S, device) by deflated Lanczos chains; body (host) [nfreq][npert][npert]
+// lanczos.hip: deflated Lanczos chains of P_c H P_c (Sec. 2.4) from the start vectors
+// w_jv = P_c Fwd(V_j u_v) of the basis potentials phi (npert rows on S, device) and,
+// with ndir = 3, the dipole vectors xi^a_v of Eq. commu scaled by sqrt(4 pi) (rows
+// npert .. npert + 2).  Row r = j * nv + v; chains advance together as one block.
+struct Chains {
+    int npert = 0, nv = 0, nl = 0, nrow = 0;   // npert counts the directions
+    std::vector<double> alpha, beta;            // [nl][nrow]: T's diagonal, off-diagonal
+    std::vector<int> len;                       // chain length (0: zero start vector)
+    std::vector<double> wn;                     // ||w_r||
+    const double2* O = nullptr;                 // device [nl][nv][j][i]: Re <w_iv|q_n of chain jv>
+    long long h_applications = 0;
+    int chains = 0, max_length = 0;
+};
+// coef (may be null) receives <c_m| Fwd(V_i u_v)> before P_c, [npert_in * nv][nv] (row
+// i * nv + v, column m): the occupied-state pair coefficients.  Ch.O stays valid until
+// the next call that uses the Lanczos work space.
+void run_chains(Ctx& c, int npert_in, const double2* phi, int ndir, int nl, Chains& ch, ApplyStats* dir_st,
+                std::vector<double>* coef);
+// A frequency point: every transition of energy D enters as [1/(D - a) + 1/(D - b)] / 2.
+// Imaginary frequency i u: a = i u, b = -i u (D / (D^2 + u^2)); real frequency w with
+// broadening eta: a = -w + i eta, b = w + i eta.
+struct FreqPoint {
+    double2 a, b;
+};
+// The matrix of -(4/Omega) sum_v <w_iv| g(A_v) |w_jv> over all start vectors at nz
+// points (g as above, A_v = P_c (H - e_v) P_c), host [nz][npert][npert] complex.
+void chain_body(Ctx& c, const Chains& ch, int nz, const FreqPoint* z, double2* out);
+
 struct LanczosResult {
     int chains = 0, max_length = 0;
     long long h_applications = 0;
 };
-// With ndir = 3 the three dipole vectors xi^a_v of Eq. commu join the start vectors
-// (after the npert potentials): body is then [nfreq][npert + 3][npert + 3] with the head
-// F in the last 3 x 3 block and the wings in the last rows / columns; dir_st (may be
-// null) receives the statistics of their Sternheimer solves.
+// The body of chi0bar at imaginary frequencies u (host array) in the basis phi, body
+// (host) [nfreq][npert][npert].  With ndir = 3 the directions join (after the npert
+// potentials): body is then [nfreq][npert + 3][npert + 3] with the head F in the last
+// 3 x 3 block and the wings in the last rows / columns; dir_st (may be null) receives
+// the statistics of their Sternheimer solves.
 LanczosResult body_lanczos(Ctx& c, int npert, const double2* phi, int ndir, int n_lanczos, int nfreq,
                            const double* u, double* body, ApplyStats* dir_st = nullptr);
 
+// Gauss-Legendre nodes and weights of order n on [-1, 1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // The integral of 4 pi / q^2 over the Brillouin zone of a Gamma-only orthorhombic cell,
 // |q_a| <= pi / L_a, divided by (2 pi)^3.
 double bz_coulomb_integral(const double L[3]);
@@ -522,6 +557,17 @@ double bz_coulomb_integral(const double L[3]);
 // body_lanczos with the three directions: F (3 x 3), U (U_aj, 3 x np), B (np x np),
 // Lambda (np x np) and Xi (a scalar), each output may be null.
 void bfinal(int np, const double* E, const double L[3], double* F, double* U, double* B, double* Lam, double* Xi);
+// The same at a real frequency, where E is complex symmetric.
+void bfinal_complex(int np, const double2* E, const double L[3], double2* Lam, double2* Xi);
+
+// gw.hip: G0W0 quasiparticle energies of occupied states (pdep_qp_energies)
+struct QpStats {
+    int chains = 0, max_length = 0, secant_iterations = 0, residue_points = 0;
+    long long h_applications = 0;
+};
+QpStats qp_energies(Ctx& c, int np, const double2* phi, int nst, const int* states, const double* vxc,
+                    const pdep_qp_opts& o, pdep_qp_result* out, int ne, const double* energies, double* sig_e,
+                    ApplyStats* dir_st);
 
 // davidson.hip
 void ground_state(Ctx& c);

@@ -1082,6 +1082,8 @@ void rhs_half_rows(Ctx& c, int npert, const double2* phi, double2* W, long ld) {
     project_c<double>(c, W, ld, nrow, static_cast<double2*>(c.ws(W_S, coef_bytes(nv, nrow))));
 }
 
+const double2* rhs_coefficients(Ctx& c) { return static_cast<const double2*>(c.ws_current(W_S)); }
+
 void apply_deflated_h64(Ctx& c, const double2* q, double2* z, long ld, int nrows, const double* zero_shift) {
     apply_op<double>(c, q, z, ld, nrows, zero_shift, 1, true, true,
                      c.ws(W_STICKS, (size_t)nrows * sticks_row_bytes(c)),

@@ -102,6 +102,32 @@ class ChibarStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class QpOpts(C.Structure):
+    _fields_ = [("n_lanczos", C.c_int), ("n_freq", C.c_int), ("omega0", C.c_double), ("eta", C.c_double),
+                ("e_fermi", C.c_double), ("secant_tol", C.c_double), ("secant_maxit", C.c_int),
+                ("dE", C.c_double)]
+
+
+class QpResult(C.Structure):
+    _fields_ = [("eps_ks", C.c_double), ("sigma_x", C.c_double), ("sigma_c_ks", C.c_double * 2),
+                ("z", C.c_double), ("e_lin", C.c_double), ("e_qp", C.c_double), ("sigma_c_qp", C.c_double * 2),
+                ("iterations", C.c_int), ("converged", C.c_int)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["sigma_c_ks"] = complex(self.sigma_c_ks[0], self.sigma_c_ks[1])
+        d["sigma_c_qp"] = complex(self.sigma_c_qp[0], self.sigma_c_qp[1])
+        return d
+
+
+class QpStats(C.Structure):
+    _fields_ = [("chains", C.c_int), ("max_length", C.c_int), ("h_applications", C.c_longlong),
+                ("secant_iterations", C.c_int), ("residue_points", C.c_int), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LanczosStats(C.Structure):
     _fields_ = [("chains", C.c_int), ("max_length", C.c_int), ("h_applications", C.c_longlong),
                 ("ms", C.c_double)]
@@ -175,6 +201,8 @@ def load(path: str = LIB_PATH):
     lib.chibar_apply.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(ChibarStats)]
     lib.pdep_body_lanczos.argtypes = [P, C.c_int, P, C.c_int, C.c_int, D, D, C.POINTER(LanczosStats)]
     lib.pdep_head_wings.argtypes = [P, C.c_int, P, C.c_int, C.c_int, D, D, D, D, D, D, C.POINTER(LanczosStats)]
+    lib.pdep_qp_energies.argtypes = [P, C.c_int, P, C.c_int, C.POINTER(C.c_int), D, C.POINTER(QpOpts),
+                                     C.POINTER(QpResult), C.c_int, D, D, C.POINTER(QpStats)]
     lib.pdep_destroy.argtypes = [P]
     lib.pdep_profile_enable.argtypes = [C.c_int]
     lib.pdep_profile_enable.restype = C.c_int
@@ -439,6 +467,40 @@ class Context:
                                          dp(out["B"]), dp(out["Lambda"]), dp(out["Xi"]), C.byref(st)),
                allow=(PDEP_ENOTCONV,) if allow_notconv else ())
         return out, st.as_dict()
+
+    def qp_energies(self, phi, states, vxc=None, energies=None, n_lanczos=40, n_freq=64, omega0=0.5,
+                    eta=1e-3, e_fermi=0.0, secant_tol=1e-8, secant_maxit=40, dE=1e-3, allow_notconv=False):
+        """G0W0 quasiparticle energies of the occupied `states` with W_p in the basis phi:
+        ([dict per state], Sigma_C at `energies` [n_states, n_e] complex or None, stats)."""
+        n = int(phi.shape[0])
+        p, keep = self._ptr(phi, np.complex128, (n, self.n_pw - 1))
+        st_idx = np.ascontiguousarray(np.asarray(states, dtype=np.int32).ravel())
+        ns = st_idx.size
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        vx = None
+        vx_arr = None
+        if vxc is not None:
+            vx_arr = np.ascontiguousarray(np.asarray(vxc, dtype=np.float64).ravel())
+            assert vx_arr.size == ns
+            vx = dp(vx_arr)
+        ne = 0
+        en = None
+        sig = None
+        if energies is not None:
+            en = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).reshape(ns, -1))
+            ne = en.shape[1]
+            sig = np.empty((ns, ne, 2))
+        res = (QpResult * ns)()
+        o = QpOpts(int(n_lanczos), int(n_freq), float(omega0), float(eta), float(e_fermi), float(secant_tol),
+                   int(secant_maxit), float(dE))
+        st = QpStats()
+        _check(self._lib.pdep_qp_energies(self._h, n, p, ns, st_idx.ctypes.data_as(C.POINTER(C.c_int)), vx,
+                                          C.byref(o), res, ne, dp(en) if en is not None else None,
+                                          dp(sig) if sig is not None else None, C.byref(st)),
+               allow=(PDEP_ENOTCONV,) if allow_notconv else ())
+        out = [r.as_dict() for r in res]
+        sc = sig[..., 0] + 1j * sig[..., 1] if sig is not None else None
+        return out, sc, st.as_dict()
 
     def eigs(self, n_pdep, seed=0, phi0=None, tol=1e-9, maxit=60, max_subspace=0, n_buffer=0,
              want_basis=False, allow_notconv=False, reducible=False, scr_tol=0.0, scr_maxit=0):

@@ -65,6 +65,7 @@ def test_null_arguments(lib):
     assert lib.pdep_setup(None, None, None, None, None, C.byref(h)) == pdep.PDEP_EINVAL
     assert lib.chi0_apply(None, 1, None, None, None) == pdep.PDEP_EINVAL
     assert lib.pdep_get_info(None, None) == pdep.PDEP_EINVAL
+    assert lib.pdep_qp_energies(None, 1, None, 1, None, None, None, None, 0, None, None, None) == pdep.PDEP_EINVAL
     assert lib.pdep_destroy(None) == pdep.PDEP_OK
 
 
