@@ -86,9 +86,13 @@ struct SplitMix64 {
 
 // rocBLAS handle for rocSOLVER calls: the context's (created on first use and kept for
 // the context's lifetime, or supplied by the server worker), bound to the context stream.
+// The device work space of each call comes from the context allocator: the call is made
+// once as a size query, the context's work-space buffer grows to that size and is handed
+// to the handle, and then the call runs.
 struct Solver {
+    Ctx& c;
     rocblas_handle h = nullptr;
-    explicit Solver(Ctx& c) {
+    explicit Solver(Ctx& cc) : c(cc) {
         if (!c.blas) {
             rocblas_handle nh = nullptr;
             if (rocblas_create_handle(&nh) != rocblas_status_success)
@@ -98,6 +102,19 @@ struct Solver {
         }
         h = static_cast<rocblas_handle>(c.blas);
         rocblas_set_stream(h, c.stream);
+    }
+    template <typename F>
+    rocblas_status run(F&& call) {
+        size_t need = 0;
+        PDEP_REQUIRE(rocblas_start_device_memory_size_query(h) == rocblas_status_success, PDEP_EDEVICE,
+                     "rocblas size query failed");
+        call();
+        PDEP_REQUIRE(rocblas_stop_device_memory_size_query(h, &need) == rocblas_status_success, PDEP_EDEVICE,
+                     "rocblas size query failed");
+        c.blas_ws.ensure(&c.al, std::max<size_t>(need, 256));
+        PDEP_REQUIRE(rocblas_set_workspace(h, c.blas_ws.get(), c.blas_ws.bytes()) == rocblas_status_success,
+                     PDEP_EDEVICE, "rocblas_set_workspace failed");
+        return call();
     }
 };
 
@@ -155,9 +172,11 @@ void dense_eig(Workspace& ws, Solver& sv, std::vector<double2>& A, int m, bool r
             for (size_t i = 0; i < Ar.size(); ++i) Ar[i] = A[i].x;
             double* dA = static_cast<double*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
             PDEP_HIP(hipMemcpyAsync(dA, Ar.data(), Ar.size() * sizeof(double), hipMemcpyHostToDevice, s));
-            st = divide_conquer
-                     ? rocsolver_dsyevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo)
-                     : rocsolver_dsyev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo);
+            st = sv.run([&] {
+                return divide_conquer
+                           ? rocsolver_dsyevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo)
+                           : rocsolver_dsyev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, dA, m, dW, dE, dinfo);
+            });
             PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_dsyev(d) failed");
             PDEP_HIP(hipMemcpyAsync(Ar.data(), dA, Ar.size() * sizeof(double), hipMemcpyDeviceToHost, s));
             PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -167,9 +186,11 @@ void dense_eig(Workspace& ws, Solver& sv, std::vector<double2>& A, int m, bool r
             double2* dA = static_cast<double2*>(ws.get(D_M, (size_t)m * m * sizeof(double2)));
             auto* zA = reinterpret_cast<rocblas_double_complex*>(dA);
             PDEP_HIP(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-            st = divide_conquer
-                     ? rocsolver_zheevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo)
-                     : rocsolver_zheev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo);
+            st = sv.run([&] {
+                return divide_conquer
+                           ? rocsolver_zheevd(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo)
+                           : rocsolver_zheev(sv.h, rocblas_evect_original, rocblas_fill_lower, m, zA, m, dW, dE, dinfo);
+            });
             PDEP_REQUIRE(st == rocblas_status_success, PDEP_EDEVICE, "rocsolver_zheev(d) failed");
             PDEP_HIP(hipMemcpyAsync(vec.data(), dA, vec.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
             PDEP_HIP(hipMemcpyAsync(w.data(), dW, m * sizeof(double), hipMemcpyDeviceToHost, s));

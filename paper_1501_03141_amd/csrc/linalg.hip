@@ -279,6 +279,113 @@ __global__ __launch_bounds__(256) void k_gemm_update(int M, int N, int K, const 
             }
 }
 
+// Y[n][kr] -= sum_m S[n][m] A[m][kr] in real arithmetic: the projection update of FP64
+// half-sphere rows with real coefficients (rows read as real vectors of 2 K doubles; S
+// real, row stride lds).  Four waves (2 x 2), each WR x WC blocks of 16 x 16 outputs on
+// the FP64 matrix cores (16 x 16 x 4 steps): workgroup tile 32 WR rows x 32 WC real
+// columns.  The Y tile is loaded first, so that its latency hides behind the product;
+// m is staged 16 at a time through LDS while the next stage's tiles are loaded into
+// registers.
+constexpr int kDgM = 16, kDgPad = 2, kDgWR = 4, kDgWC = 2;
+template <int WR, int WC>
+__global__ __launch_bounds__(256, 2) void k_dgemm_sub(int M, int N, int K2, const double* __restrict__ A, long lda2,
+                                                      const double* __restrict__ S, long lds,
+                                                      double* __restrict__ Y, long ldy2) {
+    constexpr int TN = 32 * WR, TK = 32 * WC;
+    constexpr int SJ = TN * kDgM / 256, AJ = TK * kDgM / 512;   // per-thread loads (S doubles, A double2s)
+    static_assert(SJ >= 1 && AJ >= 1, "tile too small for the loaders");
+    __shared__ double Ss[kDgM][TN + kDgPad];   // [m][n]
+    __shared__ double As[kDgM][TK + kDgPad];   // [m][kr]
+    using Op = Mfma<double>;
+    const int k0 = blockIdx.x * TK, n0 = blockIdx.y * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = (wave & 1) * 16 * WR, wk = (wave >> 1) * 16 * WC;
+    const int nb = n0 + wn + (lane >> 4), kb = k0 + wk + (lane & 15);
+    double yv[WR][WC][4];
+#pragma unroll
+    for (int q = 0; q < WR; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = nb + 16 * q + 4 * i;   // Op::row(lane, i) = 4 i + lane / 16
+#pragma unroll
+            for (int r = 0; r < WC; ++r) {
+                const int kr = kb + 16 * r;
+                yv[q][r][i] = (n < N && kr < K2) ? Y[(long)n * ldy2 + kr] : 0.0;
+            }
+        }
+    Op::acc acc[WR][WC];
+#pragma unroll
+    for (int a = 0; a < WR; ++a)
+#pragma unroll
+        for (int b = 0; b < WC; ++b) acc[a][b] = Op::acc{0, 0, 0, 0};
+    // S: thread -> (m = tid % 16, n = tid / 16 + 16 j); A: thread -> (m, kr pair) with the
+    // TK / 2 pairs of a row of A fastest
+    constexpr int AP = TK / 2;
+    const int sm = tid & 15, sn = tid >> 4;
+    double ps[SJ];
+    double2 pa[AJ];
+    auto fetch = [&](int mc) {
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int n = n0 + sn + 16 * j, m = mc + sm;
+            ps[j] = (n < N && m < M) ? S[(long)n * lds + m] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < AJ; ++j) {
+            const int e = tid + 256 * j;
+            const int m = mc + e / AP, kr = k0 + 2 * (e % AP);
+            if (m < M && kr + 1 < K2) {
+                pa[j] = *reinterpret_cast<const double2*>(A + (long)m * lda2 + kr);
+            } else {
+                pa[j].x = (m < M && kr < K2) ? A[(long)m * lda2 + kr] : 0.0;
+                pa[j].y = 0.0;
+            }
+        }
+    };
+    fetch(0);
+    for (int mc = 0; mc < M; mc += kDgM) {
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) Ss[sm][sn + 16 * j] = ps[j];
+#pragma unroll
+        for (int j = 0; j < AJ; ++j) {
+            const int e = tid + 256 * j;
+            As[e / AP][2 * (e % AP)] = pa[j].x;
+            As[e / AP][2 * (e % AP) + 1] = pa[j].y;
+        }
+        __syncthreads();
+        if (mc + kDgM < M) fetch(mc + kDgM);
+#pragma unroll
+        for (int kk = 0; kk < kDgM; kk += 4) {
+            const int mr = kk + (lane >> 4), c = lane & 15;
+            double a[WR], b[WC];
+#pragma unroll
+            for (int q = 0; q < WR; ++q) a[q] = Ss[mr][wn + 16 * q + c];
+#pragma unroll
+            for (int r = 0; r < WC; ++r) b[r] = As[mr][wk + 16 * r + c];
+#pragma unroll
+            for (int q = 0; q < WR; ++q)
+#pragma unroll
+                for (int r = 0; r < WC; ++r) acc[q][r] = Op::mma(a[q], b[r], acc[q][r]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < WR; ++q)
+#pragma unroll
+        for (int r = 0; r < WC; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = nb + 16 * q + 4 * i, kr = kb + 16 * r;
+                if (n < N && kr < K2) Y[(long)n * ldy2 + kr] = yv[q][r][i] - acc[q][r][i];
+            }
+}
+
+// out[r][m] = Re S[r][m] for nrows rows of lds entries
+__global__ void k_real_coefs(long n, const double2* __restrict__ in, double* __restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i].x;
+}
+
 // ------------------------------------------------------------------- reductions ---
 // Half-sphere rows (half != 0) hold the entries k <= c of a Hermitian-symmetric vector,
 // the centre G = 0 last (k = K - 1); every other entry stands for itself and its mirror
@@ -645,6 +752,28 @@ void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const c
         hipLaunchKernelGGL((k_gemm_update<T, false>), grid, dim3(256), 0, s, M, N, K, A, lda, S, lds, alpha, beta, Y,
                            ldy);
     PDEP_HIP(hipGetLastError());
+}
+
+void launch_dgemm_sub(int M, int N, int K, const double2* A, long lda, const double2* S, long lds, double2* Y,
+                      long ldy, double* sr, size_t sr_elems, hipStream_t s) {
+    if (N <= 0 || K <= 0 || M <= 0) return;
+    constexpr int TN = 32 * kDgWR, TK = 32 * kDgWC;
+    // the real parts of the coefficients, contiguous, in blocks of rows that fit sr
+    const int rblk = (int)std::min<long>(N, (long)(sr_elems / (size_t)lds) / TN * TN);
+    PDEP_REQUIRE(rblk >= 1, PDEP_EINVAL, "dgemm_sub: coefficient buffer too small");
+    for (int r0 = 0; r0 < N; r0 += rblk) {
+        const int nr = std::min(rblk, N - r0);
+        const long ne = (long)nr * lds;
+        hipLaunchKernelGGL(k_real_coefs, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, S + (long)r0 * lds, sr);
+        PDEP_HIP(hipGetLastError());
+        PDEP_REQUIRE((nr + TN - 1) / TN <= 65535, PDEP_EINVAL, "dgemm_sub: too many rows");
+        dim3 grid((2 * K + TK - 1) / TK, (nr + TN - 1) / TN);
+        ProfScope prof_(K_GEMM_UPDATE64, s, 16.0 * M * K + 8.0 * nr * M + 32.0 * nr * K, 4.0 * (double)M * nr * K);
+        hipLaunchKernelGGL((k_dgemm_sub<kDgWR, kDgWC>), grid, dim3(256), 0, s, M, nr, 2 * K,
+                           reinterpret_cast<const double*>(A), 2 * lda, sr, lds,
+                           reinterpret_cast<double*>(Y + (long)r0 * ldy), 2 * ldy);
+        PDEP_HIP(hipGetLastError());
+    }
 }
 
 template <typename T>

@@ -219,6 +219,13 @@ void launch_gemm_ahb(int M, int N, int K, const cplx<T>* A, long lda, const cplx
                      long lds, cplx<T>* work, size_t work_elems, hipStream_t s, bool real_out = false);
 // Y[n][k] = beta*Y + alpha * sum_m A[m][k] * S[n][m]   (S: N x M; Y must not alias A or S);
 // real_s: the imaginary parts of S are zero (and not read)
+// Y -= S A for FP64 half-sphere rows with real coefficients (the imaginary parts of the
+// complex coefficient buffer S are ignored): N rows of K complex entries (2 K reals), A:
+// M rows (stride lda complex), S: N rows of M (stride lds complex), on the FP64 matrix
+// cores.  sr: work space of sr_elems doubles for the contiguous real coefficients (rows
+// are processed in blocks that fit it).
+void launch_dgemm_sub(int M, int N, int K, const double2* A, long lda, const double2* S, long lds, double2* Y,
+                      long ldy, double* sr, size_t sr_elems, hipStream_t s);
 template <typename T>
 void launch_gemm_update(int M, int N, int K, const cplx<T>* A, long lda, const cplx<T>* S, long lds,
                         double alpha, double beta, cplx<T>* Y, long ldy, hipStream_t s, bool real_s = false);
@@ -418,6 +425,7 @@ struct Ctx {
     // solver work space (grown on demand)
     void* blas = nullptr;                 // rocblas_handle for rocSOLVER calls
     bool own_blas = false;
+    Buf blas_ws;                          // rocSOLVER work space, from the context allocator
     // the inner FP32 solves of the mixed mode use the BF16x3 projection products (set per
     // refinement step: rows that diverge with them are solved again with FP32 products)
     bool pc_x3 = false;

@@ -24,8 +24,6 @@
 // the kinetic/shift epilogue -> P_c GEMM pair, and K the diagonal kinetic preconditioner
 // 1/max(1/2|G|^2 - e_v, kPrecondFloor) with a floor of 0.1 Ha (the paper does not fix K;
 // it only changes iteration counts).
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -84,30 +82,6 @@ size_t coef_bytes(int nv, int nrows) { return (size_t)nrows * coef_ld(nv) * size
 // copies psi32w / psi64w), and the update touches the half sphere only.  S: work space
 // of coef_bytes(nv, nrows).  In the BF16x3 mode the FP32 pair runs on the bf16 matrix
 // cores (three products, real coefficients).
-namespace {
-
-// out[i] = Re in[i]
-__global__ void k_real_parts(long n, const double2* __restrict__ in, double* __restrict__ out) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = in[i].x;
-}
-
-// The context's rocBLAS handle (created on first use), bound to the context stream.
-rocblas_handle ctx_blas(Ctx& c) {
-    if (!c.blas) {
-        rocblas_handle nh = nullptr;
-        PDEP_REQUIRE(rocblas_create_handle(&nh) == rocblas_status_success, PDEP_EDEVICE,
-                     "rocblas_create_handle failed");
-        c.blas = nh;
-        c.own_blas = true;
-    }
-    rocblas_handle h = static_cast<rocblas_handle>(c.blas);
-    rocblas_set_stream(h, c.stream);
-    return h;
-}
-
-}  // namespace
-
 // Rows from which a first application tunes launch shapes by timing them on its data.
 constexpr int kTuneRows = 1024;
 
@@ -227,37 +201,13 @@ void project_c(Ctx& c, cplx<T>* Y, long ld, int nrows, double2* S) {
     if constexpr (sizeof(T) == sizeof(double)) {
         // Real coefficients over half spheres.  S = Re(Psi_w^H Y) by the split-K MFMA GEMM
         // (real parts written as complex with zero imaginary parts); with the rows read as
-        // real vectors of 2 nh doubles, Y -= S Psi is a plain DGEMM (rocBLAS, column-major
-        // views of the row-major arrays).
+        // real vectors of 2 nh doubles, Y -= S Psi is a real GEMM on the FP64 matrix cores.
         if (nrows <= 0) return;
         launch_gemm_ahb<T>(nv, nrows, nh, c.psi64w.as<double2>(), npw, Y, ld, St, lds, work, split_elems, c.stream,
                            true);
-        if (c.arena) {
-            // no library calls (rocBLAS may allocate device memory): the MFMA update
-            launch_gemm_update<T>(nv, nrows, nh, psi_of<T>(c), psi_ld<T>(c), St, lds, -1.0, 1.0, Y, ld, c.stream,
-                                  true);
-            return;
-        }
-        // the real parts, contiguous, in the split-K buffer (free once the GEMM is done),
-        // in blocks of rows that fit it
-        double* Sr = reinterpret_cast<double*>(work);
-        const int rblk = (int)std::min<long>(nrows, (long)(2 * split_elems) / lds);
-        rocblas_handle h = ctx_blas(c);
-        const double one = 1.0, mone = -1.0;
-        ProfScope prof_(K_GEMM_UPDATE64, c.stream, 16.0 * nv * nh + 32.0 * nrows * nh + 24.0 * nv * nrows,
-                        4.0 * nv * (double)nrows * nh);
-        for (int r0 = 0; r0 < nrows; r0 += rblk) {
-            const int nr = std::min(rblk, nrows - r0);
-            const long ne = (long)nr * lds;
-            hipLaunchKernelGGL(k_real_parts, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c.stream, ne,
-                               reinterpret_cast<const double2*>(St + (long)r0 * lds), Sr);
-            PDEP_HIP(hipGetLastError());
-            PDEP_REQUIRE(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, 2 * nh, nr, nv, &mone,
-                                       reinterpret_cast<const double*>(c.psi64.get()), 2 * npw, Sr, lds, &one,
-                                       reinterpret_cast<double*>(Y + (long)r0 * ld), 2 * ld) ==
-                             rocblas_status_success,
-                         PDEP_EDEVICE, "rocblas_dgemm (projection update) failed");
-        }
+        // (the split-K buffer is free once the coefficient GEMM is done)
+        launch_dgemm_sub(nv, nrows, nh, c.psi64.as<double2>(), npw, St, lds, Y, ld, reinterpret_cast<double*>(work),
+                         2 * split_elems, c.stream);
     } else {
         const long lp = sphere_ld(npw);
         const float2* pw = c.psi32w.as<float2>();
