@@ -213,10 +213,14 @@ def serving_bench(n_jobs: int, max_running: int, log):
                     time.sleep(dt)
                 w = job.workload
                 tickets.append(srv.submit(w.L, w.n, w.ecut, inputs.vloc(w), w.n_v, w.n_pdep, seed=w.seed,
-                                          precision=pdep.PDEP_MIXED_FP32, cg_tol=1e-8, eig_tol=1e-6,
+                                          precision=pdep.PDEP_MIXED_BF16X3, cg_tol=1e-8, eig_tol=1e-6,
                                           eig_maxit=60, n_buffer=8, gap_min=1e-4))
-            for job, t in zip(jobs, tickets):
+                if len(tickets) % 25 == 0:
+                    log(f"  submitted {len(tickets)}/{len(jobs)} at {time.perf_counter() - t0:.1f} s")
+            for k, (job, t) in enumerate(zip(jobs, tickets)):
                 srv.wait(t, -1)
+                if (k + 1) % 25 == 0:
+                    log(f"  finished {k + 1}/{len(jobs)} at {time.perf_counter() - t0:.1f} s")
                 state, res, _ = srv.poll(t)
                 if state == pdep.JOB_DONE:
                     ok += 1
@@ -244,7 +248,7 @@ def serving_bench(n_jobs: int, max_running: int, log):
             "p99_ms": round(float(np.percentile(lat2, 99)), 1) if lat2 else None,
             "failed": len(jobs2) - ok2, "peak_running": peak2,
             "sample": f"{n_jobs}-job Poisson stream (grids 24^3/32^3/48^3, N_v 8..128, N_pdep 16..64), "
-                      "mixed precision, Davidson to 1e-6 with 8 buffer vectors"}
+                      "BF16x3 mixed precision, Davidson to 1e-6 with 8 buffer vectors"}
 
 
 def main():

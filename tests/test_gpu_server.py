@@ -1,6 +1,7 @@
 """Serving on the GPU: jobs submitted to a running server (several running at once on
 their own streams) give the same dielectric eigenvalues as the same job run alone on a
-fresh context; latencies are reported."""
+fresh context, in both mixed modes (FP32 and BF16x3 P_c products); latencies are
+reported."""
 import time
 
 import numpy as np
@@ -23,12 +24,13 @@ def _jobs():
 
 
 @pytest.mark.timeout(600)
-def test_server_results_match_standalone():
+@pytest.mark.parametrize("prec", [pdep.PDEP_MIXED_FP32, pdep.PDEP_MIXED_BF16X3])
+def test_server_results_match_standalone(prec):
     jobs = _jobs()
     alone = []
     for w in jobs:
         V = inputs.vloc(w)
-        with pdep.Context(w.L, w.n, w.ecut, V, w.n_v, precision=pdep.PDEP_MIXED_FP32, cg_tol=w.cg_tol,
+        with pdep.Context(w.L, w.n, w.ecut, V, w.n_v, precision=prec, cg_tol=w.cg_tol,
                           gap_min=1e-4, use_torch=False) as c:
             eps, _, _ = c.eigs(w.n_pdep, seed=w.seed, tol=1e-7, maxit=60)
         alone.append(eps)
@@ -37,7 +39,7 @@ def test_server_results_match_standalone():
         t0 = time.perf_counter()
         for w in jobs:
             tickets.append(srv.submit(w.L, w.n, w.ecut, inputs.vloc(w), w.n_v, w.n_pdep, seed=w.seed,
-                                      precision=pdep.PDEP_MIXED_FP32, cg_tol=w.cg_tol, eig_tol=1e-7,
+                                      precision=prec, cg_tol=w.cg_tol, eig_tol=1e-7,
                                       gap_min=1e-4))
             time.sleep(0.05)
         for t in tickets:
