@@ -160,6 +160,8 @@ void build_basis(const pdep_cell& cell, Basis& b) {
     d.nz = b.n[2];
     d.ax = b.ax;
     d.mxmax = b.mxmax;
+    d.mymax = 0;
+    for (int c = 0; c < b.ax; ++c) d.mymax = std::max(d.mymax, -b.col_my0[c]);
     d.npw = b.npw;
     d.ns = (int)b.slab_pos.size();
     d.sld = (d.ns + 31) / 32 * 32;

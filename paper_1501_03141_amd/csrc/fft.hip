@@ -912,11 +912,64 @@ __global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cpl
     }
 }
 
+// Stick rows of nzh consecutive z slabs (nzh * sld elements, contiguous in the sticks
+// buffer) to LDS and back, in 16-byte pieces with up to K loads in flight per thread
+// before the first LDS write: a loop that waited for each load before its LDS write
+// would pay the memory latency once per piece.  The copy back writes only the sphere's
+// sticks (index < ns within each slab row), so the padding of the rows is left as it is.
+template <typename E, int NT, int K = 8>
+__device__ __forceinline__ void stage_rows_in(E* lds, const E* g, int nzh, int sld) {
+    static_assert(sizeof(E) == 8 || sizeof(E) == 16, "8- or 16-byte elements");
+    constexpr int PER = 16 / sizeof(E);   // elements per piece (sld is a multiple of 32)
+    const int n = nzh * sld / PER;
+    const float4* src = reinterpret_cast<const float4*>(g);
+    float4* dst = reinterpret_cast<float4*>(lds);
+    for (int b = 0; b < n; b += K * NT) {
+        float4 r[K];
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            r[k] = src[min(b + (int)threadIdx.x + k * NT, n - 1)];
+        });
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int i = b + (int)threadIdx.x + k * NT;
+            if (i < n) dst[i] = r[k];
+        });
+    }
+}
+template <typename E, int NT, int K = 8>
+__device__ __forceinline__ void stage_rows_out(E* g, const E* lds, int nzh, int sld, int ns) {
+    constexpr int PER = 16 / sizeof(E);
+    const int n = nzh * sld / PER;
+    const float4* src = reinterpret_cast<const float4*>(lds);
+    float4* dst = reinterpret_cast<float4*>(g);
+    for (int b = 0; b < n; b += K * NT) {
+        float4 r[K];
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            r[k] = src[min(b + (int)threadIdx.x + k * NT, n - 1)];
+        });
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int i = b + (int)threadIdx.x + k * NT;
+            if (i < n) {
+                const int e = i * PER;
+                const int ein = e - (e / sld) * sld;   // index within the slab row
+                if (ein + PER <= ns) {
+                    dst[i] = r[k];
+                } else if (PER == 2 && ein < ns) {
+                    reinterpret_cast<float2*>(dst + i)[0] = make_float2(r[k].x, r[k].y);
+                }
+            }
+        });
+    }
+}
+
 // Slab pass of H (V multiply), FP32, NX = NY = NL, with every line in registers: a
 // workgroup of 256 threads (four waves) takes ZG = 256 / NL consecutive z slabs of one
 // row.  Lines are read at clamped indices and masked afterwards, so the loads of a
 // line issue back to back.
-//   1. the ZG stick rows are copied to LDS (coalesced);
+//   1. the ZG stick rows are copied to LDS (stage_rows_in);
 //   2. one thread per (slab, non-empty x column), packed into the first ZG * ax
 //      threads: its y line from the stick row (zeros outside the column's my range),
 //      inverse y DFT, written to the transpose plane [slab][iy][column];
@@ -927,15 +980,19 @@ __global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cpl
 //   5. stick rows copied back.
 // The stick rows and the transpose plane share LDS: every thread holds its line in
 // registers across the barrier that separates reading one from writing the other.
-// MX >= 0: the sphere's largest |mx| as a compile-time constant (must equal d.mxmax), so
-// that the x lines read their non-empty columns and write back the needed outputs at
-// fixed indices and the unused outputs of the forward x transform are never computed.
+// MX >= 0: the sphere's largest |mx| and |my| are at most MX, and |mx| reaches it (the
+// launcher checks both), so the x lines read their non-empty columns and write back
+// the needed outputs at fixed indices, and the y lines hold zeros at the frequencies
+// |my| > MX as compile-time constants: the DFT stages that only see those zeros, and the
+// outputs of the forward transforms that are never stored, are not computed.
 // (A zero-padded (column, my) square for the y lines as well measured no faster.)
 template <int NL, int MX>
 __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, float2* __restrict__ sticks,
                                                      const float* __restrict__ Vr) {
     constexpr int ZG = 256 / NL;
     constexpr int HALF = (NL + 1) / 2;   // index i holds frequency i (i < HALF) or i - NL
+    // frequency my of index i lies outside the compiled y range (a zero of every y line)
+    constexpr auto y_out = [](int my) { return MX >= 0 && (my < -MX || my > MX); };
     extern __shared__ __align__(16) unsigned char smem[];
     float2* lds = reinterpret_cast<float2*>(smem);
     const int mxmax = MX >= 0 ? MX : d.mxmax, sld = d.sld, nz = d.nz;
@@ -949,9 +1006,7 @@ __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, f
     const bool zact = zl < nzh && zl < ZG;
     const bool col = zc < nzh;
     float2* g = sticks + ((long)row * nz + z0) * sld;
-    const int ns = d.ns;
-    for (int zz = 0; zz < nzh; ++zz)
-        for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+    stage_rows_in<float2, 256>(lds, g, nzh, sld);
     __syncthreads();
 
     int s0 = 0, my0 = 0;
@@ -963,8 +1018,12 @@ __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, f
         sfor<0, NL>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int my = i < HALF ? i : i - NL;
-            const float2 val = sr[min(max(my, my0), -my0)];
-            v[i] = (my >= my0 && my <= -my0) ? val : make_float2(0.f, 0.f);
+            if constexpr (y_out(my)) {
+                v[i] = make_float2(0.f, 0.f);
+            } else {
+                const float2 val = sr[min(max(my, my0), -my0)];
+                v[i] = (my >= my0 && my <= -my0) ? val : make_float2(0.f, 0.f);
+            }
         });
     }
     __syncthreads();
@@ -1016,12 +1075,13 @@ __global__ __launch_bounds__(256) void k_slab_hv_reg(FftDims d, BasisTables t, f
         sfor<0, NL>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int my = i < HALF ? i : i - NL;
-            if (my >= my0 && my <= -my0) sw[my] = X[i];
+            if constexpr (!y_out(my)) {
+                if (my >= my0 && my <= -my0) sw[my] = X[i];
+            }
         });
     }
     __syncthreads();
-    for (int zz = 0; zz < nzh; ++zz)
-        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+    stage_rows_out<float2, 256>(g, lds, nzh, sld, d.ns);
 }
 
 // ---------------------------------------------- FP64 slab pass, lines on lane quads ---
@@ -1161,8 +1221,7 @@ __global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t
         const double ang = 6.283185307179586476925 * tid / NL;
         tw[tid] = make_double2(cos(ang), sin(ang));
     }
-    for (int zz = 0; zz < nzh; ++zz)
-        for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+    stage_rows_in<double2, 256, 4>(lds, g, nzh, sld);
     __syncthreads();
     const QuadLane Lp = quad_lane<+1>(tl), Lm = quad_lane<-1>(tl);
 
@@ -1422,8 +1481,7 @@ __global__ __launch_bounds__(256) void k_slab_fwd_quad64(FftDims d, BasisTables 
     __syncthreads();
     double2* g = sticks + ((long)row * nz + z0) * sld;
     const int ns = d.ns;
-    for (int zz = 0; zz < nzh; ++zz)
-        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+    stage_rows_out<double2, 256, 4>(g, lds, nzh, sld, ns);
 }
 
 constexpr int kMaxAcc = 24;
@@ -1765,7 +1823,7 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
                     constexpr int ZG = 256 / N;
                     ProfScope prof_(K_SLAB_HV, s, bytes, flops);
                     const dim3 grid((d.nz + ZG - 1) / ZG, nrows);
-                    if (d.mxmax == slab_mx_const(N))
+                    if (d.mxmax == slab_mx_const(N) && d.mymax <= slab_mx_const(N))
                         hipLaunchKernelGGL((k_slab_hv_reg<N, slab_mx_const(N)>), grid, dim3(256), lds, s, d, t,
                                            sticks, Vz);
                     else

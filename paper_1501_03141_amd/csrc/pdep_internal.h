@@ -126,6 +126,7 @@ struct AxisPlan {
 struct FftDims {
     int nx, ny, nz;
     int ax, mxmax;
+    int mymax;                // largest |my| of the sphere's sticks
     int npw;
     int ns;                   // number of sticks
     int sld;                  // stick leading dimension of the sticks buffer (>= ns)
