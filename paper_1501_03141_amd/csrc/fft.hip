@@ -619,6 +619,87 @@ __global__ __launch_bounds__(kThreads) void k_sphere_to_sticks_pair(FftDims d, B
     }
 }
 
+// Register-resident form of the paired sphere-to-sticks pass (FP32): 128 threads, one z
+// stick each with its line in registers; threads 0..63 take kPairStickGroup front sticks,
+// threads 64..127 their mirrors.  The half-sphere entries of the group (every entry of
+// the front sticks up to the centre c) are read once, with all loads of a thread in
+// flight, into LDS for both rows: a front stick takes a_k + i b_k at its mz, its mirror
+// conj(a_k) + i conj(b_k) at -mz (the coefficients of functions real in r at -G).  The
+// middle stick (its own mirror, handled by its front thread) takes its entries k > c from
+// their mirrors npw - 1 - k, conjugated, and the centre real.
+template <int NZ>
+__global__ __launch_bounds__(2 * kPairStickGroup) void k_sphere_to_sticks_pair_reg(
+    FftDims d, BasisTables t, const float2* __restrict__ in, long ld_in, int nrows, int group,
+    float2* __restrict__ sticks) {
+    constexpr int HALF = (NZ + 1) / 2;
+    constexpr int GS = kPairStickGroup, NT = 2 * kPairStickGroup, LQ = 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2* la = reinterpret_cast<float2*>(smem);
+    float2* lb = la + d.sgp_max;
+    const int nfront = (d.ns + 1) / 2;
+    const int s0 = blockIdx.x * GS, pr = blockIdx.y;
+    const int nf = min(GS, nfront - s0);
+    const int c = (d.npw - 1) / 2;
+    const int kb = t.stick_start[s0], ne = min(t.stick_start[s0 + nf], c + 1) - kb;
+    const PairRows rw = pair_rows(pr, group, nrows);
+    const bool has_b = rw.has_b;
+    const float2* a = in + (long)rw.a * ld_in + kb;
+    const float2* b = a + ld_in;
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < ne; e0 += LQ * NT) {
+        float2 ra[LQ], rb[LQ];
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int e = min(e0 + tid + q * NT, ne - 1);
+            ra[q] = a[e];
+            rb[q] = has_b ? b[e] : make_float2(0.f, 0.f);
+        });
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int e = e0 + tid + q * NT;
+            if (e < ne) {
+                la[e] = ra[q];
+                lb[e] = rb[q];
+            }
+        });
+    }
+    __syncthreads();
+    const bool mir = tid >= GS;                 // wave-uniform
+    const int j = mir ? tid - GS : tid;
+    if (j >= nf) return;
+    const int sf = s0 + j, sk = mir ? d.ns - 1 - sf : sf;
+    if (mir && sk == sf) return;                // the middle stick: its front thread writes it
+    const int ks = t.stick_start[sf], kz = (t.stick_start[sf + 1] - ks - 1) / 2;
+    const int k0 = ks + kz;                     // front entry of mz = 0
+    float2 v[NZ], X[NZ];
+    sfor<0, NZ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int mz = i < HALF ? i : i - NZ;
+        float2 w = make_float2(0.f, 0.f);
+        if (mz >= -kz && mz <= kz) {
+            const int k = k0 + (mir ? -mz : mz);   // front entry (of -G for the mirror)
+            const bool back = k > c;               // the upper half of the middle stick
+            const int e = (back ? d.npw - 1 - k : k) - kb;
+            float2 va = la[e], vb = lb[e];
+            if (k == c) {
+                va.y = 0.f;
+                vb.y = 0.f;
+            } else if (back != mir) {
+                va.y = -va.y;
+                vb.y = -vb.y;
+            }
+            w = make_float2(va.x - vb.y, va.y + vb.x);
+        }
+        v[i] = w;
+    });
+    dft_reg<float, +1, NZ, 1>(v, X);
+    float2* dst = sticks + (long)pr * NZ * d.sld + sk;
+    sfor<0, NZ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dst[(long)i * d.sld] = X[i];
+    });
+}
+
 // Sticks of packed row j -> half-sphere rows a, b (pair_rows) with the epilogue
 // EPI_SHIFTED_H, out = F + (kin - shift[row % nshift]) x and, when dot_part is non-null,
 // the partial sums of Re<x, out> over the full sphere (weight 2 off the centre) per
@@ -776,24 +857,41 @@ __global__ __launch_bounds__(2 * kPairStickGroup) void k_sticks_to_sphere_pair_r
     const float2* xa = x + (long)ra * ld_x;
     const float2* xb = xa + ld_x;
     double acca = 0.0, accb = 0.0;
-    for (int k = kb + tid; k < k1; k += NT) {
-        const float2 W = bufF[k - kb], Wm = bufM[k - kb];
-        const double w = k == c ? 1.0 : 2.0;
-        const float kk = kin[k];
-        {
-            const float2 xv = xa[k];
-            const float dk = kk - sha;
-            const float2 ov = make_float2(half * (W.x + Wm.x) + dk * xv.x, half * (W.y - Wm.y) + dk * xv.y);
-            oa[k] = ov;
-            acca += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
-        }
-        if (has_b) {
-            const float2 xv = xb[k];
-            const float dk = kk - shb;
-            const float2 ov = make_float2(half * (W.y + Wm.y) + dk * xv.x, half * (Wm.x - W.x) + dk * xv.y);
-            ob[k] = ov;
-            accb += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
-        }
+    // LQ entries per thread at a time: their kinetic energies and x values are loaded
+    // before the first is used (clamped indices, so every load is in bounds)
+    constexpr int LQ = 8;
+    for (int e0 = kb + tid; e0 < k1; e0 += LQ * NT) {
+        float kk[LQ];
+        float2 xva[LQ], xvb[LQ];
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int k = min(e0 + q * NT, k1 - 1);
+            kk[q] = kin[k];
+            xva[q] = xa[k];
+            xvb[q] = has_b ? xb[k] : make_float2(0.f, 0.f);
+        });
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int k = e0 + q * NT;
+            if (k < k1) {
+                const float2 W = bufF[k - kb], Wm = bufM[k - kb];
+                const double w = k == c ? 1.0 : 2.0;
+                {
+                    const float2 xv = xva[q];
+                    const float dk = kk[q] - sha;
+                    const float2 ov = make_float2(half * (W.x + Wm.x) + dk * xv.x, half * (W.y - Wm.y) + dk * xv.y);
+                    oa[k] = ov;
+                    acca += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+                }
+                if (has_b) {
+                    const float2 xv = xvb[q];
+                    const float dk = kk[q] - shb;
+                    const float2 ov = make_float2(half * (W.y + Wm.y) + dk * xv.x, half * (Wm.x - W.x) + dk * xv.y);
+                    ob[k] = ov;
+                    accb += w * ((double)xv.x * (double)ov.x + (double)xv.y * (double)ov.y);
+                }
+            }
+        });
     }
     if (dot_part) {
         red[0][tid] = acca;
@@ -1697,6 +1795,19 @@ void launch_sphere_to_sticks_pair(const FftDims& d, const BasisTables& t, const 
     const double hp = (double)((d.npw + 1) / 2) * sizeof(cplx<T>), sk = (double)d.nz * d.ns * sizeof(cplx<T>);
     ProfScope prof_(sizeof(T) == sizeof(double) ? K_SPHERE_TO_STICKS64 : K_SPHERE_TO_STICKS, s,
                     (double)nrows * hp + (double)npair * sk);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (pair_reg_ok(d)) {
+            const dim3 grid(((d.ns + 1) / 2 + kPairStickGroup - 1) / kPairStickGroup, npair);
+            const size_t lds = 2 * (size_t)d.sgp_max * sizeof(float2);
+            with_n(d.nz, [&]<int NZ>() {
+                if constexpr (NZ > 0 && NZ <= 48)
+                    hipLaunchKernelGGL((k_sphere_to_sticks_pair_reg<NZ>), grid, dim3(2 * kPairStickGroup), lds, s, d,
+                                       t, in, ld_in, nrows, group > 0 ? group : nrows, sticks);
+            });
+            PDEP_HIP(hipGetLastError());
+            return;
+        }
+    }
     with_n(d.nz, [&]<int NZ>() {
         hipLaunchKernelGGL((k_sphere_to_sticks_pair<T, NZ>), stick_grid<T>(d, npair), dim3(kThreads), stick_lds<T>(d), s,
                            d, t, in, ld_in, nrows, group > 0 ? group : nrows, sticks);
