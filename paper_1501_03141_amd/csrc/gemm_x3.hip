@@ -452,31 +452,62 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
         __syncthreads();
     }
     if constexpr (FUSED) {
+        // The lane's rows are updated EB at a time, every load of a batch (r, p, x and the
+        // kinetic energies of its columns) issued before the first store: stores to x and
+        // p may alias the next entry's loads as far as the compiler knows, so an entry-by-
+        // entry loop waits for memory once per entry.  One row per batch measured best
+        // (more rows hold more registers and lower the occupancy).
+        constexpr int EB = 1;
+        float kk[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + 16 * t + lr;
+            kk[t] = du.kin[k < K ? k : K - 1];
+        }
 #pragma unroll
         for (int a = 0; a < AR; ++a)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i;
-                if (n >= N || !du.active[n]) continue;
-                const float bn = du.beta[n], an = du.xalpha[n];
-                const float sh = (float)du.shift[n];
-                const long xo = (long)(du.xrow ? du.xrow[n] : n) * ldy;
+            for (int i0 = 0; i0 < 4; i0 += EB) {
+                bool live[EB];
+                float bn[EB], an[EB], sh[EB];
+                long xo[EB];
+                float2 rv[EB][4], pv[EB][4], xv[EB][4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int k = k0 + 16 * t + lr;
-                    if (k < K) {
-                        const float d = du.kin[k] - sh;
-                        const float f = __builtin_amdgcn_rcpf(d > du.kfloor ? d : du.kfloor);
-                        const float2 rv = du.r[(long)n * du.ldr + k];
-                        float2* y = Y + (long)n * ldy + k;
-                        float2* xp = du.x + xo + k;
-                        const float2 pv = *y;
-                        float2 xv = *xp;
-                        xv.x += an * pv.x;
-                        xv.y += an * pv.y;
-                        *xp = xv;
-                        *y = make_float2(f * rv.x - acc[a][2 * t][i] + bn * pv.x,
-                                         f * rv.y - acc[a][2 * t + 1][i] + bn * pv.y);
+                for (int e = 0; e < EB; ++e) {
+                    const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i0 + e;
+                    live[e] = n < N && du.active[n];
+                    const int nn = live[e] ? n : 0;
+                    bn[e] = du.beta[nn];
+                    an[e] = du.xalpha[nn];
+                    sh[e] = (float)du.shift[nn];
+                    xo[e] = (long)(du.xrow ? du.xrow[nn] : nn) * ldy;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        int k = k0 + 16 * t + lr;
+                        k = k < K ? k : K - 1;
+                        rv[e][t] = du.r[(long)nn * du.ldr + k];
+                        pv[e][t] = Y[(long)nn * ldy + k];
+                        xv[e][t] = du.x[xo[e] + k];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    if (!live[e]) continue;
+                    const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i0 + e;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = k0 + 16 * t + lr;
+                        if (k < K) {
+                            const float d = kk[t] - sh[e];
+                            const float f = __builtin_amdgcn_rcpf(d > du.kfloor ? d : du.kfloor);
+                            float2 x = xv[e][t];
+                            x.x += an[e] * pv[e][t].x;
+                            x.y += an[e] * pv[e][t].y;
+                            du.x[xo[e] + k] = x;
+                            Y[(long)n * ldy + k] =
+                                make_float2(f * rv[e][t].x - acc[a][2 * t][i0 + e] + bn[e] * pv[e][t].x,
+                                            f * rv[e][t].y - acc[a][2 * t + 1][i0 + e] + bn[e] * pv[e][t].y);
+                        }
                     }
                 }
             }
