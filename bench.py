@@ -251,6 +251,71 @@ def serving_bench(n_jobs: int, max_running: int, log):
                       "BF16x3 mixed precision, Davidson to 1e-6 with 8 buffer vectors"}
 
 
+def chi0_requests_bench(w, V, phi_host, n_req: int, per_req: int, log):
+    """Batched chi0 requests on a resident system (the benchmark's own system, BF16x3):
+    n_req requests of per_req perturbations each (slices of the seeded block).  Capacity
+    with one request per batch (max_batch_pert = per_req) and with batches of up to the
+    whole block (N_pdep perturbations), each from all requests submitted at once; then a
+    Poisson stream at 0.8 x the batched capacity with latency percentiles and the mean
+    number of requests per batch."""
+    from paper_1501_03141_amd import pdep
+
+    rng = np.random.default_rng(2507)
+    blocks = [phi_host[(k * per_req) % w.n_pdep:][:per_req] for k in range(n_req)]
+    blocks = [b if b.shape[0] == per_req else phi_host[:per_req] for b in blocks]
+
+    def run(max_batch, arrivals):
+        with pdep.Server(max_running=1) as srv:
+            sid = srv.add_system(w.L, w.n, w.ecut, V, w.n_v, max_batch_pert=max_batch,
+                                 precision=pdep.PDEP_MIXED_BF16X3, cg_tol=w.cg_tol)
+            # warm-up batch (tunes the transform chain and GEMM shapes of the system)
+            t = srv.submit_chi0(sid, phi_host[: min(w.n_pdep, max(max_batch, per_req))])
+            srv.wait(t, -1)
+            t0 = time.perf_counter()
+            tickets = []
+            for b, ta in zip(blocks, arrivals):
+                dt = ta - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(srv.submit_chi0(sid, b))
+            lat, nb, ok = [], [], 0
+            for t in tickets:
+                srv.wait(t, -1)
+                state, res, _ = srv.poll_chi0(t)
+                if state == pdep.JOB_DONE:
+                    ok += 1
+                    lat.append(res["latency_ms"])
+                    nb.append(res["batch_requests"])
+                else:
+                    log(f"  chi0 request failed: {res.get('error')}")
+            wall = time.perf_counter() - t0
+            srv.remove_system(sid)
+        return wall, lat, nb, ok
+
+    wall1, _, _, ok1 = run(per_req, [0.0] * n_req)
+    cap1 = ok1 / wall1
+    log(f"chi0 requests, one per batch: {ok1}/{n_req} in {wall1:.2f} s -> {cap1:.1f} requests/s")
+    wallb, _, nbb, okb = run(w.n_pdep, [0.0] * n_req)
+    capb = okb / wallb
+    log(f"chi0 requests, batches of up to {w.n_pdep} perturbations: {okb}/{n_req} in {wallb:.2f} s "
+        f"-> {capb:.1f} requests/s (mean {np.mean(nbb):.1f} requests per batch)")
+    rate = 0.8 * capb
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    arrivals -= arrivals[0]
+    walls, lats, nbs, oks = run(w.n_pdep, list(arrivals))
+    log(f"chi0 request stream at {rate:.1f} requests/s: {oks}/{n_req} in {walls:.2f} s")
+    return {"requests": n_req, "perturbations_per_request": per_req,
+            "capacity_one_per_batch_req_per_s": round(cap1, 2), "capacity_batched_req_per_s": round(capb, 2),
+            "batching_speedup": round(capb / cap1, 2), "offered_rate_req_per_s": round(rate, 2),
+            "req_per_s": round(oks / walls, 2),
+            "p50_ms": round(float(np.percentile(lats, 50)), 1) if lats else None,
+            "p99_ms": round(float(np.percentile(lats, 99)), 1) if lats else None,
+            "mean_requests_per_batch": round(float(np.mean(nbs)), 2) if nbs else None,
+            "failed": n_req - oks,
+            "sample": f"{n_req} requests of {per_req} perturbations on the resident {w.name} system "
+                      f"(BF16x3, cg_tol {w.cg_tol:g}), Poisson arrivals"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +334,9 @@ def main():
     ap.add_argument("--no-gw", action="store_true", help="skip the G0W0 quasiparticle energy of the HOMO")
     ap.add_argument("--serving-jobs", type=int, default=48, help="0 disables the serving phase")
     ap.add_argument("--serving-max-running", type=int, default=4)
+    ap.add_argument("--chi0-requests", type=int, default=64,
+                    help="batched chi0 requests on the resident system (0 disables the phase)")
+    ap.add_argument("--chi0-request-pert", type=int, default=8, help="perturbations per chi0 request")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size 3 times (reference "
                          "kernel for scaling HBM byte counters)")
@@ -464,6 +532,11 @@ def main():
               "z": r["z"], "e_lin": r["e_lin"], "e_qp": r["e_qp"], "converged": bool(r["converged"])}
         log("gw", gw)
 
+    chi0_req = None
+    if args.chi0_requests > 0:
+        chi0_req = chi0_requests_bench(w, V, phi_host, args.chi0_requests, args.chi0_request_pert, log)
+        log("chi0 requests", chi0_req)
+
     serving = None
     if args.serving_jobs > 0:
         serving = serving_bench(args.serving_jobs, args.serving_max_running, log)
@@ -518,6 +591,7 @@ def main():
         "pdep_eigs": eigs,
         "serving": serving,
         "gw": gw,
+        "chi0_requests": chi0_req,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -411,7 +411,10 @@ typedef struct pdep_server pdep_server;
 
 #define PDEP_SERVER_FAKE 1u   /* test hook: no GPU work; each job sleeps for
                                  fake_ms_per_gb * (HBM estimate in GB) and returns
-                                 eps_i = 1 + (seed % 97 + 1) / (i + 1) */
+                                 eps_i = 1 + (seed % 97 + 1) / (i + 1); a resident
+                                 system is not set up, and a chi0 batch sleeps
+                                 fake_ms_per_gb ms plus 1 ms per perturbation and
+                                 returns out = -phi / 2 */
 
 typedef struct {
     int max_running;          /* jobs on the GPU at once (>= 1) */
@@ -462,8 +465,49 @@ int pdep_poll(pdep_server* s, uint64_t ticket, int* state, pdep_job_result* res,
 /* Block until the job is DONE or FAILED or timeout_ms passes (< 0: no limit). */
 int pdep_server_wait(pdep_server* s, uint64_t ticket, double timeout_ms, int* state);
 int pdep_server_stats_get(pdep_server* s, pdep_server_stats* st);
-/* Stop admitting, drop queued jobs, wait for running ones, free everything. */
+/* Stop admitting, drop queued jobs and chi0 requests, wait for running ones and
+ * running batches, remove every resident system, free everything. */
 int pdep_server_destroy(pdep_server* s);
+
+/* Resident systems and batched chi0 requests.
+ * A server can keep Kohn-Sham systems resident on the device (orbitals, grids and the
+ * chi0 work space of pdep_setup, set up once) and apply chi0bar to blocks of trial
+ * potentials on them as requests (Sec. 2.3, Eqs. stern, deltani, chiisamatrixinpdep:
+ * the operation of chi0_apply).  Every system has one batcher thread with its own HIP
+ * stream: it takes the requests queued on the system in submission order, up to
+ * max_batch_pert perturbations (at least one whole request), concatenates their
+ * perturbations and runs them as ONE chi0_apply, so the Sternheimer systems of all
+ * requests of the batch go through one batched CG; the result rows go back to their
+ * requests.  Requests that arrive while a batch runs join the next one (continuous
+ * batching); batches of different systems run concurrently.  Each row of chi0bar phi
+ * depends only on its own perturbation, so a result is the same alone and in a batch
+ * up to the rounding of the transforms that pair rows (within cg_tol of the system).
+ * The system's HBM estimate (job_hbm_estimate of its cell, options and
+ * max_batch_pert) is committed against the server budget while it is resident. */
+int pdep_server_add_system(pdep_server* s, const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
+                           int max_batch_pert, uint64_t* system_id);
+/* Fail the system's queued requests (PDEP_EINVAL), wait for its running batch, free it.
+ * PDEP_ENOTFOUND for an unknown id. */
+int pdep_server_remove_system(pdep_server* s, uint64_t system_id);
+/* Queue chi0bar applied to phi (n_pert x N_pw' complex on S', host, copied here) on a
+ * resident system; the ticket is also accepted by pdep_server_wait. */
+int pdep_submit_chi0(pdep_server* s, uint64_t system_id, int n_pert, const double* phi, uint64_t* ticket);
+
+typedef struct {
+    int status;               /* pdep_status of the batch (PDEP_OK when DONE) */
+    int n_pert;
+    int batch_requests;       /* requests in the batch this request ran in */
+    int batch_pert;           /* perturbations of that batch */
+    double queue_ms;          /* submit -> batch start */
+    double run_ms;            /* batch start -> finish */
+    double latency_ms;        /* submit -> finish */
+    pdep_apply_stats stats;   /* statistics of the whole batch */
+} pdep_chi0_result;
+
+/* Non-blocking.  When DONE and out_cap_pert >= n_pert, out (n_pert x N_pw' complex)
+ * receives the result; res may be NULL.  PDEP_ENOTFOUND for an unknown ticket. */
+int pdep_poll_chi0(pdep_server* s, uint64_t ticket, int* state, pdep_chi0_result* res, double* out,
+                   int out_cap_pert);
 
 /* Kernel timing (instrumentation, process-wide).  While enabled, every kernel launch
  * of the library is bracketed by two HIP events recorded on its launch stream.

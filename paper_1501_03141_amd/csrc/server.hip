@@ -3,6 +3,11 @@
 // stream (non-blocking, default priority) and a rocBLAS handle; a job's device memory
 // comes from stream-ordered allocations on that stream, so admitting a job never
 // synchronises the device and the kernels of concurrently running jobs overlap.
+//
+// Resident systems: a context set up once and kept, with one batcher thread and its
+// own stream, serving chi0 requests.  The batcher takes the requests queued on its
+// system in order (up to max_batch_pert perturbations), runs them as one chi0_apply on
+// their concatenated perturbations and hands each request its rows of the result.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -10,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -45,6 +51,32 @@ struct JobRec {
 
 }  // namespace
 
+struct Chi0Req {
+    uint64_t ticket = 0, sys = 0;
+    int n_pert = 0;
+    std::vector<double> phi, out;   // n_pert rows of N_pw - 1 complex (interleaved)
+    int state = PDEP_JOB_QUEUED;
+    int status = PDEP_OK;
+    std::string msg;
+    int batch_requests = 0, batch_pert = 0;
+    pdep_apply_stats st{};
+    Clock::time_point t_submit, t_start, t_end;
+};
+
+struct SysRec {
+    uint64_t id = 0;
+    pdep_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    rocblas_handle blas = nullptr;
+    int max_batch = 0;        // perturbations per batch (0: no limit)
+    int npw = 0;              // N_pw of the system (rows of N_pw - 1 complex on S')
+    size_t est = 0;           // committed against the server budget while resident
+    bool stop = false;
+    std::deque<Chi0Req*> queue;
+    std::condition_variable cv;   // waits on the server mutex
+    std::thread batcher;
+};
+
 struct pdep_server {
     pdep_server_opts opts{};
     int device = 0;
@@ -59,6 +91,9 @@ struct pdep_server {
     int running = 0, peak_running = 0, n_done = 0, n_failed = 0;
     size_t committed = 0, peak_committed = 0;
     std::vector<std::thread> workers;
+    std::map<uint64_t, std::unique_ptr<SysRec>> systems;
+    std::map<uint64_t, std::unique_ptr<Chi0Req>> reqs;
+    uint64_t next_system = 1;
 };
 
 namespace {
@@ -166,6 +201,98 @@ void worker_main(pdep_server* S) {
     }
     if (blas) rocblas_destroy_handle(blas);
     if (stream) (void)hipStreamDestroy(stream);
+}
+
+// One batch at a time for system y: the queued requests in order, up to y->max_batch
+// perturbations (at least one request), as one chi0_apply.
+void batcher_main(pdep_server* S, SysRec* y) {
+    const bool fake = (S->opts.flags & PDEP_SERVER_FAKE) != 0;
+    if (!fake) (void)hipSetDevice(S->device);
+    const size_t row = 2 * (size_t)(y->npw - 1);   // doubles per perturbation
+    std::vector<double> phi, out;
+    for (;;) {
+        std::vector<Chi0Req*> batch;
+        int np = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            y->cv.wait(lk, [&] { return y->stop || !y->queue.empty(); });
+            if (y->stop) break;
+            while (!y->queue.empty()) {
+                Chi0Req* r = y->queue.front();
+                if (!batch.empty() && y->max_batch > 0 && np + r->n_pert > y->max_batch) break;
+                y->queue.pop_front();
+                batch.push_back(r);
+                np += r->n_pert;
+            }
+            const auto now = Clock::now();
+            for (Chi0Req* r : batch) {
+                r->state = PDEP_JOB_RUNNING;
+                r->t_start = now;
+                r->batch_requests = (int)batch.size();
+                r->batch_pert = np;
+            }
+        }
+        phi.resize((size_t)np * row);
+        out.assign((size_t)np * row, 0.0);
+        size_t off = 0;
+        for (Chi0Req* r : batch) {
+            std::copy(r->phi.begin(), r->phi.end(), phi.begin() + off);
+            off += r->phi.size();
+        }
+        int rc = PDEP_OK;
+        std::string msg;
+        pdep_apply_stats st{};
+        if (fake) {
+            const double ms = S->opts.fake_ms_per_gb + np;
+            std::this_thread::sleep_for(std::chrono::microseconds((long long)(ms * 1000.0)));
+            for (size_t i = 0; i < phi.size(); ++i) out[i] = -0.5 * phi[i];
+        } else {
+            rc = chi0_apply(y->ctx, np, phi.data(), out.data(), &st);
+            if (rc != PDEP_OK) msg = pdep_last_error();
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            const auto now = Clock::now();
+            off = 0;
+            for (Chi0Req* r : batch) {
+                r->t_end = now;
+                r->status = rc;
+                r->st = st;
+                r->state = rc == PDEP_OK ? PDEP_JOB_DONE : PDEP_JOB_FAILED;
+                if (rc == PDEP_OK)
+                    r->out.assign(out.begin() + off, out.begin() + off + (size_t)r->n_pert * row);
+                else
+                    r->msg = msg;
+                off += (size_t)r->n_pert * row;
+                std::vector<double>().swap(r->phi);
+            }
+        }
+        S->done_cv.notify_all();
+    }
+}
+
+// Stop a system's batcher (its queued requests fail) and free it; y is out of the map.
+void close_system(pdep_server* S, std::unique_ptr<SysRec> y) {
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        y->stop = true;
+        for (Chi0Req* r : y->queue) {
+            r->state = PDEP_JOB_FAILED;
+            r->status = PDEP_EINVAL;
+            r->msg = "system removed before the request ran";
+            r->t_end = Clock::now();
+        }
+        y->queue.clear();
+    }
+    y->cv.notify_all();
+    S->done_cv.notify_all();
+    if (y->batcher.joinable()) y->batcher.join();
+    if (y->ctx) pdep_destroy(y->ctx);
+    if (y->stream) (void)hipStreamSynchronize(y->stream);
+    if (y->blas) rocblas_destroy_handle(y->blas);
+    if (y->stream) (void)hipStreamDestroy(y->stream);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->committed -= y->est;
 }
 
 int fail(int code, const std::string& m) {
@@ -302,15 +429,16 @@ int pdep_poll(pdep_server* S, uint64_t ticket, int* state, pdep_job_result* res,
 int pdep_server_wait(pdep_server* S, uint64_t ticket, double timeout_ms, int* state) {
     if (!S || !state) return fail(PDEP_EINVAL, "null argument");
     std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->jobs.find(ticket);
-    if (it == S->jobs.end()) return fail(PDEP_ENOTFOUND, "unknown ticket");
-    JobRec* j = it->second.get();
-    auto finished = [&] { return j->state == PDEP_JOB_DONE || j->state == PDEP_JOB_FAILED; };
+    int* st = nullptr;   // state of the job or chi0 request (records are never erased)
+    if (auto it = S->jobs.find(ticket); it != S->jobs.end()) st = &it->second->state;
+    else if (auto ir = S->reqs.find(ticket); ir != S->reqs.end()) st = &ir->second->state;
+    if (!st) return fail(PDEP_ENOTFOUND, "unknown ticket");
+    auto finished = [&] { return *st == PDEP_JOB_DONE || *st == PDEP_JOB_FAILED; };
     if (timeout_ms < 0)
         S->done_cv.wait(lk, finished);
     else
         S->done_cv.wait_for(lk, std::chrono::microseconds((long long)(timeout_ms * 1000.0)), finished);
-    *state = j->state;
+    *state = *st;
     return PDEP_OK;
 }
 
@@ -324,6 +452,155 @@ int pdep_server_stats_get(pdep_server* S, pdep_server_stats* st) {
     st->committed_bytes = S->committed;
     st->peak_committed_bytes = S->peak_committed;
     st->peak_running = S->peak_running;
+    return PDEP_OK;
+}
+
+int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
+                           int max_batch_pert, uint64_t* system_id) {
+    if (!S || !cell || !vloc || !opts || !system_id) return fail(PDEP_EINVAL, "null argument");
+    if (max_batch_pert < 0) return fail(PDEP_EINVAL, "max_batch_pert must be >= 0");
+    const bool fake = (S->opts.flags & PDEP_SERVER_FAKE) != 0;
+    auto y = std::make_unique<SysRec>();
+    y->max_batch = max_batch_pert;
+    try {
+        PDEP_REQUIRE(opts->n_v >= 1, PDEP_EINVAL, "n_v must be >= 1");
+        pdep_eig_opts eo{};
+        eo.tol = 1e-6;
+        eo.maxit = 1;
+        y->est = pdep::job_hbm_estimate(*cell, *opts, max_batch_pert > 0 ? max_batch_pert : 16, eo, nullptr);
+        pdep::Basis b;
+        pdep::build_basis(*cell, b);
+        y->npw = b.npw;
+        const size_t ng = (size_t)cell->n[0] * cell->n[1] * cell->n[2];
+        for (size_t i = 0; i < ng; ++i) PDEP_REQUIRE(std::isfinite(vloc[i]), PDEP_EINVAL, "V_loc contains NaN or Inf");
+    } catch (const pdep::Error& e) {
+        return fail(e.code, e.what());
+    } catch (const std::exception& e) {
+        return fail(PDEP_EINVAL, e.what());
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return fail(PDEP_EINVAL, "server is shutting down");
+        if (S->committed + y->est > S->budget)
+            return fail(PDEP_ENOMEM, "system needs " + std::to_string(y->est >> 20) + " MiB, " +
+                                         std::to_string((S->budget - std::min(S->budget, S->committed)) >> 20) +
+                                         " MiB of the budget are free");
+        S->committed += y->est;   // reserved while the system is set up and resident
+        S->peak_committed = std::max(S->peak_committed, S->committed);
+    }
+    auto release = [&](int code, const std::string& m) {
+        if (y->blas) rocblas_destroy_handle(y->blas);
+        if (y->stream) (void)hipStreamDestroy(y->stream);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->committed -= y->est;
+        return fail(code, m);
+    };
+    if (!fake) {
+        if (hipStreamCreateWithFlags(&y->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            y->stream = nullptr;
+            return release(PDEP_EDEVICE, "could not create the system's stream");
+        }
+        if (rocblas_create_handle(&y->blas) != rocblas_status_success) {
+            y->blas = nullptr;
+            return release(PDEP_EDEVICE, "could not create the system's rocBLAS handle");
+        }
+        rocblas_set_stream(y->blas, y->stream);
+        pdep_opts o = *opts;
+        o.stream = y->stream;
+        o.alloc.alloc = stream_alloc;
+        o.alloc.free = stream_free;
+        o.alloc.ctx = y->stream;
+        o.flags = 0;   // host arrays: requests hold host copies
+        const int rc = pdep::setup_context(cell, vloc, &o, nullptr, nullptr, y->blas, &y->ctx);
+        if (rc != PDEP_OK) return release(rc, pdep_last_error());
+        pdep_info info{};
+        pdep_get_info(y->ctx, &info);
+        y->npw = info.n_pw;
+    }
+    SysRec* yp = y.get();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        y->id = S->next_system++;
+        *system_id = y->id;
+        S->systems[y->id] = std::move(y);
+        yp->batcher = std::thread(batcher_main, S, yp);
+    }
+    return PDEP_OK;
+}
+
+int pdep_server_remove_system(pdep_server* S, uint64_t system_id) {
+    if (!S) return fail(PDEP_EINVAL, "null argument");
+    std::unique_ptr<SysRec> y;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->systems.find(system_id);
+        if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "unknown system");
+        y = std::move(it->second);
+        S->systems.erase(it);
+    }
+    close_system(S, std::move(y));
+    return PDEP_OK;
+}
+
+int pdep_submit_chi0(pdep_server* S, uint64_t system_id, int n_pert, const double* phi, uint64_t* ticket) {
+    if (!S || !phi || !ticket) return fail(PDEP_EINVAL, "null argument");
+    if (n_pert < 1) return fail(PDEP_EINVAL, "n_pert must be >= 1");
+    int npw = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->systems.find(system_id);
+        if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "unknown system");
+        npw = it->second->npw;
+    }
+    auto r = std::make_unique<Chi0Req>();
+    r->sys = system_id;
+    r->n_pert = n_pert;
+    const size_t n = (size_t)n_pert * 2 * (size_t)(npw - 1);
+    r->phi.assign(phi, phi + n);
+    for (double v : r->phi)
+        if (!std::isfinite(v)) return fail(PDEP_EINVAL, "phi contains NaN or Inf");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(PDEP_EINVAL, "server is shutting down");
+    auto it = S->systems.find(system_id);
+    if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "system removed");
+    SysRec* y = it->second.get();
+    if ((int)y->queue.size() >= S->opts.queue_capacity) return fail(PDEP_EBUSY, "queue full");
+    r->ticket = S->next_ticket++;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    y->queue.push_back(r.get());
+    S->reqs[r->ticket] = std::move(r);
+    y->cv.notify_all();
+    return PDEP_OK;
+}
+
+int pdep_poll_chi0(pdep_server* S, uint64_t ticket, int* state, pdep_chi0_result* res, double* out,
+                   int out_cap_pert) {
+    if (!S || !state) return fail(PDEP_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(PDEP_ENOTFOUND, "unknown ticket");
+    const Chi0Req* r = it->second.get();
+    *state = r->state;
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        res->n_pert = r->n_pert;
+        if (r->state != PDEP_JOB_QUEUED) {
+            res->batch_requests = r->batch_requests;
+            res->batch_pert = r->batch_pert;
+        }
+        if (r->state == PDEP_JOB_DONE || r->state == PDEP_JOB_FAILED) {
+            res->status = r->status;
+            res->queue_ms = ms_between(r->t_submit, r->t_start);
+            res->run_ms = ms_between(r->t_start, r->t_end);
+            res->latency_ms = ms_between(r->t_submit, r->t_end);
+            res->stats = r->st;
+        }
+    }
+    if (r->state == PDEP_JOB_DONE && out && out_cap_pert >= r->n_pert)
+        std::copy(r->out.begin(), r->out.end(), out);
+    if (r->state == PDEP_JOB_FAILED) pdep_set_error_message(r->msg.c_str());
     return PDEP_OK;
 }
 
@@ -342,6 +619,13 @@ int pdep_server_destroy(pdep_server* S) {
     S->cv.notify_all();
     S->done_cv.notify_all();
     for (auto& t : S->workers) t.join();
+    std::vector<std::unique_ptr<SysRec>> sys;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto& kv : S->systems) sys.push_back(std::move(kv.second));
+        S->systems.clear();
+    }
+    for (auto& y : sys) close_system(S, std::move(y));
     delete S;
     return PDEP_OK;
 }

@@ -155,6 +155,17 @@ class JobResult(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Chi0Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_pert", C.c_int), ("batch_requests", C.c_int), ("batch_pert", C.c_int),
+                ("queue_ms", C.c_double), ("run_ms", C.c_double), ("latency_ms", C.c_double),
+                ("stats", ApplyStats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        return d
+
+
 class ServerStats(C.Structure):
     _fields_ = [("queued", C.c_int), ("running", C.c_int), ("done", C.c_int), ("failed", C.c_int),
                 ("committed_bytes", C.c_size_t), ("peak_committed_bytes", C.c_size_t), ("peak_running", C.c_int)]
@@ -218,8 +229,14 @@ def load(path: str = LIB_PATH):
     lib.pdep_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_int)]
     lib.pdep_server_stats_get.argtypes = [P, C.POINTER(ServerStats)]
     lib.pdep_server_destroy.argtypes = [P]
+    lib.pdep_server_add_system.argtypes = [P, C.POINTER(Cell), C.c_void_p, C.POINTER(Opts), C.c_int,
+                                           C.POINTER(C.c_uint64)]
+    lib.pdep_server_remove_system.argtypes = [P, C.c_uint64]
+    lib.pdep_submit_chi0.argtypes = [P, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_uint64)]
+    lib.pdep_poll_chi0.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(Chi0Result), C.c_void_p, C.c_int]
     for name in ("pdep_server_create", "pdep_submit", "pdep_poll", "pdep_server_wait", "pdep_server_stats_get",
-                 "pdep_server_destroy"):
+                 "pdep_server_destroy", "pdep_server_add_system", "pdep_server_remove_system", "pdep_submit_chi0",
+                 "pdep_poll_chi0"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
                  "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_body_lanczos", "pdep_head_wings",
@@ -546,7 +563,8 @@ class Context:
 
 class Server:
     """Serving loop (pdep_server_*): jobs of (cell, V_loc, N_v, N_pdep, seed, options)
-    admitted under an HBM budget and run concurrently on their own streams."""
+    admitted under an HBM budget and run concurrently on their own streams; resident
+    systems serving chi0 requests in batches (pdep_server_add_system, pdep_submit_chi0)."""
 
     def __init__(self, max_running=4, hbm_budget=0, queue_capacity=0, fake=False, fake_ms_per_gb=100.0):
         self._lib = load()
@@ -594,6 +612,49 @@ class Server:
         st = C.c_int()
         _check(self._lib.pdep_server_wait(self._h, C.c_uint64(ticket), float(timeout_ms), C.byref(st)))
         return st.value
+
+    def add_system(self, L, n, ecut, vloc, n_v, max_batch_pert=0, precision=PDEP_MIXED_FP32, cg_tol=1e-8, **opt):
+        """Set up a resident system (pdep_server_add_system); returns its id."""
+        o = Opts()
+        self._lib.pdep_default_opts(C.byref(o))
+        o.n_v = int(n_v)
+        o.precision = int(precision)
+        o.cg_tol = float(cg_tol)
+        for k, v in opt.items():
+            setattr(o, k, v)
+        v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
+        cell = Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut))
+        sid = C.c_uint64()
+        _check(self._lib.pdep_server_add_system(self._h, C.byref(cell), v.ctypes.data, C.byref(o),
+                                                int(max_batch_pert), C.byref(sid)))
+        return sid.value
+
+    def remove_system(self, system_id):
+        _check(self._lib.pdep_server_remove_system(self._h, C.c_uint64(system_id)))
+
+    def submit_chi0(self, system_id, phi):
+        """Queue chi0bar applied to phi [n_pert, N_pw - 1] (complex) on a resident system."""
+        a = np.ascontiguousarray(np.asarray(phi, dtype=np.complex128))
+        assert a.ndim == 2
+        t = C.c_uint64()
+        _check(self._lib.pdep_submit_chi0(self._h, C.c_uint64(system_id), int(a.shape[0]), a.ctypes.data, C.byref(t)))
+        self._keep[t.value] = (int(a.shape[0]), int(a.shape[1]))
+        return t.value
+
+    def poll_chi0(self, ticket):
+        """(state, result dict or None, out [n_pert, N_pw - 1] or None); never blocks."""
+        st = C.c_int()
+        res = Chi0Result()
+        n, w = self._keep[ticket]
+        out = np.empty((n, w), dtype=np.complex128)
+        _check(self._lib.pdep_poll_chi0(self._h, C.c_uint64(ticket), C.byref(st), C.byref(res), out.ctypes.data, n))
+        if st.value == JOB_DONE:
+            return st.value, res.as_dict(), out
+        if st.value == JOB_FAILED:
+            d = res.as_dict()
+            d["error"] = self._lib.pdep_last_error().decode()
+            return st.value, d, None
+        return st.value, None, None
 
     def stats(self):
         s = ServerStats()
