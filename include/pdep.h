@@ -505,7 +505,9 @@ typedef struct {
 } pdep_chi0_result;
 
 /* Non-blocking.  When DONE and out_cap_pert >= n_pert, out (n_pert x N_pw' complex)
- * receives the result; res may be NULL.  PDEP_ENOTFOUND for an unknown ticket. */
+ * receives the result, which the server then releases: a later poll with out set fails
+ * with PDEP_EINVAL (state and res stay available).  res may be NULL.  PDEP_ENOTFOUND
+ * for an unknown ticket. */
 int pdep_poll_chi0(pdep_server* s, uint64_t ticket, int* state, pdep_chi0_result* res, double* out,
                    int out_cap_pert);
 

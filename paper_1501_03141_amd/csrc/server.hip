@@ -59,6 +59,7 @@ struct Chi0Req {
     int status = PDEP_OK;
     std::string msg;
     int batch_requests = 0, batch_pert = 0;
+    bool delivered = false;         // out was copied to the caller and released
     pdep_apply_stats st{};
     Clock::time_point t_submit, t_start, t_end;
 };
@@ -287,6 +288,7 @@ void close_system(pdep_server* S, std::unique_ptr<SysRec> y) {
     y->cv.notify_all();
     S->done_cv.notify_all();
     if (y->batcher.joinable()) y->batcher.join();
+    if (y->stream) (void)hipSetDevice(S->device);
     if (y->ctx) pdep_destroy(y->ctx);
     if (y->stream) (void)hipStreamSynchronize(y->stream);
     if (y->blas) rocblas_destroy_handle(y->blas);
@@ -581,7 +583,7 @@ int pdep_poll_chi0(pdep_server* S, uint64_t ticket, int* state, pdep_chi0_result
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(ticket);
     if (it == S->reqs.end()) return fail(PDEP_ENOTFOUND, "unknown ticket");
-    const Chi0Req* r = it->second.get();
+    Chi0Req* r = it->second.get();
     *state = r->state;
     if (res) {
         std::memset(res, 0, sizeof(*res));
@@ -598,8 +600,12 @@ int pdep_poll_chi0(pdep_server* S, uint64_t ticket, int* state, pdep_chi0_result
             res->stats = r->st;
         }
     }
-    if (r->state == PDEP_JOB_DONE && out && out_cap_pert >= r->n_pert)
+    if (r->state == PDEP_JOB_DONE && out && out_cap_pert >= r->n_pert) {
+        if (r->delivered) return fail(PDEP_EINVAL, "the request's result was already delivered");
         std::copy(r->out.begin(), r->out.end(), out);
+        std::vector<double>().swap(r->out);
+        r->delivered = true;
+    }
     if (r->state == PDEP_JOB_FAILED) pdep_set_error_message(r->msg.c_str());
     return PDEP_OK;
 }

@@ -125,3 +125,16 @@ def test_concurrent_submitters_get_their_own_rows():
         assert len(out) == 20
         for p, o in out.values():
             np.testing.assert_array_equal(o, -0.5 * p)
+
+
+def test_result_is_delivered_once():
+    with pdep.Server(max_running=1, fake=True, fake_ms_per_gb=0.0) as s:
+        sid = _system(s)
+        p = _phi(2, 3)
+        t = s.submit_chi0(sid, p)
+        assert s.wait(t, 10000) == pdep.JOB_DONE
+        state, res, out = s.poll_chi0(t)
+        np.testing.assert_array_equal(out, -0.5 * p)
+        with pytest.raises(pdep.PdepError) as e:
+            s.poll_chi0(t)
+        assert e.value.code == pdep.PDEP_EINVAL
