@@ -1014,8 +1014,7 @@ __global__ __launch_bounds__(kThreads) void k_slab(FftDims d, BasisTables t, cpl
 // buffer) to LDS and back, in 16-byte pieces with up to K loads in flight per thread
 // before the first LDS write: a loop that waited for each load before its LDS write
 // would pay the memory latency once per piece.  The copy back writes only the sphere's
-// sticks (index < ns within each slab row), so the padding of the rows is left as it is
-// (ns > 0; a row of an odd number of FP32 sticks ends with one 8-byte write).
+// sticks (index < ns within each slab row), so the padding of the rows is left as it is.
 template <typename E, int NT, int K = 8>
 __device__ __forceinline__ void stage_rows_in(E* lds, const E* g, int nzh, int sld) {
     static_assert(sizeof(E) == 8 || sizeof(E) == 16, "8- or 16-byte elements");
@@ -1036,22 +1035,31 @@ __device__ __forceinline__ void stage_rows_in(E* lds, const E* g, int nzh, int s
         });
     }
 }
-template <typename E, int NT>
+template <typename E, int NT, int K = 8>
 __device__ __forceinline__ void stage_rows_out(E* g, const E* lds, int nzh, int sld, int ns) {
-    // row by row (no division by the row stride per piece), two pieces per thread at a time
     constexpr int PER = 16 / sizeof(E);
-    const int full = ns / PER, tail = ns - full * PER;   // whole pieces of sphere sticks, rest
-    for (int zz = 0; zz < nzh; ++zz) {
-        const float4* src = reinterpret_cast<const float4*>(lds + (long)zz * sld);
-        float4* dst = reinterpret_cast<float4*>(g + (long)zz * sld);
-        for (int j0 = 0; j0 < full; j0 += 2 * NT) {
-            const int ja = j0 + (int)threadIdx.x, jb = ja + NT;
-            const float4 a = src[min(ja, full - 1)], b = src[min(jb, full - 1)];
-            if (ja < full) dst[ja] = a;
-            if (jb < full) dst[jb] = b;
-        }
-        if (PER == 2 && tail && threadIdx.x == 0)
-            reinterpret_cast<float2*>(dst + full)[0] = reinterpret_cast<const float2*>(src + full)[0];
+    const int n = nzh * sld / PER;
+    const float4* src = reinterpret_cast<const float4*>(lds);
+    float4* dst = reinterpret_cast<float4*>(g);
+    for (int b = 0; b < n; b += K * NT) {
+        float4 r[K];
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            r[k] = src[min(b + (int)threadIdx.x + k * NT, n - 1)];
+        });
+        sfor<0, K>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int i = b + (int)threadIdx.x + k * NT;
+            if (i < n) {
+                const int e = i * PER;
+                const int ein = e - (e / sld) * sld;   // index within the slab row
+                if (ein + PER <= ns) {
+                    dst[i] = r[k];
+                } else if (PER == 2 && ein < ns) {
+                    reinterpret_cast<float2*>(dst + i)[0] = make_float2(r[k].x, r[k].y);
+                }
+            }
+        });
     }
 }
 
@@ -1571,7 +1579,7 @@ __global__ __launch_bounds__(256) void k_slab_fwd_quad64(FftDims d, BasisTables 
     __syncthreads();
     double2* g = sticks + ((long)row * nz + z0) * sld;
     const int ns = d.ns;
-    stage_rows_out<double2, 256>(g, lds, nzh, sld, ns);
+    stage_rows_out<double2, 256, 4>(g, lds, nzh, sld, ns);
 }
 
 constexpr int kMaxAcc = 24;
