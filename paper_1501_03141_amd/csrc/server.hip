@@ -277,11 +277,12 @@ void close_system(pdep_server* S, std::unique_ptr<SysRec> y) {
     {
         std::lock_guard<std::mutex> lk(S->mu);
         y->stop = true;
+        const auto now = Clock::now();
         for (Chi0Req* r : y->queue) {
             r->state = PDEP_JOB_FAILED;
             r->status = PDEP_EINVAL;
             r->msg = "system removed before the request ran";
-            r->t_end = Clock::now();
+            r->t_start = r->t_end = now;
         }
         y->queue.clear();
     }

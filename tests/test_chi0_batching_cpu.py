@@ -77,6 +77,7 @@ def test_remove_system_fails_queued_requests_only():
         assert all(st == pdep.JOB_FAILED for st in states[1:])
         _, res, _ = s.poll_chi0(tickets[1])
         assert res["status"] == pdep.PDEP_EINVAL and "removed" in res["error"]
+        assert 0 <= res["queue_ms"] <= res["latency_ms"] < 60000 and res["run_ms"] == 0
         with pytest.raises(pdep.PdepError) as e:
             s.submit_chi0(sid, _phi(1, 9))
         assert e.value.code == pdep.PDEP_ENOTFOUND
