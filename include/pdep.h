@@ -493,6 +493,19 @@ int pdep_server_remove_system(pdep_server* s, uint64_t system_id);
  * resident system; the ticket is also accepted by pdep_server_wait. */
 int pdep_submit_chi0(pdep_server* s, uint64_t system_id, int n_pert, const double* phi, uint64_t* ticket);
 
+/* Queue a PDEP Davidson on a resident system (pdep_eigs of n_pdep eigenvalues with the
+ * library's seeded start and options eo, Sec. 2.3): it reuses the system's orbitals
+ * instead of a new ground state, runs on the system's batcher in submission order with
+ * its chi0 batches (never merged into one), and is polled with pdep_poll_eigs; the
+ * ticket is also accepted by pdep_server_wait.  PDEP_EINVAL for bad options,
+ * PDEP_ENOTFOUND for an unknown system. */
+int pdep_submit_eigs(pdep_server* s, uint64_t system_id, int n_pdep, uint64_t seed, const pdep_eig_opts* eo,
+                     uint64_t* ticket);
+/* As pdep_poll for a job: res->gap is the system's, res->hbm_estimate the system's
+ * estimate; up to eps_cap eigenvalues (descending) when DONE.  PDEP_ENOTFOUND for a
+ * ticket that is not such a request. */
+int pdep_poll_eigs(pdep_server* s, uint64_t ticket, int* state, pdep_job_result* res, double* eps_out, int eps_cap);
+
 typedef struct {
     int status;               /* pdep_status of the batch (PDEP_OK when DONE) */
     int n_pert;
@@ -507,7 +520,7 @@ typedef struct {
 /* Non-blocking.  When DONE and out_cap_pert >= n_pert, out (n_pert x N_pw' complex)
  * receives the result, which the server then releases: a later poll with out set fails
  * with PDEP_EINVAL (state and res stay available).  res may be NULL.  PDEP_ENOTFOUND
- * for an unknown ticket. */
+ * for a ticket that is not a chi0 request. */
 int pdep_poll_chi0(pdep_server* s, uint64_t ticket, int* state, pdep_chi0_result* res, double* out,
                    int out_cap_pert);
 

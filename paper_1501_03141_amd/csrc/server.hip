@@ -53,6 +53,12 @@ struct JobRec {
 
 struct Chi0Req {
     uint64_t ticket = 0, sys = 0;
+    bool eigs = false;              // a PDEP Davidson (pdep_submit_eigs) instead of a chi0 block
+    int n_pdep = 0;                 // eigs: dielectric eigenvalues wanted
+    uint64_t seed = 0;              // eigs: start block of the library generator
+    pdep_eig_opts eo{};             // eigs: options
+    std::vector<double> eps;        // eigs: result (descending)
+    int eig_iterations = 0;
     int n_pert = 0;
     std::vector<double> phi, out;   // n_pert rows of N_pw - 1 complex (interleaved)
     int state = PDEP_JOB_QUEUED;
@@ -72,6 +78,7 @@ struct SysRec {
     int max_batch = 0;        // perturbations per batch (0: no limit)
     int npw = 0;              // N_pw of the system (rows of N_pw - 1 complex on S')
     size_t est = 0;           // committed against the server budget while resident
+    double gap = 0.0;         // HOMO-LUMO gap of its ground state
     bool stop = false;
     std::deque<Chi0Req*> queue;
     std::condition_variable cv;   // waits on the server mutex
@@ -220,6 +227,8 @@ void batcher_main(pdep_server* S, SysRec* y) {
             if (y->stop) break;
             while (!y->queue.empty()) {
                 Chi0Req* r = y->queue.front();
+                // a PDEP Davidson runs alone; chi0 blocks batch up to max_batch perturbations
+                if (!batch.empty() && (r->eigs || batch[0]->eigs)) break;
                 if (!batch.empty() && y->max_batch > 0 && np + r->n_pert > y->max_batch) break;
                 y->queue.pop_front();
                 batch.push_back(r);
@@ -232,6 +241,32 @@ void batcher_main(pdep_server* S, SysRec* y) {
                 r->batch_requests = (int)batch.size();
                 r->batch_pert = np;
             }
+        }
+        if (batch[0]->eigs) {
+            Chi0Req* r = batch[0];
+            std::vector<double> eps(r->n_pdep, 0.0);
+            int rc = PDEP_OK, iters = 0;
+            std::string msg;
+            if (fake) {
+                std::this_thread::sleep_for(std::chrono::microseconds((long long)(S->opts.fake_ms_per_gb * 1000.0)));
+                for (int i = 0; i < r->n_pdep; ++i) eps[i] = 1.0 + (double)(r->seed % 97 + 1) / (i + 1);
+            } else {
+                pdep_eig_stats est{};
+                rc = pdep_eigs(y->ctx, r->n_pdep, r->seed, nullptr, &r->eo, eps.data(), nullptr, &est);
+                if (rc != PDEP_OK) msg = pdep_last_error();
+                iters = est.iterations;
+            }
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                r->t_end = Clock::now();
+                r->status = rc;
+                r->eig_iterations = iters;
+                r->state = rc == PDEP_OK ? PDEP_JOB_DONE : PDEP_JOB_FAILED;
+                if (rc == PDEP_OK) r->eps.swap(eps);
+                else r->msg = msg;
+            }
+            S->done_cv.notify_all();
+            continue;
         }
         phi.resize((size_t)np * row);
         out.assign((size_t)np * row, 0.0);
@@ -520,6 +555,7 @@ int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* 
         pdep_info info{};
         pdep_get_info(y->ctx, &info);
         y->npw = info.n_pw;
+        y->gap = info.gap;
     }
     SysRec* yp = y.get();
     {
@@ -578,12 +614,71 @@ int pdep_submit_chi0(pdep_server* S, uint64_t system_id, int n_pert, const doubl
     return PDEP_OK;
 }
 
+int pdep_submit_eigs(pdep_server* S, uint64_t system_id, int n_pdep, uint64_t seed, const pdep_eig_opts* eo,
+                     uint64_t* ticket) {
+    if (!S || !eo || !ticket) return fail(PDEP_EINVAL, "null argument");
+    if (n_pdep < 1) return fail(PDEP_EINVAL, "n_pdep must be >= 1");
+    if (!(eo->tol > 0 && eo->maxit >= 1 && eo->n_buffer >= 0 && eo->scr_tol >= 0 && eo->scr_maxit >= 0 &&
+          (eo->reducible == 0 || eo->reducible == 1)))
+        return fail(PDEP_EINVAL, "bad eig options");
+    if (eo->max_subspace > 0 && eo->max_subspace < 2 * (n_pdep + eo->n_buffer))
+        return fail(PDEP_EINVAL, "max_subspace must be 0 or at least 2 (n_pdep + n_buffer)");
+    auto r = std::make_unique<Chi0Req>();
+    r->sys = system_id;
+    r->eigs = true;
+    r->n_pdep = n_pdep;
+    r->seed = seed;
+    r->eo = *eo;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(PDEP_EINVAL, "server is shutting down");
+    auto it = S->systems.find(system_id);
+    if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "unknown system");
+    SysRec* y = it->second.get();
+    if (n_pdep >= y->npw - 1) return fail(PDEP_EINVAL, "n_pdep must be below the number of plane waves");
+    if ((int)y->queue.size() >= S->opts.queue_capacity) return fail(PDEP_EBUSY, "queue full");
+    r->ticket = S->next_ticket++;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    y->queue.push_back(r.get());
+    S->reqs[r->ticket] = std::move(r);
+    y->cv.notify_all();
+    return PDEP_OK;
+}
+
+int pdep_poll_eigs(pdep_server* S, uint64_t ticket, int* state, pdep_job_result* res, double* eps_out, int eps_cap) {
+    if (!S || !state) return fail(PDEP_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || !it->second->eigs) return fail(PDEP_ENOTFOUND, "unknown ticket");
+    const Chi0Req* r = it->second.get();
+    *state = r->state;
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        res->n_pdep = r->n_pdep;
+        if (auto sy = S->systems.find(r->sys); sy != S->systems.end()) {
+            res->hbm_estimate = sy->second->est;
+            res->gap = sy->second->gap;
+        }
+        if (r->state == PDEP_JOB_DONE || r->state == PDEP_JOB_FAILED) {
+            res->status = r->status;
+            res->eig_iterations = r->eig_iterations;
+            res->queue_ms = ms_between(r->t_submit, r->t_start);
+            res->run_ms = ms_between(r->t_start, r->t_end);
+            res->latency_ms = ms_between(r->t_submit, r->t_end);
+        }
+    }
+    if (r->state == PDEP_JOB_DONE && eps_out)
+        for (int i = 0; i < std::min(eps_cap, (int)r->eps.size()); ++i) eps_out[i] = r->eps[i];
+    if (r->state == PDEP_JOB_FAILED) pdep_set_error_message(r->msg.c_str());
+    return PDEP_OK;
+}
+
 int pdep_poll_chi0(pdep_server* S, uint64_t ticket, int* state, pdep_chi0_result* res, double* out,
                    int out_cap_pert) {
     if (!S || !state) return fail(PDEP_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return fail(PDEP_ENOTFOUND, "unknown ticket");
+    if (it == S->reqs.end() || it->second->eigs) return fail(PDEP_ENOTFOUND, "unknown ticket");
     Chi0Req* r = it->second.get();
     *state = r->state;
     if (res) {

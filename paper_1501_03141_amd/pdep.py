@@ -234,9 +234,11 @@ def load(path: str = LIB_PATH):
     lib.pdep_server_remove_system.argtypes = [P, C.c_uint64]
     lib.pdep_submit_chi0.argtypes = [P, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_uint64)]
     lib.pdep_poll_chi0.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(Chi0Result), C.c_void_p, C.c_int]
+    lib.pdep_submit_eigs.argtypes = [P, C.c_uint64, C.c_int, C.c_uint64, C.POINTER(EigOpts), C.POINTER(C.c_uint64)]
+    lib.pdep_poll_eigs.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(JobResult), D, C.c_int]
     for name in ("pdep_server_create", "pdep_submit", "pdep_poll", "pdep_server_wait", "pdep_server_stats_get",
                  "pdep_server_destroy", "pdep_server_add_system", "pdep_server_remove_system", "pdep_submit_chi0",
-                 "pdep_poll_chi0"):
+                 "pdep_poll_chi0", "pdep_submit_eigs", "pdep_poll_eigs"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
                  "chi0_apply_raw", "chi0_apply_noalloc", "chibar_apply", "pdep_body_lanczos", "pdep_head_wings",
@@ -641,13 +643,40 @@ class Server:
         self._keep[t.value] = (int(a.shape[0]), int(a.shape[1]))
         return t.value
 
+    def submit_eigs(self, system_id, n_pdep, seed=0, eig_tol=1e-7, eig_maxit=60, n_buffer=0, max_subspace=0):
+        """Queue a PDEP Davidson on a resident system (reuses its orbitals)."""
+        eo = EigOpts(float(eig_tol), int(eig_maxit), int(max_subspace), int(n_buffer), 0, 0.0, 0)
+        t = C.c_uint64()
+        _check(self._lib.pdep_submit_eigs(self._h, C.c_uint64(system_id), int(n_pdep), C.c_uint64(int(seed)),
+                                          C.byref(eo), C.byref(t)))
+        self._keep[t.value] = int(n_pdep)
+        return t.value
+
+    def poll_eigs(self, ticket):
+        """(state, result dict or None, eps or None) of a request of submit_eigs."""
+        st = C.c_int()
+        res = JobResult()
+        n = self._keep.get(ticket, 0)
+        eps = np.empty(max(n, 1), dtype=np.float64)
+        _check(self._lib.pdep_poll_eigs(self._h, C.c_uint64(ticket), C.byref(st), C.byref(res),
+                                        eps.ctypes.data_as(C.POINTER(C.c_double)), n))
+        if st.value == JOB_DONE:
+            return st.value, res.as_dict(), eps[:n].copy()
+        if st.value == JOB_FAILED:
+            d = res.as_dict()
+            d["error"] = self._lib.pdep_last_error().decode()
+            return st.value, d, None
+        return st.value, None, None
+
     def poll_chi0(self, ticket):
         """(state, result dict or None, out [n_pert, N_pw - 1] or None); never blocks."""
         st = C.c_int()
         res = Chi0Result()
-        n, w = self._keep[ticket]
-        out = np.empty((n, w), dtype=np.complex128)
-        _check(self._lib.pdep_poll_chi0(self._h, C.c_uint64(ticket), C.byref(st), C.byref(res), out.ctypes.data, n))
+        kept = self._keep.get(ticket)
+        n, w = kept if isinstance(kept, tuple) else (0, 1)   # not a chi0 request: the library says so
+        out = np.empty((max(n, 1), w), dtype=np.complex128)
+        _check(self._lib.pdep_poll_chi0(self._h, C.c_uint64(ticket), C.byref(st), C.byref(res),
+                                        out.ctypes.data if n > 0 else None, n))
         if st.value == JOB_DONE:
             return st.value, res.as_dict(), out
         if st.value == JOB_FAILED:

@@ -139,3 +139,27 @@ def test_result_is_delivered_once():
         with pytest.raises(pdep.PdepError) as e:
             s.poll_chi0(t)
         assert e.value.code == pdep.PDEP_EINVAL
+
+
+def test_pdep_request_runs_alone_between_chi0_batches():
+    with pdep.Server(max_running=1, fake=True, fake_ms_per_gb=40.0) as s:
+        sid = _system(s)
+        t1 = s.submit_chi0(sid, _phi(2, 1))
+        te = s.submit_eigs(sid, 6, seed=11)
+        t2 = s.submit_chi0(sid, _phi(1, 2))
+        t3 = s.submit_chi0(sid, _phi(3, 3))
+        for t in (t1, te, t2, t3):
+            assert s.wait(t, 10000) == pdep.JOB_DONE
+        state, res, eps = s.poll_eigs(te)
+        assert state == pdep.JOB_DONE and res["status"] == 0 and res["n_pdep"] == 6
+        np.testing.assert_allclose(eps, 1.0 + (11 % 97 + 1) / np.arange(1, 7))
+        r1 = s.poll_chi0(t1)[1]
+        r2 = s.poll_chi0(t2)[1]
+        # the chi0 blocks on either side of the Davidson never share its batch
+        assert r1["batch_pert"] == 2 and r2["batch_requests"] == 2 and r2["batch_pert"] == 4
+        with pytest.raises(pdep.PdepError) as e:
+            s.poll_chi0(te)
+        assert e.value.code == pdep.PDEP_ENOTFOUND
+        with pytest.raises(pdep.PdepError) as e:
+            s.submit_eigs(sid, 4, eig_tol=-1.0)
+        assert e.value.code == pdep.PDEP_EINVAL

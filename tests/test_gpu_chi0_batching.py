@@ -46,3 +46,31 @@ def test_batched_requests_match_alone(name, prec, tol, bar):
         assert err <= bar, (name, prec, err, r["batch_requests"])
         print(f"{name} prec {prec}: request of {p.shape[0]} in a batch of {r['batch_requests']} requests "
               f"({r['batch_pert']} perturbations): max rel diff vs alone {err:.2e}")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec,tol", [(pdep.PDEP_FP64, 1e-12), (pdep.PDEP_MIXED_BF16X3, 1e-10)])
+def test_pdep_on_resident_system_matches_standalone(prec, tol):
+    """pdep_submit_eigs on a resident system (its orbitals reused, queued behind a chi0
+    batch) gives the dielectric eigenvalues of pdep_eigs on a fresh context of the same
+    system with the same seeded start (Sec. 2.3, Fig. pdepscheme)."""
+    w = inputs.WORKLOADS["tiny"]
+    V = inputs.vloc(w)
+    with pdep.Context(w.L, w.n, w.ecut, V, w.n_v, precision=prec, cg_tol=tol, use_torch=False) as c:
+        alone, _, _ = c.eigs(w.n_pdep, seed=w.seed, tol=1e-9, maxit=60)
+        miller = c.miller()
+    nz = np.any(miller != 0, axis=1)
+    phi = inputs.trial_block(miller[nz], 3, w.seed + 1)
+    with pdep.Server(max_running=1) as s:
+        sid = s.add_system(w.L, w.n, w.ecut, V, w.n_v, precision=prec, cg_tol=tol)
+        tc = s.submit_chi0(sid, phi)
+        te = s.submit_eigs(sid, w.n_pdep, seed=w.seed, eig_tol=1e-9, eig_maxit=60)
+        assert s.wait(tc, 120000) == pdep.JOB_DONE
+        assert s.wait(te, 120000) == pdep.JOB_DONE
+        state, res, eps = s.poll_eigs(te)
+        assert state == pdep.JOB_DONE and res["status"] == 0, res
+        s.remove_system(sid)
+    err = float(np.max(np.abs(eps - alone) / np.abs(alone)))
+    print(f"prec {prec}: resident-system PDEP vs standalone, max rel diff {err:.2e}, "
+          f"{res['eig_iterations']} iterations")
+    assert err <= 1e-12, (eps, alone)
