@@ -119,7 +119,10 @@ void stream_free(void* p, void* ctx) { (void)hipFreeAsync(p, static_cast<hipStre
 bool admissible(pdep_server* S) {
     if (S->queue.empty() || S->running >= S->opts.max_running) return false;
     const JobRec* j = S->queue.front();
-    return S->committed + j->est <= S->budget || S->running == 0;
+    // a job that does not fit starts only on an otherwise empty device (no running job and
+    // no resident system holds memory), so that a job larger than the free budget cannot
+    // wait forever behind smaller ones
+    return S->committed + j->est <= S->budget || (S->running == 0 && S->committed == 0);
 }
 
 void run_fake(pdep_server* S, JobRec* j) {

@@ -163,3 +163,23 @@ def test_pdep_request_runs_alone_between_chi0_batches():
         with pytest.raises(pdep.PdepError) as e:
             s.submit_eigs(sid, 4, eig_tol=-1.0)
         assert e.value.code == pdep.PDEP_EINVAL
+
+
+def test_jobs_are_admitted_within_the_budget_left_by_resident_systems():
+    with pdep.Server(max_running=2, fake=True, fake_ms_per_gb=0.0) as s0:
+        sid = _system(s0)
+        est_sys = s0.stats()["committed_bytes"]
+        t = s0.submit(CELL["L"], CELL["n"], CELL["ecut"], np.zeros(16 ** 3), 4, 8, seed=1)
+        s0.wait(t, 10000)
+        est_job = s0.poll(t)[1]["hbm_estimate"]
+    # room for the system and one job beside it, not two
+    budget = est_sys + est_job + est_job // 2
+    with pdep.Server(max_running=4, hbm_budget=budget, fake=True, fake_ms_per_gb=30.0) as s:
+        sid = _system(s)
+        tickets = [s.submit(CELL["L"], CELL["n"], CELL["ecut"], np.zeros(16 ** 3), 4, 8, seed=k) for k in range(4)]
+        for t in tickets:
+            assert s.wait(t, 20000) == pdep.JOB_DONE
+        st = s.stats()
+        assert st["peak_running"] == 1 and st["peak_committed_bytes"] <= budget
+        s.remove_system(sid)
+        assert s.stats()["committed_bytes"] == 0
