@@ -309,7 +309,15 @@ def _torch_allocator():
         return torch.cuda.caching_allocator_alloc(int(nbytes), dev, torch.cuda.current_stream(dev))
 
     def free(ptr, _ctx):
-        torch.cuda.caching_allocator_delete(ptr)
+        # a context collected at interpreter shutdown may outlive torch's allocator; the
+        # process is ending, so its memory goes with it
+        cuda = getattr(torch, "cuda", None)
+        if cuda is None or not hasattr(cuda, "caching_allocator_delete"):
+            return
+        try:
+            cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
     a = Allocator(ALLOC_FN(alloc), FREE_FN(free), None)
     return a
 
