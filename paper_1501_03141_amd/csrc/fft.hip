@@ -1283,8 +1283,12 @@ __host__ __device__ inline int quad64_data_elems(const FftDims& d, int nl) {
     return a > b ? a : b;
 }
 
+// Threads of the lane-quad slab pass of H: one quad per (slab, iy) line of the x pass,
+// ZG = 64 / NL slabs (192 threads for NL = 24 and 48: no wave without an x line).
+constexpr int quad64_threads(int nl) { return 4 * (64 / nl) * nl; }
+
 // Slab pass of H (V multiply), FP64, NX = NY = NL (a multiple of 4): the register slab
-// pass with every line on a lane quad.  A workgroup of 256 threads (64 quads) takes
+// pass with every line on a lane quad.  A workgroup of quad64_threads(NL) threads takes
 // ZG = 64 / NL consecutive z slabs of one row: stick rows to LDS; one quad per (slab,
 // non-empty column): inverse y DFT into the transpose plane [slab][iy][column]; one
 // quad per (slab, iy): inverse x DFT (decimation in time), times V(z, x, y), forward x
@@ -1293,11 +1297,12 @@ __host__ __device__ inline int quad64_data_elems(const FftDims& d, int nl) {
 // the stick row; stick rows back.  Stick rows and transpose planes share LDS (every
 // quad holds its line in registers across the barrier between).
 template <int NL>
-__global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t, double2* __restrict__ sticks,
-                                                        const double* __restrict__ Vr) {
+__global__ __launch_bounds__(quad64_threads(NL)) void k_slab_hv_quad64(FftDims d, BasisTables t,
+                                                                       double2* __restrict__ sticks,
+                                                                       const double* __restrict__ Vr) {
     static_assert(NL % 4 == 0 && NL <= 64, "lines split over a lane quad");
     constexpr int Q = NL / 4, H = NL / 2;
-    constexpr int ZG = 64 / NL;
+    constexpr int ZG = 64 / NL, NT = quad64_threads(NL);
     extern __shared__ __align__(16) unsigned char smem[];
     double2* lds = reinterpret_cast<double2*>(smem);
     const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
@@ -1319,7 +1324,7 @@ __global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t
         const double ang = 6.283185307179586476925 * tid / NL;
         tw[tid] = make_double2(cos(ang), sin(ang));
     }
-    stage_rows_in<double2, 256, 4>(lds, g, nzh, sld);
+    stage_rows_in<double2, NT, 4>(lds, g, nzh, sld);
     __syncthreads();
     const QuadLane Lp = quad_lane<+1>(tl), Lm = quad_lane<-1>(tl);
 
@@ -1394,7 +1399,7 @@ __global__ __launch_bounds__(256) void k_slab_hv_quad64(FftDims d, BasisTables t
     }
     __syncthreads();
     for (int zz = 0; zz < nzh; ++zz)
-        for (int e = tid; e < ns; e += 256) g[(long)zz * sld + e] = lds[zz * sld + e];
+        for (int e = tid; e < ns; e += NT) g[(long)zz * sld + e] = lds[zz * sld + e];
 }
 
 // Density on lane quads (FP64, NX = NY = NL): for ZG = 64 / NL slabs of PB consecutive
@@ -1652,6 +1657,135 @@ __global__ void k_transpose_grid(int nx, int ny, int nz, const double* __restric
     out[(long)row * ng + g] = in[(long)row * ng + src];
 }
 
+// ------------------------------------ FP64 paired sticks-to-sphere pass on lane quads ---
+// The FP64 form of the register sticks-to-sphere pass: a z stick of NZ doubles is held
+// by the four lanes of a DPP quad (NZ / 4 values each) and transformed with the lane-quad
+// DFT of the slab pass.  A workgroup of 256 threads takes kQuadStickGroup front sticks
+// (quads 0 .. 31, waves 0 and 1) and their mirrors ns - 1 - s (quads 32 .. 63, waves 2
+// and 3); the two half-sphere rows are separated as in k_sticks_to_sphere_pair_reg.
+// (The sphere-to-sticks direction on lane quads measured slower than the LDS form, with
+// and without an LDS tile for whole-row stores, and is not used.)
+constexpr int kQuadStickGroup = 32;
+
+// Sticks of packed row pr -> half-sphere rows a, b with the epilogue EPI_SHIFTED_H of
+// k_sticks_to_sphere_pair (out = F + (kin - shift) x, optional partial sums of
+// Re<x, out> per row and workgroup), FP64.
+template <int NZ>
+__global__ __launch_bounds__(256) void k_sticks_to_sphere_pair_quad64(
+    FftDims d, BasisTables t, const double2* __restrict__ sticks, int nrows, int group, double2* __restrict__ out,
+    long ld_out, const double2* __restrict__ x, long ld_x, const double* __restrict__ kin,
+    const double* __restrict__ shift, int nshift, double* __restrict__ dot_part) {
+    static_assert(NZ % 4 == 0 && NZ <= 64, "sticks split over a lane quad");
+    constexpr int Q = NZ / 4, HALF = (NZ + 1) / 2;
+    constexpr int GS = kQuadStickGroup, NT = 256, LQ = 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][NT];
+    double2* bufF = reinterpret_cast<double2*>(smem);
+    double2* bufM = bufF + d.sgp_max;
+    double2* tw = bufM + d.sgp_max;   // exp(2 pi i e / NZ), e < NZ
+    const int nfront = (d.ns + 1) / 2;
+    const int s0 = blockIdx.x * GS, pr = blockIdx.y;
+    const int nf = min(GS, nfront - s0);
+    const int kb = t.stick_start[s0], ke = t.stick_start[s0 + nf];
+    const int tid = threadIdx.x;
+    if (tid < NZ) {
+        const double ang = 6.283185307179586476925 * tid / NZ;
+        tw[tid] = make_double2(cos(ang), sin(ang));
+    }
+    const int u = tid >> 2, tl = tid & 3;
+    const bool mir = u >= GS;                   // wave-uniform
+    const int j = mir ? u - GS : u;
+    const int sf = s0 + j;
+    double2 v[Q];
+    if (j < nf) {
+        const int sk = mir ? d.ns - 1 - sf : sf;
+        const double2* src = sticks + (long)pr * NZ * d.sld + sk;
+        sfor<0, Q>([&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            v[jj] = src[(long)(4 * jj + tl) * d.sld];
+        });
+    }
+    __syncthreads();   // the twiddle table is complete
+    if (j < nf) {
+        const QuadLane L = quad_lane<-1>(tl);
+        quad_dft_dit<-1, NZ>(v, L, tw);
+        const int blk = Q * quad_block(tl);
+        const int ks = t.stick_start[sf] - kb, kz = (t.stick_start[sf + 1] - t.stick_start[sf] - 1) / 2;
+        double2* line = (mir ? bufM : bufF) + ks + kz;
+        const int sgn = mir ? -1 : 1;           // the mirror stick's mz lands at the front entry of -mz
+        sfor<0, Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int i = k + blk;
+            const int mz = i < HALF ? i : i - NZ;
+            if (mz >= -kz && mz <= kz) line[sgn * mz] = v[k];
+        });
+    }
+    __syncthreads();
+    const int c = (d.npw - 1) / 2;
+    const int k1 = min(ke, c + 1);
+    const double half = 0.5 / ((double)d.nx * d.ny * d.nz);
+    const PairRows rw = pair_rows(pr, group, nrows);
+    const int ra = rw.a, rb = ra + 1;
+    const bool has_b = rw.has_b;
+    const double sha = shift[ra % nshift], shb = has_b ? shift[rb % nshift] : 0.0;
+    double2* oa = out + (long)ra * ld_out;
+    double2* ob = oa + ld_out;
+    const double2* xa = x + (long)ra * ld_x;
+    const double2* xb = xa + ld_x;
+    double acca = 0.0, accb = 0.0;
+    // LQ entries per thread at a time, their kinetic energies and x values loaded before
+    // the first is used (clamped indices, so every load is in bounds)
+    for (int e0 = kb + tid; e0 < k1; e0 += LQ * NT) {
+        double kk[LQ];
+        double2 xva[LQ], xvb[LQ];
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int k = min(e0 + q * NT, k1 - 1);
+            kk[q] = kin[k];
+            xva[q] = xa[k];
+            xvb[q] = has_b ? xb[k] : make_double2(0.0, 0.0);
+        });
+        sfor<0, LQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int k = e0 + q * NT;
+            if (k < k1) {
+                const double2 W = bufF[k - kb], Wm = bufM[k - kb];
+                const double w = k == c ? 1.0 : 2.0;
+                {
+                    const double2 xv = xva[q];
+                    const double dk = kk[q] - sha;
+                    const double2 ov = make_double2(half * (W.x + Wm.x) + dk * xv.x, half * (W.y - Wm.y) + dk * xv.y);
+                    oa[k] = ov;
+                    acca += w * (xv.x * ov.x + xv.y * ov.y);
+                }
+                if (has_b) {
+                    const double2 xv = xvb[q];
+                    const double dk = kk[q] - shb;
+                    const double2 ov = make_double2(half * (W.y + Wm.y) + dk * xv.x, half * (Wm.x - W.x) + dk * xv.y);
+                    ob[k] = ov;
+                    accb += w * (xv.x * ov.x + xv.y * ov.y);
+                }
+            }
+        });
+    }
+    if (dot_part) {
+        red[0][tid] = acca;
+        red[1][tid] = accb;
+        __syncthreads();
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                red[0][tid] += red[0][tid + s];
+                red[1][tid] += red[1][tid + s];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            dot_part[(long)ra * gridDim.x + blockIdx.x] = red[0][0];
+            if (has_b) dot_part[(long)rb * gridDim.x + blockIdx.x] = red[1][0];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host side ------
 
 void check_stages(const AxisPlan& p, int nlines, const char* what) {
@@ -1774,8 +1908,19 @@ bool pair_reg_ok(const FftDims& d) {
     return len && d.sgp_max > 0 && 2 * (size_t)d.sgp_max * sizeof(float2) <= 65536;
 }
 
+// The FP64 lane-quad sticks-to-sphere pass: z lengths that are multiples of 4 up to 48,
+// its staging arrays, twiddles and reduction space within 64 KB of LDS.
+bool pair_quad64_ok(const FftDims& d) {
+    const bool len = d.nz == 16 || d.nz == 24 || d.nz == 32 || d.nz == 48;
+    return len && d.sgp_max > 0 &&
+           (2 * (size_t)d.sgp_max + d.nz) * sizeof(double2) + 2 * 256 * sizeof(double) <= 65536;
+}
+size_t pair_quad64_lds(const FftDims& d) { return (2 * (size_t)d.sgp_max + d.nz) * sizeof(double2); }
+
 template <typename T> int sticks_to_sphere_pair_groups(const FftDims& d) {
     if (sizeof(T) == sizeof(float) && pair_reg_ok(d)) return ((d.ns + 1) / 2 + kPairStickGroup - 1) / kPairStickGroup;
+    if (sizeof(T) == sizeof(double) && pair_quad64_ok(d))
+        return ((d.ns + 1) / 2 + kQuadStickGroup - 1) / kQuadStickGroup;
     const int sgh = sticks_per_group<T>(d.nz) / 2;
     return ((d.ns + 1) / 2 + sgh - 1) / sgh;
 }
@@ -1841,6 +1986,18 @@ void launch_sticks_to_sphere_pair(const FftDims& d, const BasisTables& t, const 
                     hipLaunchKernelGGL((k_sticks_to_sphere_pair_reg<NZ>), grid, dim3(2 * kPairStickGroup), lds, s, d,
                                        t, sticks, nrows, group > 0 ? group : nrows, out, ld_out, x, ld_x, kin, shift,
                                        nshift > 0 ? nshift : 1, dot_part);
+            });
+            PDEP_HIP(hipGetLastError());
+            return;
+        }
+    } else {
+        if (epi == EPI_SHIFTED_H && pair_quad64_ok(d)) {
+            const dim3 grid(((d.ns + 1) / 2 + kQuadStickGroup - 1) / kQuadStickGroup, npair);
+            with_n(d.nz, [&]<int NZ>() {
+                if constexpr (NZ > 0 && NZ % 4 == 0 && NZ <= 48)
+                    hipLaunchKernelGGL((k_sticks_to_sphere_pair_quad64<NZ>), grid, dim3(256), pair_quad64_lds(d), s,
+                                       d, t, sticks, nrows, group > 0 ? group : nrows, out, ld_out, x, ld_x, kin,
+                                       shift, nshift > 0 ? nshift : 1, dot_part);
             });
             PDEP_HIP(hipGetLastError());
             return;
@@ -1916,7 +2073,8 @@ void launch_slab_hv(const FftDims& d, const BasisTables& t, cplx<T>* sticks, int
                     constexpr int ZG = 64 / N;
                     ProfScope prof_(K_SLAB_HV64, s, bytes, flops);
                     const dim3 grid((d.nz + ZG - 1) / ZG, nrows);
-                    hipLaunchKernelGGL((k_slab_hv_quad64<N>), grid, dim3(256), lds, s, d, t, sticks, Vz);
+                    hipLaunchKernelGGL((k_slab_hv_quad64<N>), grid, dim3(quad64_threads(N)), lds, s, d, t, sticks,
+                                       Vz);
                     PDEP_HIP(hipGetLastError());
                     done = true;
                 }
