@@ -1283,8 +1283,10 @@ __host__ __device__ inline int quad64_data_elems(const FftDims& d, int nl) {
     return a > b ? a : b;
 }
 
-// Threads of the lane-quad slab pass of H: one quad per (slab, iy) line of the x pass,
-// ZG = 64 / NL slabs (192 threads for NL = 24 and 48: no wave without an x line).
+// Threads of the lane-quad slab passes of H and of the forward transform: one quad per
+// (slab, iy) line of the x pass, ZG = 64 / NL slabs (192 threads for NL = 24 and 48: no
+// wave without an x line).  The density pass keeps 256 threads: it is held to two waves
+// per SIMD by its accumulators, and three-wave workgroups would leave SIMD slots empty.
 constexpr int quad64_threads(int nl) { return 4 * (64 / nl) * nl; }
 
 // Slab pass of H (V multiply), FP64, NX = NY = NL (a multiple of 4): the register slab
@@ -1509,11 +1511,12 @@ __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTab
 // contiguous x block) into the transpose plane -> forward y (decimation in time) -> the
 // row's sticks.
 template <int NL, bool PRODUCT>
-__global__ __launch_bounds__(256) void k_slab_fwd_quad64(FftDims d, BasisTables t, double2* __restrict__ sticks,
-                                                         const double* __restrict__ Vr,
-                                                         const double2* __restrict__ u, int nv) {
+__global__ __launch_bounds__(quad64_threads(NL)) void k_slab_fwd_quad64(FftDims d, BasisTables t,
+                                                                        double2* __restrict__ sticks,
+                                                                        const double* __restrict__ Vr,
+                                                                        const double2* __restrict__ u, int nv) {
     constexpr int Q = NL / 4, H = NL / 2;
-    constexpr int ZG = 64 / NL;
+    constexpr int ZG = 64 / NL, NT = quad64_threads(NL);
     extern __shared__ __align__(16) unsigned char smem[];
     double2* lds = reinterpret_cast<double2*>(smem);
     const int mxmax = d.mxmax, sld = d.sld, nz = d.nz;
@@ -1584,7 +1587,7 @@ __global__ __launch_bounds__(256) void k_slab_fwd_quad64(FftDims d, BasisTables 
     __syncthreads();
     double2* g = sticks + ((long)row * nz + z0) * sld;
     const int ns = d.ns;
-    stage_rows_out<double2, 256, 4>(g, lds, nzh, sld, ns);
+    stage_rows_out<double2, NT, 4>(g, lds, nzh, sld, ns);
 }
 
 constexpr int kMaxAcc = 24;
@@ -2138,12 +2141,12 @@ void launch_slab_fwd_product(const FftDims& d, const BasisTables& t, const T* Vr
                     if (u) {
                         ProfScope prof_(K_SLAB_FWD_PRODUCT, s,
                                         (double)nrows * (sk + g * sizeof(cplx<T>)) + g * sizeof(T) * (nrows / nv));
-                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, true>), grid, dim3(256), lds, s, d, t, sticks, Vr,
-                                           u, nv);
+                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, true>), grid, dim3(quad64_threads(N)), lds, s, d, t,
+                                           sticks, Vr, u, nv);
                     } else {
                         ProfScope prof_(K_SLAB_FWD_PRODUCT, s, (double)nrows * (sk + g * sizeof(T)));
-                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, false>), grid, dim3(256), lds, s, d, t, sticks,
-                                           Vr, nullptr, 1);
+                        hipLaunchKernelGGL((k_slab_fwd_quad64<N, false>), grid, dim3(quad64_threads(N)), lds, s, d, t,
+                                           sticks, Vr, nullptr, 1);
                     }
                     PDEP_HIP(hipGetLastError());
                     done = true;
