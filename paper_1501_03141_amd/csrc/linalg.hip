@@ -585,11 +585,20 @@ __global__ void k_convert_scaled(int K, const cplx<Tin>* __restrict__ in, long l
 
 template <typename T>
 __global__ void k_axpy_rows(int K, const cplx<T>* __restrict__ d, long ldd, const int* __restrict__ rows,
-                            const double* __restrict__ rowscale, double2* __restrict__ x, long ldx) {
+                            const double* __restrict__ rowscale, double2* __restrict__ x, long ldx, int set) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;
-    if (k >= K) return;
+    if (k >= (set ? (int)ldx : K)) return;
     const double s = rowscale[row];
+    if (set) {
+        double2 xv = make_double2(0.0, 0.0);
+        if (k < K && s != 0.0) {
+            const cplx<T> v = d[(long)row * ldd + k];
+            xv = make_double2(s * (double)v.x, s * (double)v.y);
+        }
+        x[(rows ? rows[row] : row) * ldx + k] = xv;
+        return;
+    }
     if (s == 0.0) return;   // a dropped solution (it may hold non-finite values)
     const cplx<T> v = d[(long)row * ldd + k];
     const long xr = rows ? rows[row] : row;
@@ -844,10 +853,12 @@ void launch_convert_rows(int nrows, int K, const cplx<Tin>* in, long ldi, const 
 
 template <typename T>
 void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* rows, const double* rowscale,
-                      double2* x, long ldx, hipStream_t s) {
+                      double2* x, long ldx, hipStream_t s, bool set) {
     if (nrows <= 0) return;
+    PDEP_REQUIRE(ldx >= K && ldx <= (1L << 30), PDEP_EINVAL, "axpy_rows: bad row stride");
     ProfScope prof_(K_MISC, s);
-    hipLaunchKernelGGL(k_axpy_rows<T>, rows_grid(K, nrows), dim3(256), 0, s, K, d, ldd, rows, rowscale, x, ldx);
+    hipLaunchKernelGGL(k_axpy_rows<T>, rows_grid(set ? (int)ldx : K, nrows), dim3(256), 0, s, K, d, ldd, rows,
+                       rowscale, x, ldx, set ? 1 : 0);
     PDEP_HIP(hipGetLastError());
 }
 
@@ -927,7 +938,7 @@ void launch_compact_s1(int nrows, int npw, int g0, const double2* in, long ldi, 
     template void launch_cg_step2<T>(int, int, cplx<T>*, const cplx<T>*, long, const double*, double*,         \
                                      const int*, hipStream_t);                                                \
     template void launch_axpy_rows<T>(int, int, const cplx<T>*, long, const int*, const double*, double2*,     \
-                                      long, hipStream_t);
+                                      long, hipStream_t, bool);
 
 PDEP_INST_LA(double)
 PDEP_INST_LA(float)

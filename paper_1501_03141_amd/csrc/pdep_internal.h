@@ -319,10 +319,12 @@ void launch_cg_check(int nrows, const double* rr, const double* thr2, int* activ
 template <typename Tin, typename Tout>
 void launch_convert_rows(int nrows, int K, const cplx<Tin>* in, long ldi, const int* rows,
                          const double* rowscale, cplx<Tout>* out, long ldo, hipStream_t s);
-// x[rows[r]] += rowscale[r] * d[r] (rows with rowscale 0 are left untouched)
+// x[rows[r]] += rowscale[r] * d[r] (rows with rowscale 0 are left untouched); with set,
+// x[rows[r]] = rowscale[r] * d[r] instead, zeros for rowscale 0 and in the padding
+// entries K .. ldx - 1 (the state of a zero-filled x after the update)
 template <typename T>
 void launch_axpy_rows(int nrows, int K, const cplx<T>* d, long ldd, const int* rows,
-                      const double* rowscale, double2* x, long ldx, hipStream_t s);
+                      const double* rowscale, double2* x, long ldx, hipStream_t s, bool set = false);
 // out[r][k] = 2 in[r][k] for k < K - 1, in[r][K - 1] at k = K - 1 (half-sphere weights)
 template <typename T>
 void launch_half_weights(int nrows, int K, const cplx<T>* in, long ldi, cplx<T>* out, long ldo, hipStream_t s);

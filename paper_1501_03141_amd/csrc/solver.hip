@@ -796,9 +796,10 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
     std::vector<double> bb(n), rr(n), dots(n);
     launch_row_dots<double>(n, npw, b64, ld, b64, ld, sc.rr, nullptr, s, true);
     PDEP_HIP(hipMemcpyAsync(bb.data(), sc.rr, n * sizeof(double), hipMemcpyDeviceToHost, s));
-    launch_fill_zero(x64, vb64, s);
-    PDEP_HIP(hipMemcpyAsync(r64, b64, vb64, hipMemcpyDeviceToDevice, s));
     PDEP_HIP(hipStreamSynchronize(s));
+    // x starts at zero and r at b: the first step reads b itself, and when it updates
+    // every row it writes x = its correction (zeros elsewhere) instead of adding it to a
+    // zero-filled x, so neither the fill nor the copy of b is made then
     for (int i = 0; i < n; ++i) PDEP_REQUIRE(std::isfinite(bb[i]), PDEP_EINVAL, "non-finite right-hand side");
     if (ref2) {
         std::vector<double> w2(n);
@@ -818,12 +819,15 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         rows.clear();
         for (int i = 0; i < n; ++i)
             if (bb[i] > 0.0 && rr[i] > tol * tol * bb[i]) rows.push_back(i);
+        const int na = (int)rows.size();
+        const bool set_x = step == 0 && na == n;   // the first update writes every row of x
+        if (step == 0 && !set_x) launch_fill_zero(x64, vb64, s);
         if (rows.empty()) break;
         if (step >= std::max(1, c.opts.refine_maxit)) {
             st.n_notconv += (int)rows.size();
             break;
         }
-        const int na = (int)rows.size();
+        const double2* rsrc = step == 0 ? b64 : r64;   // r = b before the first update
         std::vector<double> scale(na), invscale(na), shift(na), thr2(na);
         for (int j = 0; j < na; ++j) {
             const int i = rows[j];
@@ -851,7 +855,7 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
         const long ldh = sphere_ld(npw);
         if (mixed) {
             float2* rhs = static_cast<float2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(float2)));
-            launch_convert_rows<double, float>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            launch_convert_rows<double, float>(na, npw, rsrc, ld, d_rows, d_scale, rhs, ldh, s);
             c.pc_x3 = x3;
             if (!fp32_row.empty() && !x3)
                 for (int i : rows) fp32_row[i] = 1;
@@ -874,12 +878,12 @@ void solve_rows(Ctx& c, int n, const double2* b64, double2* x64, long ld, ApplyS
                             step + 1), fflush(stderr);
                 x3 = false;
             }
-            launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s);
+            launch_axpy_rows<float>(na, npw, cg_solution<float>(c), ldh, d_rows, d_invscale, x64, ld, s, set_x);
         } else {
             double2* rhs = static_cast<double2*>(c.ws(W_RHS, (size_t)na * ldh * sizeof(double2)));
-            launch_convert_rows<double, double>(na, npw, r64, ld, d_rows, d_scale, rhs, ldh, s);
+            launch_convert_rows<double, double>(na, npw, rsrc, ld, d_rows, d_scale, rhs, ldh, s);
             cg_inner<double>(c, na, rhs, ldh, sc, c.opts.cg_maxit, st);
-            launch_axpy_rows<double>(na, npw, cg_solution<double>(c), ldh, d_rows, d_invscale, x64, ld, s);
+            launch_axpy_rows<double>(na, npw, cg_solution<double>(c), ldh, d_rows, d_invscale, x64, ld, s, set_x);
         }
         std::vector<int> its(na);
         PDEP_HIP(hipMemcpyAsync(its.data(), sc.iters, na * sizeof(int), hipMemcpyDeviceToHost, s));
