@@ -88,6 +88,28 @@ def test_uniform_potential_gives_zero_response(oracle_tiny):
     assert st["cg_iter_max"] == 0
 
 
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_zero_and_ordinary_right_hand_sides_in_one_block(oracle_tiny, mode):
+    """Degenerate rows beside ordinary ones: a uniform potential (b = 0 for all its
+    bands) between two random ones, so the refinement updates only part of the rows
+    from its first step on (x starts from a zero fill instead of being written by the
+    first update).  The uniform potential's response is exactly zero and the others
+    match the oracle."""
+    V, m, gs, lam, Phi = oracle_tiny
+    from paper_1501_03141_amd import pdep
+    dv = inputs.random_grid_potentials(W.n, 3, 106)
+    dv[1] = 0.7
+    want = np.stack([R.chi0_real(m, gs, dv[i]) for i in (0, 2)])
+    kw = {} if mode == "fp64" else {"precision": pdep.PDEP_MIXED_BF16X3, "cg_tol": 1e-10}
+    with _ctx(V, gs, **kw) as c:
+        got, st = c.chi0_apply_raw(dv)
+    assert st["n_notconv"] == 0
+    assert np.max(np.abs(got[1])) < 1e-13
+    err = _relerr(got[[0, 2]], want)
+    print(mode, "stats", st, "relerr", err)
+    assert err <= (1e-10 if mode == "fp64" else 1e-8)
+
+
 def test_empty_block(oracle_tiny):
     V, m, gs, lam, Phi = oracle_tiny
     with _ctx(V, gs) as c:
