@@ -332,8 +332,11 @@ void close_system(pdep_server* S, std::unique_ptr<SysRec> y) {
     if (y->stream) (void)hipStreamSynchronize(y->stream);
     if (y->blas) rocblas_destroy_handle(y->blas);
     if (y->stream) (void)hipStreamDestroy(y->stream);
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->committed -= y->est;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->committed -= y->est;
+    }
+    S->cv.notify_all();   // a queued job may fit in the memory the system held
 }
 
 int fail(int code, const std::string& m) {

@@ -183,3 +183,20 @@ def test_jobs_are_admitted_within_the_budget_left_by_resident_systems():
         assert st["peak_running"] == 1 and st["peak_committed_bytes"] <= budget
         s.remove_system(sid)
         assert s.stats()["committed_bytes"] == 0
+
+
+def test_a_job_waiting_for_memory_starts_when_a_system_is_removed():
+    with pdep.Server(max_running=1, fake=True, fake_ms_per_gb=0.0) as s0:
+        _system(s0)
+        est_sys = s0.stats()["committed_bytes"]
+        t = s0.submit(CELL["L"], CELL["n"], CELL["ecut"], np.zeros(16 ** 3), 4, 8, seed=1)
+        s0.wait(t, 10000)
+        est_job = s0.poll(t)[1]["hbm_estimate"]
+    # the job does not fit beside the resident system, and nothing else happens on the
+    # server after the removal: the removal itself has to start it
+    with pdep.Server(max_running=1, hbm_budget=est_sys + est_job // 2, fake=True, fake_ms_per_gb=0.0) as s:
+        sid = _system(s)
+        t = s.submit(CELL["L"], CELL["n"], CELL["ecut"], np.zeros(16 ** 3), 4, 8, seed=2)
+        assert s.wait(t, 200) == pdep.JOB_QUEUED
+        s.remove_system(sid)
+        assert s.wait(t, 10000) == pdep.JOB_DONE
