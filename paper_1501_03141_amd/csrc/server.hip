@@ -327,11 +327,17 @@ void close_system(pdep_server* S, std::unique_ptr<SysRec> y) {
     y->cv.notify_all();
     S->done_cv.notify_all();
     if (y->batcher.joinable()) y->batcher.join();
+    int dev_prev = -1;   // the caller's current device, restored after the frees
+    if (y->stream && hipGetDevice(&dev_prev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_prev = -1;
+    }
     if (y->stream) (void)hipSetDevice(S->device);
     if (y->ctx) pdep_destroy(y->ctx);
     if (y->stream) (void)hipStreamSynchronize(y->stream);
     if (y->blas) rocblas_destroy_handle(y->blas);
     if (y->stream) (void)hipStreamDestroy(y->stream);
+    if (dev_prev >= 0 && dev_prev != S->device) (void)hipSetDevice(dev_prev);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->committed -= y->est;
@@ -532,14 +538,31 @@ int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* 
         S->committed += y->est;   // reserved while the system is set up and resident
         S->peak_committed = std::max(S->peak_committed, S->committed);
     }
+    // the system lives on the server's device; the caller's current device is restored
+    int dev_prev = -1;
+    if (!fake && hipGetDevice(&dev_prev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_prev = -1;
+    }
+    auto restore_device = [&] {
+        if (dev_prev >= 0 && dev_prev != S->device) (void)hipSetDevice(dev_prev);
+    };
     auto release = [&](int code, const std::string& m) {
         if (y->blas) rocblas_destroy_handle(y->blas);
         if (y->stream) (void)hipStreamDestroy(y->stream);
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->committed -= y->est;
+        restore_device();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->committed -= y->est;
+        }
+        S->cv.notify_all();   // a queued job may fit in the memory reserved here
         return fail(code, m);
     };
     if (!fake) {
+        if (hipSetDevice(S->device) != hipSuccess) {
+            (void)hipGetLastError();
+            return release(PDEP_EDEVICE, "could not select the server's device");
+        }
         if (hipStreamCreateWithFlags(&y->stream, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             y->stream = nullptr;
@@ -562,6 +585,7 @@ int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* 
         pdep_get_info(y->ctx, &info);
         y->npw = info.n_pw;
         y->gap = info.gap;
+        restore_device();
     }
     SysRec* yp = y.get();
     {
