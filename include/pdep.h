@@ -486,6 +486,10 @@ int pdep_server_destroy(pdep_server* s);
  * max_batch_pert) is committed against the server budget while it is resident. */
 int pdep_server_add_system(pdep_server* s, const pdep_cell* cell, const double* vloc, const pdep_opts* opts,
                            int max_batch_pert, uint64_t* system_id);
+/* Sizes and ground-state figures of a resident system (as pdep_get_info of its context;
+ * n_pw fixes the row length N_pw - 1 of its requests; in the fake mode only the sizes and
+ * the volume are set).  PDEP_ENOTFOUND for an unknown id. */
+int pdep_server_system_info(pdep_server* s, uint64_t system_id, pdep_info* info);
 /* Fail the system's queued requests (PDEP_EINVAL), wait for its running batch, free it.
  * PDEP_ENOTFOUND for an unknown id. */
 int pdep_server_remove_system(pdep_server* s, uint64_t system_id);

@@ -19,6 +19,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <new>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -79,6 +80,7 @@ struct SysRec {
     int npw = 0;              // N_pw of the system (rows of N_pw - 1 complex on S')
     size_t est = 0;           // committed against the server budget while resident
     double gap = 0.0;         // HOMO-LUMO gap of its ground state
+    pdep_info info{};         // sizes and ground-state figures, fixed once it is set up
     bool stop = false;
     std::deque<Chi0Req*> queue;
     std::condition_variable cv;   // waits on the server mutex
@@ -271,21 +273,27 @@ void batcher_main(pdep_server* S, SysRec* y) {
             S->done_cv.notify_all();
             continue;
         }
-        phi.resize((size_t)np * row);
-        out.assign((size_t)np * row, 0.0);
-        size_t off = 0;
-        for (Chi0Req* r : batch) {
-            std::copy(r->phi.begin(), r->phi.end(), phi.begin() + off);
-            off += r->phi.size();
-        }
         int rc = PDEP_OK;
         std::string msg;
         pdep_apply_stats st{};
-        if (fake) {
+        size_t off = 0;
+        try {
+            phi.resize((size_t)np * row);
+            out.assign((size_t)np * row, 0.0);
+        } catch (const std::bad_alloc&) {
+            rc = PDEP_ENOMEM;
+            msg = "no host memory for the batch";
+        }
+        if (rc == PDEP_OK)
+            for (Chi0Req* r : batch) {
+                std::copy(r->phi.begin(), r->phi.end(), phi.begin() + off);
+                off += r->phi.size();
+            }
+        if (rc == PDEP_OK && fake) {
             const double ms = S->opts.fake_ms_per_gb + np;
             std::this_thread::sleep_for(std::chrono::microseconds((long long)(ms * 1000.0)));
             for (size_t i = 0; i < phi.size(); ++i) out[i] = -0.5 * phi[i];
-        } else {
+        } else if (rc == PDEP_OK) {
             rc = chi0_apply(y->ctx, np, phi.data(), out.data(), &st);
             if (rc != PDEP_OK) msg = pdep_last_error();
         }
@@ -297,11 +305,17 @@ void batcher_main(pdep_server* S, SysRec* y) {
                 r->t_end = now;
                 r->status = rc;
                 r->st = st;
-                r->state = rc == PDEP_OK ? PDEP_JOB_DONE : PDEP_JOB_FAILED;
-                if (rc == PDEP_OK)
-                    r->out.assign(out.begin() + off, out.begin() + off + (size_t)r->n_pert * row);
-                else
+                if (rc == PDEP_OK) {
+                    try {
+                        r->out.assign(out.begin() + off, out.begin() + off + (size_t)r->n_pert * row);
+                    } catch (const std::bad_alloc&) {
+                        r->status = PDEP_ENOMEM;
+                        r->msg = "no host memory for the request's result";
+                    }
+                } else {
                     r->msg = msg;
+                }
+                r->state = r->status == PDEP_OK ? PDEP_JOB_DONE : PDEP_JOB_FAILED;
                 off += (size_t)r->n_pert * row;
                 std::vector<double>().swap(r->phi);
             }
@@ -581,11 +595,15 @@ int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* 
         o.flags = 0;   // host arrays: requests hold host copies
         const int rc = pdep::setup_context(cell, vloc, &o, nullptr, nullptr, y->blas, &y->ctx);
         if (rc != PDEP_OK) return release(rc, pdep_last_error());
-        pdep_info info{};
-        pdep_get_info(y->ctx, &info);
-        y->npw = info.n_pw;
-        y->gap = info.gap;
+        pdep_get_info(y->ctx, &y->info);
+        y->npw = y->info.n_pw;
+        y->gap = y->info.gap;
         restore_device();
+    } else {
+        y->info.n_pw = y->npw;
+        y->info.n_v = opts->n_v;
+        y->info.n_grid = cell->n[0] * cell->n[1] * cell->n[2];
+        y->info.volume = cell->L[0] * cell->L[1] * cell->L[2];
     }
     SysRec* yp = y.get();
     {
@@ -595,6 +613,15 @@ int pdep_server_add_system(pdep_server* S, const pdep_cell* cell, const double* 
         S->systems[y->id] = std::move(y);
         yp->batcher = std::thread(batcher_main, S, yp);
     }
+    return PDEP_OK;
+}
+
+int pdep_server_system_info(pdep_server* S, uint64_t system_id, pdep_info* info) {
+    if (!S || !info) return fail(PDEP_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->systems.find(system_id);
+    if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "unknown system");
+    *info = it->second->info;
     return PDEP_OK;
 }
 
@@ -622,11 +649,15 @@ int pdep_submit_chi0(pdep_server* S, uint64_t system_id, int n_pert, const doubl
         if (it == S->systems.end()) return fail(PDEP_ENOTFOUND, "unknown system");
         npw = it->second->npw;
     }
-    auto r = std::make_unique<Chi0Req>();
+    std::unique_ptr<Chi0Req> r;
+    try {
+        r = std::make_unique<Chi0Req>();
+        r->phi.assign(phi, phi + (size_t)n_pert * 2 * (size_t)(npw - 1));
+    } catch (const std::bad_alloc&) {
+        return fail(PDEP_ENOMEM, "no host memory for the request's copy of phi");
+    }
     r->sys = system_id;
     r->n_pert = n_pert;
-    const size_t n = (size_t)n_pert * 2 * (size_t)(npw - 1);
-    r->phi.assign(phi, phi + n);
     for (double v : r->phi)
         if (!std::isfinite(v)) return fail(PDEP_EINVAL, "phi contains NaN or Inf");
     std::lock_guard<std::mutex> lk(S->mu);

@@ -232,12 +232,14 @@ def load(path: str = LIB_PATH):
     lib.pdep_server_add_system.argtypes = [P, C.POINTER(Cell), C.c_void_p, C.POINTER(Opts), C.c_int,
                                            C.POINTER(C.c_uint64)]
     lib.pdep_server_remove_system.argtypes = [P, C.c_uint64]
+    lib.pdep_server_system_info.argtypes = [P, C.c_uint64, C.POINTER(Info)]
     lib.pdep_submit_chi0.argtypes = [P, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_uint64)]
     lib.pdep_poll_chi0.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(Chi0Result), C.c_void_p, C.c_int]
     lib.pdep_submit_eigs.argtypes = [P, C.c_uint64, C.c_int, C.c_uint64, C.POINTER(EigOpts), C.POINTER(C.c_uint64)]
     lib.pdep_poll_eigs.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(JobResult), D, C.c_int]
     for name in ("pdep_server_create", "pdep_submit", "pdep_poll", "pdep_server_wait", "pdep_server_stats_get",
-                 "pdep_server_destroy", "pdep_server_add_system", "pdep_server_remove_system", "pdep_submit_chi0",
+                 "pdep_server_destroy", "pdep_server_add_system", "pdep_server_remove_system",
+                 "pdep_server_system_info", "pdep_submit_chi0",
                  "pdep_poll_chi0", "pdep_submit_eigs", "pdep_poll_eigs"):
         getattr(lib, name).restype = C.c_int
     for name in ("pdep_setup", "pdep_get_info", "pdep_get_gvectors", "pdep_get_orbitals", "chi0_apply",
@@ -594,6 +596,8 @@ class Server:
         for k, v in opt.items():
             setattr(o, k, v)
         v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
+        if v.size != int(np.prod([int(x) for x in n])):
+            raise ValueError(f"vloc has {v.size} values for a {tuple(n)} grid")
         job = Job(Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut)),
                   v.ctypes.data, o, int(n_pdep), C.c_uint64(int(seed)),
                   EigOpts(float(eig_tol), int(eig_maxit), int(max_subspace), int(n_buffer), 0, 0.0, 0))
@@ -633,6 +637,8 @@ class Server:
         for k, v in opt.items():
             setattr(o, k, v)
         v = np.ascontiguousarray(np.asarray(vloc, dtype=np.float64).ravel())
+        if v.size != int(np.prod([int(x) for x in n])):
+            raise ValueError(f"vloc has {v.size} values for a {tuple(n)} grid")
         cell = Cell((C.c_double * 3)(*[float(x) for x in L]), (C.c_int * 3)(*[int(x) for x in n]), float(ecut))
         sid = C.c_uint64()
         _check(self._lib.pdep_server_add_system(self._h, C.byref(cell), v.ctypes.data, C.byref(o),
@@ -642,10 +648,18 @@ class Server:
     def remove_system(self, system_id):
         _check(self._lib.pdep_server_remove_system(self._h, C.c_uint64(system_id)))
 
+    def system_info(self, system_id):
+        """Sizes and ground-state figures of a resident system (pdep_server_system_info)."""
+        i = Info()
+        _check(self._lib.pdep_server_system_info(self._h, C.c_uint64(system_id), C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
     def submit_chi0(self, system_id, phi):
         """Queue chi0bar applied to phi [n_pert, N_pw - 1] (complex) on a resident system."""
         a = np.ascontiguousarray(np.asarray(phi, dtype=np.complex128))
-        assert a.ndim == 2
+        npw = self.system_info(system_id)["n_pw"]
+        if a.ndim != 2 or a.shape[1] != npw - 1:
+            raise ValueError(f"phi must be [n_pert, {npw - 1}], got {a.shape}")
         t = C.c_uint64()
         _check(self._lib.pdep_submit_chi0(self._h, C.c_uint64(system_id), int(a.shape[0]), a.ctypes.data, C.byref(t)))
         self._keep[t.value] = (int(a.shape[0]), int(a.shape[1]))

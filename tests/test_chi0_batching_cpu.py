@@ -200,3 +200,19 @@ def test_a_job_waiting_for_memory_starts_when_a_system_is_removed():
         assert s.wait(t, 200) == pdep.JOB_QUEUED
         s.remove_system(sid)
         assert s.wait(t, 10000) == pdep.JOB_DONE
+
+
+def test_system_info_and_shape_checks():
+    with pdep.Server(max_running=1, fake=True, fake_ms_per_gb=0.0) as s:
+        sid = _system(s)
+        info = s.system_info(sid)
+        assert info["n_pw"] == NPW and info["n_v"] == 4 and info["n_grid"] == 16 ** 3
+        assert abs(info["volume"] - 1000.0) < 1e-12
+        # rows of the wrong length or a potential of the wrong size never reach the library
+        with pytest.raises(ValueError):
+            s.submit_chi0(sid, _phi(1, 0)[:, :-1])
+        with pytest.raises(ValueError):
+            s.add_system(CELL["L"], CELL["n"], CELL["ecut"], np.zeros(16 ** 3 - 1), 4)
+        with pytest.raises(pdep.PdepError) as e:
+            s.system_info(sid + 100)
+        assert e.value.code == pdep.PDEP_ENOTFOUND
