@@ -656,11 +656,9 @@ __global__ __launch_bounds__(2 * kPairStickGroup) void k_sphere_to_sticks_pair_r
         });
         sfor<0, LQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            const int e = e0 + tid + q * NT;
-            if (e < ne) {
-                la[e] = ra[q];
-                lb[e] = rb[q];
-            }
+            const int e = min(e0 + tid + q * NT, ne - 1);   // unguarded: see stage_rows_in
+            la[e] = ra[q];
+            lb[e] = rb[q];
         });
     }
     __syncthreads();
@@ -1028,10 +1026,12 @@ __device__ __forceinline__ void stage_rows_in(E* lds, const E* g, int nzh, int s
             constexpr int k = decltype(kc)::value;
             r[k] = src[min(b + (int)threadIdx.x + k * NT, n - 1)];
         });
+        // every lane writes (the lanes past the end write the last piece again, with its
+        // own value): a guarded store would let the compiler sink each load into its
+        // guard and wait for it there, one load at a time
         sfor<0, K>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const int i = b + (int)threadIdx.x + k * NT;
-            if (i < n) dst[i] = r[k];
+            dst[min(b + (int)threadIdx.x + k * NT, n - 1)] = r[k];
         });
     }
 }
