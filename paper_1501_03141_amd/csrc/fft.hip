@@ -644,7 +644,10 @@ __global__ __launch_bounds__(2 * kPairStickGroup) void k_sphere_to_sticks_pair_r
     const PairRows rw = pair_rows(pr, group, nrows);
     const bool has_b = rw.has_b;
     const float2* a = in + (long)rw.a * ld_in + kb;
-    const float2* b = a + ld_in;
+    // an absent second row reads the first again (finite values) and is scaled to zero:
+    // a select or a branch around its load would wait for each load inside the branch
+    const float2* b = has_b ? a + ld_in : a;
+    const float bscale = has_b ? 1.f : 0.f;
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < ne; e0 += LQ * NT) {
         float2 ra[LQ], rb[LQ];
@@ -652,7 +655,8 @@ __global__ __launch_bounds__(2 * kPairStickGroup) void k_sphere_to_sticks_pair_r
             constexpr int q = decltype(qc)::value;
             const int e = min(e0 + tid + q * NT, ne - 1);
             ra[q] = a[e];
-            rb[q] = has_b ? b[e] : make_float2(0.f, 0.f);
+            const float2 vb = b[e];
+            rb[q] = make_float2(bscale * vb.x, bscale * vb.y);
         });
         sfor<0, LQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;

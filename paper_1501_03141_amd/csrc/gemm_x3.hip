@@ -513,7 +513,25 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             }
     } else {
 #pragma unroll
-        for (int a = 0; a < AR; ++a)
+        for (int a = 0; a < AR; ++a) {
+            // the row group's old values are loaded together (clamped indices) and held
+            // before the guarded stores: loaded inside the guard, each would be waited for
+            // on its own
+            float2 old[4][4];
+            if (beta != 0.f) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int n = min(n0 + 16 * AR * wave + 16 * a + 4 * lq + i, N - 1);
+                        const int k = min(k0 + 16 * t + lr, K - 1);
+                        old[t][i] = Y[(long)n * ldy + k];
+                    }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) asm volatile("" ::"v"(old[t][i].x), "v"(old[t][i].y));
+            }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -521,16 +539,15 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
                     const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i;
                     const int k = k0 + 16 * t + lr;
                     if (n < N && k < K) {
-                        float2* y = Y + (long)n * ldy + k;
                         float2 o = make_float2(alpha * acc[a][2 * t][i], alpha * acc[a][2 * t + 1][i]);
                         if (beta != 0.f) {
-                            const float2 old = *y;
-                            o.x += beta * old.x;
-                            o.y += beta * old.y;
+                            o.x += beta * old[t][i].x;
+                            o.y += beta * old[t][i].y;
                         }
-                        *y = o;
+                        Y[(long)n * ldy + k] = o;
                     }
                 }
+        }
     }
 }
 
