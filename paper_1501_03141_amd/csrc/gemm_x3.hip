@@ -383,7 +383,7 @@ struct DirUpdate {
     float kfloor;
 };
 template <bool FUSED, int AR = 2>
-__global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, const float2* __restrict__ A,
+__global__ __launch_bounds__(256, 4) void k_gemm_update_x3r(int M, int N, int K, const float2* __restrict__ A,
                                                          long lda, const float* __restrict__ S, long lds,
                                                          float alpha, float beta, float2* __restrict__ Y, long ldy,
                                                          DirUpdate du) {
@@ -464,6 +464,20 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
             const int k = k0 + 16 * t + lr;
             kk[t] = du.kin[k < K ? k : K - 1];
         }
+        // the active flags and x rows of all the lane's rows, loaded together up front, so
+        // that a row's loads below depend on registers only (loaded per row, each row waited
+        // for its flag and then for its x row before its data loads)
+        bool lv[AR][4];
+        int xr[AR][4];
+#pragma unroll
+        for (int a = 0; a < AR; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i;
+                const int nn = n < N ? n : 0;
+                lv[a][i] = (n < N) & (du.active[nn] != 0);
+                xr[a][i] = du.xrow ? du.xrow[nn] : nn;
+            }
 #pragma unroll
         for (int a = 0; a < AR; ++a)
 #pragma unroll
@@ -475,12 +489,12 @@ __global__ __launch_bounds__(256) void k_gemm_update_x3r(int M, int N, int K, co
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int n = n0 + 16 * AR * wave + 16 * a + 4 * lq + i0 + e;
-                    live[e] = n < N && du.active[n];
-                    const int nn = live[e] ? n : 0;
+                    live[e] = lv[a][i0 + e];
+                    const int nn = n < N ? n : 0;
                     bn[e] = du.beta[nn];
                     an[e] = du.xalpha[nn];
                     sh[e] = (float)du.shift[nn];
-                    xo[e] = (long)(du.xrow ? du.xrow[nn] : nn) * ldy;
+                    xo[e] = (long)xr[a][i0 + e] * ldy;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         int k = k0 + 16 * t + lr;
