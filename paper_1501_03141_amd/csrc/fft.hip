@@ -1436,7 +1436,6 @@ __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTab
     const bool xact = zl < nzh;
     const bool col = zc < nzh;
     const long ng = (long)NL * NL * nz;
-    const int ns = d.ns;
     double2* tw = lds + quad64_data_elems(d, NL);
     if (tid < NL) {
         const double ang = 6.283185307179586476925 * tid / NL;
@@ -1457,8 +1456,7 @@ __global__ __launch_bounds__(256) void k_slab_density_quad64(FftDims d, BasisTab
             if (q >= np) break;   // uniform over the workgroup
             const double2* g = sticks + (((long)(p0 + q) * nv + v) * nz + z0) * sld;
             __syncthreads();   // the previous row's transpose planes are read
-            for (int zz = 0; zz < nzh; ++zz)
-                for (int e = tid; e < ns; e += 256) lds[zz * sld + e] = g[(long)zz * sld + e];
+            stage_rows_in<double2, 256, 4>(lds, g, nzh, sld);
             __syncthreads();
             double2 w[Q];
             if (col) {
