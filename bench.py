@@ -37,17 +37,22 @@ VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 VALU_KERNELS = {"slab_hv": "f32", "slab_hv_fp64": "f64"}
 # Measured HBM traffic of a kernel class, KiB per dispatch averaged over one bench step of
 # the medium workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, scaled by the factors
-# that make a plain 1 GiB copy (torch.mul) read and write 1 GiB (2.0 and 1.0).  Reported
-# only while the kernel source file is the one that was measured.
+# that make a plain 1 GiB copy (torch.mul) read and write 1 GiB (2.0 and 1.0), with the
+# algorithmic bytes of the profiled launches (chain block fixed at 1017 rows).  A run whose
+# tuned chain block differs reports the same measured-to-algorithmic ratio: the traffic is
+# scaled to its own launches.  Reported only while the kernel source file is the one that
+# was measured.
 MEASURED_TRAFFIC = {
-    "slab_hv": {"fetch_kib": 64865.4, "write_kib": 125406.4, "fetch_scale": 2.0, "write_scale": 1.0,
-                "source": "paper_1501_03141_amd/csrc/fft.hip", "sha1": "3174f3935e8f3033b40d91158aa315f5e032fcae",
+    "slab_hv": {"fetch_kib": 64833.2, "write_kib": 125398.2, "fetch_scale": 2.0, "write_scale": 1.0,
+                "algorithmic_bytes": 256258836,
+                "source": "paper_1501_03141_amd/csrc/fft.hip", "sha1": "b9565f66b6cb4d55d1a9a33c927465d5649cd355",
                 "workload": "medium"},
 }
 
 
-def measured_traffic(name: str, workload: str):
-    """HBM bytes per launch from the committed counter runs, or None."""
+def measured_traffic(name: str, workload: str, algorithmic_bytes: float):
+    """HBM bytes per launch from the committed counter runs, scaled to launches of the
+    given algorithmic bytes, or None."""
     import hashlib
     m = MEASURED_TRAFFIC.get(name)
     if m is None or m["workload"] != workload:
@@ -58,7 +63,8 @@ def measured_traffic(name: str, workload: str):
                 return None
     except OSError:
         return None
-    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+    measured = 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+    return measured * algorithmic_bytes / m["algorithmic_bytes"]
 
 
 def ritz_eps(phi: np.ndarray, chi_phi: np.ndarray) -> np.ndarray:
@@ -420,7 +426,7 @@ def main():
     log(f"timed ({main_mode})", stats[-1], f"{ms_step:.1f} ms/step")
     kname, roof = dominant_roofline({dominant: prof_dom[dominant]}, "bf16" if main_mode == "bf16x3" else "f32")
     pdep.profile_classes(None)
-    roof["traffic"] = measured_traffic(kname, w0.name)
+    roof["traffic"] = measured_traffic(kname, w0.name, roof["algorithmic_bytes_per_launch"])
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes/launch"
         roof["traffic_over_algorithmic"] = round(roof["traffic"] / max(roof["algorithmic_bytes_per_launch"], 1), 3)

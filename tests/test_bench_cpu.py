@@ -25,19 +25,22 @@ def test_traffic_table_is_tied_to_its_source(tmp_path, monkeypatch):
     src = os.path.join(ROOT, m["source"])
     with open(src, "rb") as f:
         current = hashlib.sha1(f.read()).hexdigest()
-    got = bench.measured_traffic("slab_hv", "medium")
+    alg = m["algorithmic_bytes"]
+    got = bench.measured_traffic("slab_hv", "medium", alg)
     if current == m["sha1"]:
         want = 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
         assert got == pytest.approx(want)
+        # launches of another chain block keep the measured-to-algorithmic ratio
+        assert bench.measured_traffic("slab_hv", "medium", 1.5 * alg) == pytest.approx(1.5 * want)
     else:
         assert got is None          # a changed kernel source reports no measured traffic
     # another workload, or a source that differs from the measured one, reports none
-    assert bench.measured_traffic("slab_hv", "small") is None
+    assert bench.measured_traffic("slab_hv", "small", alg) is None
     fake = tmp_path / "fft.hip"
     fake.write_bytes(b"// not the measured source\n")
     monkeypatch.setitem(bench.MEASURED_TRAFFIC, "slab_hv", dict(m, source=str(fake)))
     monkeypatch.setattr(bench, "ROOT", "/")
-    assert bench.measured_traffic("slab_hv", "medium") is None
+    assert bench.measured_traffic("slab_hv", "medium", alg) is None
 
 
 def test_roofline_bound_is_the_larger_floor():
